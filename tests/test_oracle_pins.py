@@ -1,0 +1,316 @@
+"""Pins of the FP64 oracle against results fixed by the mathematics.
+
+* BP is exact on tree-structured factor graphs: after convergence the oracle's
+  normalised beliefs equal brute-force T-marginals / max-marginals, and its MAP
+  equals the brute-force MAP (textbook BP, cited as [Pearl 1988; Kschischang
+  2001] in the paper's introduction).
+* One factor update equals the LSE_T over the factor's valid joint states
+  computed by enumeration (enumeration factors: Sec. "Specifying complex
+  factor graphs"; OR/AND closed forms: Sec. "Package features", logical
+  factors).
+* Damping m <- d m + (1-d) u [Pretti 2005] is checked on one step against
+  brute-force u, at d != 0.5 so the convention is pinned.
+* Messages are a gauge: shifting a message row by a constant changes nothing
+  after one step; every row's maximum is 0.
+* A converged damped run is a fixed point of the undamped map.
+* The adjoint matches central finite differences of the forward run and, on a
+  converged tree, the closed form dq[v,s]/dphi_f(c) = P(x_f=c | x_v=s) - P(x_f=c).
+"""
+import numpy as np
+import pytest
+
+import brute
+from oracle import OracleGraph
+from paper_2202_04110_amd import workloads as W
+
+TEMPS = [0.0, 0.05, 0.7, 1.0]
+
+
+def _tree(seed, **kw):
+    return W.random_factor_graph(seed, num_vars=kw.pop("num_vars", 7), tree=True, **kw)
+
+
+@pytest.mark.parametrize("T", TEMPS)
+@pytest.mark.parametrize("seed", range(6))
+def test_tree_exact_marginals(seed, T):
+    g = _tree(seed, max_states=4, max_arity=3, logical_frac=0.25, explicit_frac=0.4)
+    og = OracleGraph(g)
+    m, res = og.run(400, 0.5, T, residuals=True)
+    assert res[-1] < 1e-10
+    _, q, mp = og.beliefs(m, T)
+    qx = brute.exact_q(g, T)
+    np.testing.assert_allclose(q, qx, atol=1e-9, rtol=0)
+    if T == 0.0:
+        x, _ = brute.exact_map(g)
+        np.testing.assert_array_equal(mp, x)
+
+
+@pytest.mark.parametrize("T", [0.0, 1.0])
+def test_chain_exact(T):
+    g = W.chain(11, length=8, n=4)
+    og = OracleGraph(g)
+    m = og.run(300, 0.5, T)
+    _, q, _ = og.beliefs(m, T)
+    np.testing.assert_allclose(q, brute.exact_q(g, T), atol=1e-10, rtol=0)
+
+
+def _one_step_expected(g, og, T, d, m0):
+    """m1 = normalise(d m0 + (1-d) u) with u from enumeration."""
+    esoff = g.edge_state_off()
+    vsoff = g.var_state_off()
+    B = g.evidence.astype(np.float64).copy()
+    for e in range(g.num_edges):
+        v = g.edge_var[e]
+        B[vsoff[v]:vsoff[v + 1]] += m0[esoff[e]:esoff[e + 1]]
+    n = np.array([B[vsoff[g.edge_var[e]] + s] - m0[esoff[e] + s]
+                  for e in range(g.num_edges) for s in range(g.var_num_states[g.edge_var[e]])])
+    out = np.zeros_like(m0)
+    for f in range(g.num_factors):
+        e0, e1 = g.factor_edge_off[f], g.factor_edge_off[f + 1]
+        rows = [n[esoff[e]:esoff[e + 1]] for e in range(e0, e1)]
+        u = brute.factor_update(g, f, rows, T)
+        for j, e in enumerate(range(e0, e1)):
+            mp = d * m0[esoff[e]:esoff[e + 1]] + (1 - d) * u[j]
+            out[esoff[e]:esoff[e + 1]] = mp - mp.max()
+    return out
+
+
+@pytest.mark.parametrize("T", [0.0, 0.05, 0.3, 1.0])
+@pytest.mark.parametrize("kind", [W.OR, W.AND])
+@pytest.mark.parametrize("parents", [1, 2, 3, 5, 8, 12])
+def test_logical_closed_form_vs_enumeration(kind, parents, T):
+    for seed in range(3):
+        g = W.single_logical(100 * parents + seed, kind, parents)
+        og = OracleGraph(g)
+        m1 = og.run(1, 0.0, T)
+        exp = _one_step_expected(g, og, T, 0.0, np.zeros(og.ES))
+        np.testing.assert_allclose(m1, exp, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("T", [0.0, 0.3, 1.0])
+def test_logical_extreme_inputs(T):
+    """Large |delta| (clamped-pixel scale) keeps the closed form exact."""
+    rng = np.random.default_rng(7)
+    for kind in (W.OR, W.AND):
+        g = W.single_logical(5, kind, 6)
+        g.evidence[:] = rng.choice([-12.0, -3.0, 0.0, 2.5, 11.0], size=g.evidence.shape)
+        og = OracleGraph(g)
+        m1 = og.run(1, 0.0, T)
+        exp = _one_step_expected(g, og, T, 0.0, np.zeros(og.ES))
+        np.testing.assert_allclose(m1, exp, atol=1e-10, rtol=0)
+
+
+@pytest.mark.parametrize("T", [0.0, 0.05, 1.0])
+def test_logical_all_parents_off(T):
+    """Every parent favours state 0 (OR) / state 1 (AND): the branch where the
+    best non-trivial parent configuration switches on a single parent."""
+    rng = np.random.default_rng(11)
+    for kind in (W.OR, W.AND):
+        for p in (1, 2, 4, 9):
+            g = W.single_logical(3, kind, p)
+            ev = g.evidence.reshape(-1, 2)
+            x = rng.uniform(0.2, 3.0, size=p)
+            ev[:p, 0] = 0.0
+            ev[:p, 1] = -x if kind == W.OR else x
+            og = OracleGraph(g)
+            m1 = og.run(1, 0.0, T)
+            exp = _one_step_expected(g, og, T, 0.0, np.zeros(og.ES))
+            np.testing.assert_allclose(m1, exp, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("T", [0.0, 0.5, 1.0])
+@pytest.mark.parametrize("d", [0.0, 0.3, 0.8])
+def test_damped_step_vs_enumeration(T, d):
+    """One damped step from random messages on a loopy mixed graph."""
+    g = W.random_factor_graph(21, num_vars=8, tree=False, extra_factors=4, max_arity=3,
+                              logical_frac=0.3, explicit_frac=0.4)
+    og = OracleGraph(g)
+    rng = np.random.default_rng(3)
+    m0 = rng.normal(0, 1, og.ES)
+    m1 = og.run(1, d, T, m0=m0)
+    np.testing.assert_allclose(m1, _one_step_expected(g, og, T, d, m0), atol=1e-11, rtol=0)
+
+
+@pytest.mark.parametrize("shape", [(2, 3), (3, 3, 2), (4, 2, 2, 3)])
+@pytest.mark.parametrize("explicit", [False, True])
+def test_enum_factor_vs_enumeration(shape, explicit):
+    for T in (0.0, 0.2, 1.0):
+        g = W.single_enum(len(shape) * 10 + explicit, shape, explicit=explicit)
+        og = OracleGraph(g)
+        m1 = og.run(1, 0.0, T)
+        np.testing.assert_allclose(m1, _one_step_expected(g, og, T, 0.0, np.zeros(og.ES)),
+                                   atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("T", [0.0, 1.0])
+def test_gauge_invariance(T):
+    g = W.random_factor_graph(5, num_vars=9, tree=False, extra_factors=5, logical_frac=0.3)
+    og = OracleGraph(g)
+    rng = np.random.default_rng(0)
+    m0 = rng.normal(0, 1, og.ES)
+    shift = np.repeat(rng.normal(0, 3, g.num_edges), g.var_num_states[g.edge_var])
+    a = og.run(3, 0.5, T, m0=m0)
+    b = og.run(3, 0.5, T, m0=m0 + shift)
+    np.testing.assert_allclose(a, b, atol=1e-11, rtol=0)
+    # every message row has max 0 after a step
+    esoff = g.edge_state_off()
+    mx = np.array([a[esoff[e]:esoff[e + 1]].max() for e in range(g.num_edges)])
+    assert np.all(mx == 0.0)
+
+
+def test_fixed_point_of_undamped_map():
+    g = W.potts_grid(6, 3, seed=9, diag=0.5, off_sd=0.2)
+    og = OracleGraph(g)
+    m, res = og.run(600, 0.5, 1.0, residuals=True)
+    assert res[-1] < 1e-12
+    u = og.update(m, 1.0)
+    esoff = g.edge_state_off()
+    for e in range(g.num_edges):
+        row = u[esoff[e]:esoff[e + 1]]
+        np.testing.assert_allclose(row - row.max(), m[esoff[e]:esoff[e + 1]], atol=1e-11)
+
+
+def test_zero_iterations_gives_normalised_evidence():
+    g = W.random_factor_graph(2, num_vars=6)
+    og = OracleGraph(g)
+    _, q, _ = og.beliefs(og.zero_messages(), 1.0)
+    vs = g.var_state_off()
+    ev = g.evidence.astype(np.float64)
+    for v in range(g.num_vars):
+        r = ev[vs[v]:vs[v + 1]]
+        np.testing.assert_allclose(q[vs[v]:vs[v + 1]], r - np.log(np.exp(r).sum()), atol=1e-14)
+
+
+def test_score_matches_enumeration():
+    g = W.random_factor_graph(4, num_vars=7, tree=False, extra_factors=3, logical_frac=0.3)
+    og = OracleGraph(g)
+    X, sc = brute.joint_scores(g)
+    for i in range(0, X.shape[0], max(1, X.shape[0] // 50)):
+        assert og.score(X[i]) == pytest.approx(sc[i], abs=1e-12) or (
+            np.isinf(sc[i]) and np.isinf(og.score(X[i])))
+
+
+# ----------------------------------------------------------------- adjoint
+def _fd_grad(g, iters, d, T, gq, which, idx, h):
+    """Central differences of sum(gq * q) through the oracle's forward run.
+    Values sit on a 2^-10 grid and h = 2^-10, so x +- h is exact in FP32."""
+    out = []
+    for i in idx:
+        vals = []
+        for sgn in (1, -1):
+            g2 = g.copy()
+            arr = g2.log_potentials if which == "phi" else g2.evidence
+            arr[i] = np.float32(arr[i] + sgn * h)
+            og = OracleGraph(g2)
+            m = og.run(iters, d, T)
+            _, q, _ = og.beliefs(m, T)
+            vals.append(float(np.dot(gq, q)))
+        out.append((vals[0] - vals[1]) / (2 * h))
+    return np.asarray(out)
+
+
+def _exact_grid(g):
+    """Round the graph's values to multiples of 2^-10 so x +- 2^-10 steps are
+    exact in FP32."""
+    g = g.copy()
+    g.evidence = (np.round(g.evidence * 1024) / 1024).astype(np.float32)
+    g.log_potentials = (np.round(g.log_potentials * 1024) / 1024).astype(np.float32)
+    return g
+
+
+@pytest.mark.parametrize("loopy", [False, True])
+@pytest.mark.parametrize("T", [0.5, 1.0])
+def test_adjoint_vs_finite_differences(loopy, T):
+    g = W.random_factor_graph(31 + loopy, num_vars=6, tree=not loopy,
+                              extra_factors=3 if loopy else 0, max_arity=3, explicit_frac=0.4,
+                              lp_sd=0.7)
+    g = _exact_grid(g)
+    og = OracleGraph(g)
+    rng = np.random.default_rng(1)
+    gq = rng.normal(0, 1, og.VS)
+    iters, d = 12, 0.5
+    gphi, gth, gm0 = og.backward(iters, d, T, gq)
+    h = 2.0 ** -10
+    pi = rng.choice(og.Tn, size=min(10, og.Tn), replace=False)
+    ti = rng.choice(og.VS, size=6, replace=False)
+    fd_phi = _fd_grad(g, iters, d, T, gq, "phi", pi, h)
+    fd_th = _fd_grad(g, iters, d, T, gq, "theta", ti, h)
+    # central differences with step h: error O(h^2 * third derivative)
+    np.testing.assert_allclose(gphi[pi], fd_phi, atol=2e-5, rtol=1e-4)
+    np.testing.assert_allclose(gth[ti], fd_th, atol=2e-5, rtol=1e-4)
+    # the loss does not change when a message row is shifted: zero row sums
+    esoff = g.edge_state_off()
+    rows = np.array([gm0[esoff[e]:esoff[e + 1]].sum() for e in range(g.num_edges)])
+    assert np.abs(rows).max() < 1e-12 * max(1.0, np.abs(gm0).max())
+
+
+@pytest.mark.parametrize("d", [0.3, 0.8])
+def test_adjoint_fd_damping(d):
+    """Finite differences at damping != 0.5 pin the damping convention of the
+    reverse sweep."""
+    T = 0.7
+    g = _exact_grid(W.random_factor_graph(52, num_vars=5, tree=False, extra_factors=2,
+                                          max_arity=3, explicit_frac=0.3, lp_sd=0.7))
+    og = OracleGraph(g)
+    rng = np.random.default_rng(4)
+    gq = rng.normal(0, 1, og.VS)
+    gphi, gth, _ = og.backward(8, d, T, gq)
+    h = 2.0 ** -10
+    pi = rng.choice(og.Tn, size=min(8, og.Tn), replace=False)
+    ti = rng.choice(og.VS, size=4, replace=False)
+    np.testing.assert_allclose(gphi[pi], _fd_grad(g, 8, d, T, gq, "phi", pi, h), atol=2e-5,
+                               rtol=1e-4)
+    np.testing.assert_allclose(gth[ti], _fd_grad(g, 8, d, T, gq, "theta", ti, h), atol=2e-5,
+                               rtol=1e-4)
+
+
+def test_adjoint_tree_closed_form():
+    """Converged tree: dq[v,s]/dphi_f(c) = P(x_f=c | x_v=s) - P(x_f=c)."""
+    T = 1.0
+    g = W.random_factor_graph(44, num_vars=6, tree=True, max_arity=3, explicit_frac=0.3)
+    og = OracleGraph(g)
+    rng = np.random.default_rng(2)
+    gq = rng.normal(0, 1, og.VS)
+    gphi, gth, _ = og.backward(300, 0.5, T, gq)
+    X, p = brute.marginal_probs(g, T)
+    vs_off = g.var_state_off()
+    exp_phi = np.zeros(og.Tn)
+    exp_th = np.zeros(og.VS)
+    for v in range(g.num_vars):
+        for s in range(g.var_num_states[v]):
+            sel = X[:, v] == s
+            pc = p * sel / p[sel].sum()
+            w = gq[vs_off[v] + s]
+            for f in range(g.num_factors):
+                vs, cfg, _ = brute._factor_configs(g, f)
+                for c in range(cfg.shape[0]):
+                    hit = np.all(X[:, vs] == cfg[c], axis=1)
+                    exp_phi[g.logpot_off[f] + c] += w * (pc[hit].sum() - p[hit].sum())
+            for u in range(g.num_vars):
+                for t in range(g.var_num_states[u]):
+                    hit = X[:, u] == t
+                    exp_th[vs_off[u] + t] += w * (pc[hit].sum() - p[hit].sum())
+    np.testing.assert_allclose(gphi, exp_phi, atol=1e-8)
+    np.testing.assert_allclose(gth, exp_th, atol=1e-8)
+
+
+def test_rbm_map_quality_statistic():
+    """The paper's small-RBM protocol (20 RBMs, 15 + 15 units, exact MAP by
+    enumeration, 200 iterations, damping 0.5).  A statistic, not a gate: the
+    paper does not state its weight distribution.  Pins: the oracle's MAP is a
+    valid assignment whose score never exceeds the exact optimum."""
+    hits = 0
+    for r in range(20):
+        g = W.random_rbm_small(1000 + r)
+        og = OracleGraph(g)
+        m = og.run(200, 0.5, 0.0)
+        _, _, x = og.beliefs(m, 0.0)
+        w = g.log_potentials.reshape(-1, 4)[:, 3].astype(np.float64).reshape(15, 15)
+        b = g.evidence.reshape(-1, 2)[:, 1].astype(np.float64)
+        xs, best = brute.rbm_exact_map(15, 15, w, b[:15], b[15:])
+        sc = og.score(x)
+        assert sc <= best + 1e-9
+        assert og.score(xs) == pytest.approx(best, abs=1e-9)
+        hits += int(abs(sc - best) < 1e-9)
+    print("exact MAP recovered on %d/20 RBMs" % hits)
+    assert hits >= 5
