@@ -1,0 +1,228 @@
+/*
+ * lbp.h -- C-ABI of liblbp.so: damped, log-domain loopy belief propagation
+ * (max-product and sum-product at a temperature) on discrete factor graphs,
+ * run by HIP kernels on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: PGMax (Zhou et al., arXiv 2202.04110).  Messages of a factor graph
+ * live in flat edge-state arrays (Sec. "A fully flat array-based LBP
+ * implementation"); every iteration recomputes all factor-to-variable
+ * messages in parallel from the previous iterate and damps them (Sec.
+ * "Package features", citing Pretti 2005); factors are enumeration factors
+ * given by their valid configurations (Sec. "Specifying complex factor
+ * graphs") or OR / AND logical factors with updates linear in their arity
+ * (Sec. "Package features"); variables may have different numbers of states.
+ * The paper prints no update equations; this library implements textbook
+ * log-domain BP at temperature T with
+ *     LSE_T(x) = max x (T = 0),  M + T log sum exp((x - M)/T) (T > 0):
+ *   B[v,s] = theta[v,s] + sum_{e in N(v)} m[e,s]
+ *   n[e,s] = B[var(e),s] - m[e,s]
+ *   u[e_j,s] = LSE_T{ phi_f(c) + sum_l n[e_l,c_l] : c_j = s } - n[e_j,s]
+ *   m[e,s] <- d m[e,s] + (1-d) u[e,s], then minus its max over s
+ *   q[v,s] = B[v,s] - LSE_T(B[v,:]),  MAP x_v = lowest argmax_s B[v,s]
+ * Messages start at 0.  T = 0 is max-product, T = 1 sum-product.
+ *
+ * Conventions for every function:
+ *  - Return value: LBP_OK (0) or a negative LBP_E_* code; lbp_last_error()
+ *    returns a message for the calling thread's last failure.  No C++
+ *    exception crosses this interface.  On failure, out-parameters are left
+ *    untouched and nothing is leaked.
+ *  - "Host" pointers are read or written synchronously; "device" pointers are
+ *    used in stream order on the context's stream.  The caller owns every
+ *    buffer it passes in.
+ *  - Work is asynchronous on the context's stream unless stated otherwise;
+ *    asynchronous GPU faults surface at the next synchronising call as
+ *    LBP_E_HIP.
+ *  - Limits: every graph's internal message, belief and potential arrays
+ *    must each hold fewer than 2^31 floats (about 8 GiB).
+ */
+#ifndef LBP_H
+#define LBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBP_OK = 0,
+    LBP_E_INVALID = -1,     /* bad argument or malformed graph */
+    LBP_E_OOM = -2,         /* device or host allocation failed */
+    LBP_E_HIP = -3,         /* a HIP runtime call failed */
+    LBP_E_STATE = -4,       /* call not valid in the object's current state */
+    LBP_E_BUDGET = -5,      /* request larger than the server's memory budget */
+    LBP_E_NONFINITE = -6,   /* beliefs contain NaN or infinity */
+    LBP_E_UNSUPPORTED = -7  /* valid graph outside this build's kernel limits */
+};
+
+enum { LBP_FACTOR_ENUM = 0, LBP_FACTOR_OR = 1, LBP_FACTOR_AND = 2 };
+
+typedef struct lbp_ctx lbp_ctx;
+typedef struct lbp_graph lbp_graph;
+typedef struct lbp_batch lbp_batch;
+
+/*
+ * Factor graph description (all host pointers).  The flat-array form of the
+ * paper's Sec. "A fully flat array-based LBP implementation": global indices
+ * of variable states and of valid factor configurations.
+ *
+ *  num_vars            V >= 0
+ *  var_num_states[V]   states of each variable, 2 <= n <= 64
+ *  evidence[VS]        unary log-potentials theta, variable-major (variable v
+ *                      owns entries vs_off[v] .. vs_off[v]+n_v-1, vs_off the
+ *                      prefix sum of var_num_states); NULL means all zero
+ *  num_factors         F >= 0
+ *  factor_kind[F]      LBP_FACTOR_ENUM / _OR / _AND
+ *  factor_edge_off[F+1] edges of factor f are factor_edge_off[f] ..
+ *                      factor_edge_off[f+1]-1; [0] = 0, non-decreasing
+ *  edge_var[E]         variable of each edge, E = factor_edge_off[F].  For
+ *                      OR / AND the last edge of the factor is the child and
+ *                      the others are its parents (at least one); all of
+ *                      their variables must be binary
+ *  factor_cfg_table[F] configuration table of an enumeration factor, -1 for
+ *                      logical factors
+ *  num_cfg_tables      NT >= 0
+ *  cfg_table_num_cfgs[NT] number of valid configurations; 0 marks a dense
+ *                      table holding every joint state of the factor's
+ *                      variables in row-major order (last variable fastest)
+ *  cfg_table_arity[NT] must equal the arity of every factor using the table
+ *  cfg_table_off[NT+1] offsets into cfg_table_states
+ *  cfg_table_states    explicit tables: num_cfgs rows of arity states each;
+ *                      every state of every slot must appear in at least one
+ *                      row (otherwise a message would be -inf)
+ *  logpot_off[F+1]     offsets into log_potentials; an enumeration factor
+ *                      holds one log-potential per configuration of its
+ *                      table, a logical factor none
+ *  log_potentials[Tn]  phi_f(c), Tn = logpot_off[F]; must be finite
+ *
+ * Messages are exchanged (lbp_get_messages / lbp_set_messages) in the flat
+ * edge-state order: edge e owns var_num_states[edge_var[e]] consecutive
+ * floats, edges in increasing order; ES is the total.
+ */
+typedef struct lbp_graph_desc {
+    int32_t num_vars;
+    const int32_t *var_num_states;
+    const float *evidence;
+    int32_t num_factors;
+    const int32_t *factor_kind;
+    const int64_t *factor_edge_off;
+    const int32_t *edge_var;
+    const int32_t *factor_cfg_table;
+    int32_t num_cfg_tables;
+    const int32_t *cfg_table_num_cfgs;
+    const int32_t *cfg_table_arity;
+    const int64_t *cfg_table_off;
+    const int32_t *cfg_table_states;
+    const int64_t *logpot_off;
+    const float *log_potentials;
+} lbp_graph_desc;
+
+/* Message of the calling thread's last failure ("" if none).  The pointer
+ * stays valid until the thread's next lbp_* call. */
+const char *lbp_last_error(void);
+
+/* Host-only check of a description; needs no GPU.  sizes_out (may be NULL)
+ * receives {V, VS, F, E, ES, Tn}.  Rejects: out-of-range indices, offsets that
+ * are not monotone or do not start at 0, n < 2 or n > 64, logical factors on
+ * non-binary variables or without a parent, a table whose arity differs from
+ * its factor's, a state outside its variable's range, an (edge, state) that
+ * no configuration covers, a log-potential count that does not match the
+ * table, non-finite evidence or log-potentials.  LBP_E_UNSUPPORTED: a valid
+ * graph beyond the kernels' limits (enumeration factors of arity > 8, more
+ * than 4096 configurations or more than 64 summed slot states; logical
+ * factors of more than 1024 edges). */
+int lbp_validate(const lbp_graph_desc *desc, int64_t sizes_out[6]);
+
+/* Host-only diagnostic: compiles the description into the library's internal
+ * layout and replays the address arithmetic of every kernel against the
+ * sizes of the arrays it touches (no GPU needed; lbp_graph_upload runs the
+ * same check).  info_out (may be NULL) receives the internal array sizes
+ * {message floats, belief floats, potential floats, factor tiles}.
+ * Returns LBP_E_INVALID with a message naming the access on failure. */
+int lbp_check_layout(const lbp_graph_desc *desc, int64_t info_out[4]);
+
+/* Context on HIP device `device`.  hip_stream is a hipStream_t the caller
+ * keeps alive (e.g. torch.cuda.current_stream().cuda_stream), or NULL for
+ * the null stream.  The context owns nothing on the device but its cached
+ * launch graphs. */
+int lbp_ctx_create(int device, void *hip_stream, lbp_ctx **out);
+/* Changes the stream used by later calls on this context. */
+int lbp_ctx_set_stream(lbp_ctx *ctx, void *hip_stream);
+/* Waits for all work queued on the context's stream. */
+int lbp_ctx_synchronize(lbp_ctx *ctx);
+/* Frees the context; every graph and batch made with it must be freed first. */
+void lbp_ctx_destroy(lbp_ctx *ctx);
+
+/* Validates and uploads a graph (Sec. "A fully flat array-based LBP
+ * implementation": index arrays computed once, messages in flat arrays).
+ * Host arrays are read before return and may be freed afterwards.  The
+ * graph owns its device memory until lbp_graph_free.  Messages start at 0.
+ * The upload is complete (stream synchronised) when the call returns. */
+int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out);
+/* Frees a graph after waiting for its queued work. */
+void lbp_graph_free(lbp_graph *g);
+/* out[8] = {V, VS, F, E, ES, Tn, device_bytes, padded_edge_states}. */
+int lbp_graph_sizes(const lbp_graph *g, int64_t out[8]);
+
+/* Replace evidence (VS floats, variable-major) or log-potentials (Tn floats,
+ * in log_potentials order) without re-uploading; on_device selects whether
+ * `values` is a device pointer (stream-ordered) or a host pointer (read
+ * before return).  Device values are not checked for finiteness; non-finite
+ * results are reported by the read-out calls. */
+int lbp_set_evidence(lbp_graph *g, const float *values, int on_device);
+int lbp_set_log_potentials(lbp_graph *g, const float *values, int on_device);
+
+/* Sets every message to 0. */
+int lbp_reset_messages(lbp_graph *g);
+
+/* Runs `iters` >= 0 parallel damped iterations from the current messages
+ * (Sec. "Package features": parallel updates with damping; the paper's
+ * experiments use 200 iterations and damping 0.5).  0 <= damping <= 1 is the
+ * weight of the previous message; temperature T >= 0 (0 = max-product).
+ * Messages persist, so a second call continues where the first stopped. */
+int lbp_run_bp(lbp_graph *g, int32_t iters, float damping, float temperature);
+
+/* Beliefs from the current messages at the temperature of the last run (0
+ * before any run), VS floats variable-major: normalised q = B - LSE_T(B) when
+ * `normalized`, else B.  MAP: lowest-index argmax of B per variable (V int32;
+ * the paper scores MAP inference by the potential of the returned
+ * configuration, Sec. "Comparison with existing alternatives").  Outputs on
+ * the host synchronise the stream; LBP_E_NONFINITE reports NaN/inf beliefs
+ * (the output is still written).  Device outputs are stream-ordered and the
+ * non-finite check is then reported by lbp_graph_status. */
+int lbp_get_beliefs(lbp_graph *g, float *out, int normalized, int out_on_device);
+int lbp_decode_map(lbp_graph *g, int32_t *out, int out_on_device);
+/* Synchronises and reports LBP_E_NONFINITE if any read-out since the last
+ * call saw a non-finite belief (and clears the flag). */
+int lbp_graph_status(lbp_graph *g);
+
+/* Message state in the flat edge-state order (ES floats), for checkpoints and
+ * for starting several runs from one state. */
+int lbp_get_messages(lbp_graph *g, float *out, int on_device);
+int lbp_set_messages(lbp_graph *g, const float *values, int on_device);
+
+/*
+ * Batches (the paper's Sec. "Exciting new possibilities": processing batches
+ * of models in parallel).  A batch references graphs uploaded to the same
+ * context and advances all of them in shared kernel launches; each graph's
+ * arithmetic is the same as when it runs alone, so results are bitwise
+ * identical.  The batch does not own its graphs, which must outlive it.
+ */
+int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
+                     lbp_batch **out);
+int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature);
+void lbp_batch_free(lbp_batch *b);
+
+/* Diagnostic timing: runs `reps` launches of one phase of an iteration on the
+ * current messages and returns the mean launch time in milliseconds measured
+ * with HIP events on the context's stream.  phase 0 = variable (belief)
+ * kernels, 1 = factor kernels, 2 = one whole iteration.  The factor phase
+ * updates the messages, like an iteration does. */
+int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, float temperature,
+                   float *ms_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBP_H */

@@ -1,0 +1,600 @@
+// Validation of a factor-graph description and its compilation into the
+// panel layout used by the kernels (see lbp_internal.h).
+//
+// The flat-array idea is the paper's (Sec. "A fully flat array-based LBP
+// implementation": messages in flat arrays, global indices of variable states
+// and valid configurations computed once); the panel layout, the shape
+// classes and the tile tables are this library's own.
+#include "compile.h"
+
+#include <climits>
+#include <cmath>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace lbp {
+namespace {
+
+int bad(std::string *err, const std::string &msg, int code = LBP_E_INVALID) {
+    *err = msg;
+    return code;
+}
+
+std::string at(const char *what, int64_t i) { return std::string(what) + "[" + std::to_string(i) + "]"; }
+
+bool monotone_from_zero(const int64_t *off, int64_t n) {
+    if (off[0] != 0) return false;
+    for (int64_t i = 0; i < n; ++i)
+        if (off[i + 1] < off[i]) return false;
+    return true;
+}
+
+// Whether an enumeration factor with these slot state counts uses the dense
+// pairwise fast path.
+bool pair_fast(bool dense, int32_t arity, const int32_t *ns) {
+    return dense && arity == 2 && ns[0] <= kPairStatesMax && ns[1] <= kPairStatesMax;
+}
+
+}  // namespace
+
+int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
+    if (!d) return bad(err, "graph description is NULL");
+    const int64_t V = d->num_vars, F = d->num_factors, NT = d->num_cfg_tables;
+    if (V < 0 || F < 0 || NT < 0) return bad(err, "negative num_vars, num_factors or num_cfg_tables");
+    if (V > 0 && !d->var_num_states) return bad(err, "var_num_states is NULL");
+    if (!d->factor_edge_off || !d->logpot_off) return bad(err, "factor_edge_off or logpot_off is NULL");
+    if (F > 0 && (!d->factor_kind || !d->factor_cfg_table))
+        return bad(err, "factor_kind or factor_cfg_table is NULL");
+    if (NT > 0 && (!d->cfg_table_num_cfgs || !d->cfg_table_arity || !d->cfg_table_off))
+        return bad(err, "configuration table arrays are NULL");
+
+    int64_t VS = 0;
+    for (int64_t v = 0; v < V; ++v) {
+        int32_t n = d->var_num_states[v];
+        if (n < 2 || n > kMaxStates)
+            return bad(err, at("var_num_states", v) + " = " + std::to_string(n) + " outside [2, 64]");
+        VS += n;
+    }
+    if (d->evidence)
+        for (int64_t i = 0; i < VS; ++i)
+            if (!std::isfinite(d->evidence[i])) return bad(err, at("evidence", i) + " is not finite");
+
+    if (!monotone_from_zero(d->factor_edge_off, F))
+        return bad(err, "factor_edge_off must start at 0 and be non-decreasing");
+    const int64_t E = d->factor_edge_off[F];
+    if (E > INT32_MAX) return bad(err, "more than 2^31-1 edges", LBP_E_UNSUPPORTED);
+    if (E > 0 && !d->edge_var) return bad(err, "edge_var is NULL");
+    for (int64_t e = 0; e < E; ++e)
+        if (d->edge_var[e] < 0 || d->edge_var[e] >= V)
+            return bad(err, at("edge_var", e) + " out of range");
+
+    if (!monotone_from_zero(d->logpot_off, F))
+        return bad(err, "logpot_off must start at 0 and be non-decreasing");
+    const int64_t Tn = d->logpot_off[F];
+    if (Tn > 0 && !d->log_potentials) return bad(err, "log_potentials is NULL");
+    for (int64_t i = 0; i < Tn; ++i)
+        if (!std::isfinite(d->log_potentials[i]))
+            return bad(err, at("log_potentials", i) + " is not finite");
+
+    if (NT > 0) {
+        if (!monotone_from_zero(d->cfg_table_off, NT))
+            return bad(err, "cfg_table_off must start at 0 and be non-decreasing");
+        if (d->cfg_table_off[NT] > 0 && !d->cfg_table_states) return bad(err, "cfg_table_states is NULL");
+        for (int64_t t = 0; t < NT; ++t) {
+            int64_t a = d->cfg_table_arity[t], c = d->cfg_table_num_cfgs[t];
+            int64_t len = d->cfg_table_off[t + 1] - d->cfg_table_off[t];
+            if (a < 1) return bad(err, at("cfg_table_arity", t) + " < 1");
+            if (c < 0) return bad(err, at("cfg_table_num_cfgs", t) + " < 0");
+            if (len != c * a) return bad(err, "table " + std::to_string(t) + " holds " +
+                                                 std::to_string(len) + " states, expected num_cfgs*arity");
+        }
+    }
+
+    // explicit tables checked once per (table, slot state counts)
+    std::map<std::vector<int32_t>, int> checked;
+    for (int64_t f = 0; f < F; ++f) {
+        const int64_t e0 = d->factor_edge_off[f];
+        const int64_t k = d->factor_edge_off[f + 1] - e0;
+        const int64_t nlp = d->logpot_off[f + 1] - d->logpot_off[f];
+        const int32_t kind = d->factor_kind[f];
+        if (kind == LBP_FACTOR_ENUM) {
+            if (k < 1) return bad(err, "enumeration factor " + std::to_string(f) + " has no edge");
+            int32_t t = d->factor_cfg_table[f];
+            if (t < 0 || t >= NT) return bad(err, at("factor_cfg_table", f) + " out of range");
+            if (d->cfg_table_arity[t] != k)
+                return bad(err, "factor " + std::to_string(f) + " has arity " + std::to_string(k) +
+                                    " but its table has arity " + std::to_string(d->cfg_table_arity[t]));
+            std::vector<int32_t> ns(k);
+            int64_t nsum = 0;
+            for (int64_t j = 0; j < k; ++j) {
+                ns[j] = d->var_num_states[d->edge_var[e0 + j]];
+                nsum += ns[j];
+            }
+            const bool dense = d->cfg_table_num_cfgs[t] == 0;
+            int64_t ncfg;
+            if (dense) {
+                ncfg = 1;
+                for (int64_t j = 0; j < k; ++j) {
+                    ncfg *= ns[j];
+                    if (ncfg > INT32_MAX) return bad(err, "dense table of factor " + std::to_string(f) +
+                                                              " is too large", LBP_E_UNSUPPORTED);
+                }
+            } else {
+                ncfg = d->cfg_table_num_cfgs[t];
+                std::vector<int32_t> key(ns);
+                key.push_back(t);
+                if (!checked.count(key)) {
+                    std::vector<std::vector<char>> cov(k);
+                    for (int64_t j = 0; j < k; ++j) cov[j].assign(ns[j], 0);
+                    const int32_t *st = d->cfg_table_states + d->cfg_table_off[t];
+                    for (int64_t c = 0; c < ncfg; ++c)
+                        for (int64_t j = 0; j < k; ++j) {
+                            int32_t s = st[c * k + j];
+                            if (s < 0 || s >= ns[j])
+                                return bad(err, "table " + std::to_string(t) + " config " + std::to_string(c) +
+                                                    " slot " + std::to_string(j) + " state out of range for factor " +
+                                                    std::to_string(f));
+                            cov[j][s] = 1;
+                        }
+                    for (int64_t j = 0; j < k; ++j)
+                        for (int32_t s = 0; s < ns[j]; ++s)
+                            if (!cov[j][s])
+                                return bad(err, "factor " + std::to_string(f) + ": no configuration has slot " +
+                                                    std::to_string(j) + " in state " + std::to_string(s));
+                    checked[key] = 1;
+                }
+            }
+            if (nlp != ncfg)
+                return bad(err, "factor " + std::to_string(f) + " has " + std::to_string(nlp) +
+                                    " log-potentials, its table " + std::to_string(ncfg) + " configurations");
+            if (!pair_fast(dense, (int32_t)k, ns.data()) &&
+                (k > kGenArityMax || ncfg > kGenCfgMax || nsum > kGenRowsMax))
+                return bad(err, "enumeration factor " + std::to_string(f) +
+                                    " exceeds the generic kernel limits (arity <= 8, <= 4096 configurations, "
+                                    "<= 64 summed slot states)", LBP_E_UNSUPPORTED);
+        } else if (kind == LBP_FACTOR_OR || kind == LBP_FACTOR_AND) {
+            if (k < 2) return bad(err, "logical factor " + std::to_string(f) + " needs a parent and a child");
+            if (k > kLogWaveArityMax)
+                return bad(err, "logical factor " + std::to_string(f) + " has more than 1024 edges",
+                           LBP_E_UNSUPPORTED);
+            for (int64_t j = 0; j < k; ++j)
+                if (d->var_num_states[d->edge_var[e0 + j]] != 2)
+                    return bad(err, "logical factor " + std::to_string(f) + " touches a non-binary variable");
+            if (nlp != 0) return bad(err, "logical factor " + std::to_string(f) + " has log-potentials");
+        } else {
+            return bad(err, at("factor_kind", f) + " is not 0, 1 or 2");
+        }
+    }
+    int64_t ES = 0;
+    for (int64_t e = 0; e < E; ++e) ES += d->var_num_states[d->edge_var[e]];
+    if (sizes) {
+        sizes[0] = V; sizes[1] = VS; sizes[2] = F; sizes[3] = E; sizes[4] = ES; sizes[5] = Tn;
+    }
+    return LBP_OK;
+}
+
+int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
+    int64_t sz[6];
+    int rc = validate_desc(d, sz, err);
+    if (rc != LBP_OK) return rc;
+    L->V = sz[0]; L->VS = sz[1]; L->F = sz[2]; L->E = sz[3]; L->ES = sz[4]; L->Tn = sz[5];
+    const int64_t V = L->V, F = L->F, E = L->E;
+
+    L->vs_off.assign(V + 1, 0);
+    L->vn.assign(V, 0);
+    for (int64_t v = 0; v < V; ++v) {
+        L->vn[v] = d->var_num_states[v];
+        L->vs_off[v + 1] = L->vs_off[v] + L->vn[v];
+    }
+    L->es_off.assign(E + 1, 0);
+    for (int64_t e = 0; e < E; ++e) L->es_off[e + 1] = L->es_off[e] + L->vn[d->edge_var[e]];
+    L->lp_off.assign(d->logpot_off, d->logpot_off + F + 1);
+
+    // ---------------------------------------------------------- variable tiles
+    const int64_t nvt = (V + kLanes - 1) / kLanes;
+    std::vector<int32_t> vaddr(V);
+    L->vtile.resize(nvt);
+    int64_t VB = 0;
+    for (int64_t t = 0; t < nvt; ++t) {
+        int32_t nt = 2;
+        for (int64_t v = t * kLanes; v < std::min<int64_t>(V, (t + 1) * kLanes); ++v) nt = std::max(nt, L->vn[v]);
+        L->vtile[t].b_off = (int32_t)VB;
+        L->vtile[t].n = nt;
+        for (int64_t v = t * kLanes; v < std::min<int64_t>(V, (t + 1) * kLanes); ++v)
+            vaddr[v] = (int32_t)(VB + (v - t * kLanes));
+        VB += (int64_t)kLanes * nt;
+        if (VB >= INT32_MAX) return bad(err, "belief array exceeds 2^31 floats", LBP_E_UNSUPPORTED);
+    }
+    // a spare panel that idle lanes of partly filled factor tiles point at
+    const int32_t b_zero = (int32_t)VB;
+    VB += (int64_t)kLanes * kMaxStates;
+    L->VB = VB;
+    auto add_vb_rows = [&](int32_t rows) {
+        const size_t base = L->fvb.size();
+        L->fvb.resize(base + (size_t)rows * kLanes);
+        for (int32_t r = 0; r < rows; ++r)
+            for (int32_t l = 0; l < kLanes; ++l) L->fvb[base + (size_t)r * kLanes + l] = b_zero + l;
+    };
+
+    // variable -> edges, increasing edge order
+    std::vector<int64_t> adj_off(V + 1, 0), adj(E);
+    for (int64_t e = 0; e < E; ++e) adj_off[d->edge_var[e] + 1]++;
+    for (int64_t v = 0; v < V; ++v) adj_off[v + 1] += adj_off[v];
+    {
+        std::vector<int64_t> fill(adj_off.begin(), adj_off.end() - 1);
+        for (int64_t e = 0; e < E; ++e) adj[fill[d->edge_var[e]]++] = e;
+    }
+
+    // ---------------------------------------------------------- factor classes
+    // key: (tile kind, a, b, table, slot state counts)
+    typedef std::tuple<int32_t, int32_t, int32_t, int32_t, std::vector<int32_t>> Key;
+    std::map<Key, int32_t> class_of;
+    std::vector<Key> class_key;
+    std::vector<std::vector<int32_t>> class_facs;
+    std::vector<int32_t> fclass(F);
+    for (int64_t f = 0; f < F; ++f) {
+        const int64_t e0 = d->factor_edge_off[f];
+        const int32_t k = (int32_t)(d->factor_edge_off[f + 1] - e0);
+        std::vector<int32_t> ns(k);
+        for (int32_t j = 0; j < k; ++j) ns[j] = L->vn[d->edge_var[e0 + j]];
+        Key key;
+        if (d->factor_kind[f] == LBP_FACTOR_ENUM) {
+            int32_t t = d->factor_cfg_table[f];
+            bool dense = d->cfg_table_num_cfgs[t] == 0;
+            if (pair_fast(dense, k, ns.data()))
+                key = Key(TK_PAIR, ns[0], ns[1], -1, std::vector<int32_t>());
+            else
+                key = Key(TK_GEN, k, 0, dense ? -1 : t, ns);
+        } else {
+            int32_t flip = d->factor_kind[f] == LBP_FACTOR_AND;
+            if (k <= kLogLaneArityMax)
+                key = Key(TK_LOGL, k, flip, -1, std::vector<int32_t>());
+            else  // one tile per factor; grouped by chunk bucket
+                key = Key(TK_LOGW, chunk_bucket((k + kLanes - 1) / kLanes), 0, -1, std::vector<int32_t>());
+        }
+        auto it = class_of.find(key);
+        int32_t c;
+        if (it == class_of.end()) {
+            c = (int32_t)class_key.size();
+            class_of[key] = c;
+            class_key.push_back(key);
+            class_facs.emplace_back();
+        } else {
+            c = it->second;
+        }
+        class_facs[c].push_back((int32_t)f);
+        fclass[f] = c;
+    }
+
+    L->edge_maddr.assign(E, 0);
+    L->fac_phi.assign(F, -1);
+    int64_t M = 0, P = 0;
+    auto check = [&](int64_t x, const char *what) {
+        return x < INT32_MAX - 4096 ? LBP_OK : bad(err, std::string(what) + " exceeds 2^31 floats", LBP_E_UNSUPPORTED);
+    };
+    std::vector<std::pair<int64_t, float>> phi_fill;  // filled after sizing
+    for (size_t c = 0; c < class_key.size(); ++c) {
+        const int32_t kind = std::get<0>(class_key[c]);
+        const std::vector<int32_t> &facs = class_facs[c];
+        FGroup grp;
+        grp.kind = kind;
+        grp.a = 0;
+        grp.b = 0;
+        if (kind == TK_PAIR) {
+            const int32_t na = std::get<1>(class_key[c]), nb = std::get<2>(class_key[c]);
+            grp.a = na;
+            grp.b = nb;
+            for (size_t i0 = 0; i0 < facs.size(); i0 += kLanes) {
+                FTile ft{};
+                ft.kind = TK_PAIR;
+                ft.a = na;
+                ft.b = nb;
+                ft.nact = (int32_t)std::min<size_t>(kLanes, facs.size() - i0);
+                ft.m_off = (int32_t)M;
+                ft.phi_off = (int32_t)P;
+                ft.vb_off = (int32_t)L->fvb.size();
+                add_vb_rows(2);
+                for (int32_t l = 0; l < ft.nact; ++l) {
+                    const int64_t f = facs[i0 + l], e0 = d->factor_edge_off[f];
+                    L->edge_maddr[e0] = (int32_t)(M + l);
+                    L->edge_maddr[e0 + 1] = (int32_t)(M + (int64_t)na * kLanes + l);
+                    L->fvb[ft.vb_off + l] = vaddr[d->edge_var[e0]];
+                    L->fvb[ft.vb_off + kLanes + l] = vaddr[d->edge_var[e0 + 1]];
+                    L->fac_phi[f] = (int32_t)(P + l);
+                }
+                M += (int64_t)kLanes * (na + nb);
+                P += (int64_t)kLanes * na * nb;
+                if ((rc = check(M, "message array")) || (rc = check(P, "potential array"))) return rc;
+                grp.tiles.push_back((int32_t)L->ftile.size());
+                L->ftile.push_back(ft);
+            }
+        } else if (kind == TK_LOGL) {
+            const int32_t k = std::get<1>(class_key[c]), flip = std::get<2>(class_key[c]);
+            for (size_t i0 = 0; i0 < facs.size(); i0 += kLanes) {
+                FTile ft{};
+                ft.kind = TK_LOGL;
+                ft.a = k;
+                ft.b = flip;
+                ft.nact = (int32_t)std::min<size_t>(kLanes, facs.size() - i0);
+                ft.m_off = (int32_t)M;
+                ft.vb_off = (int32_t)L->fvb.size();
+                add_vb_rows(k);
+                for (int32_t l = 0; l < ft.nact; ++l) {
+                    const int64_t f = facs[i0 + l], e0 = d->factor_edge_off[f];
+                    for (int32_t j = 0; j < k; ++j) {
+                        L->edge_maddr[e0 + j] = (int32_t)(M + (int64_t)2 * j * kLanes + l);
+                        L->fvb[ft.vb_off + j * kLanes + l] = vaddr[d->edge_var[e0 + j]];
+                    }
+                }
+                M += (int64_t)kLanes * 2 * k;
+                if ((rc = check(M, "message array"))) return rc;
+                grp.tiles.push_back((int32_t)L->ftile.size());
+                L->ftile.push_back(ft);
+            }
+        } else if (kind == TK_LOGW) {
+            grp.a = std::get<1>(class_key[c]);
+            for (int32_t f : facs) {
+                const int64_t e0 = d->factor_edge_off[f];
+                const int32_t k = (int32_t)(d->factor_edge_off[f + 1] - e0);
+                const int32_t chunks = (k + kLanes - 1) / kLanes;
+                FTile ft{};
+                ft.kind = TK_LOGW;
+                ft.a = k;
+                ft.b = d->factor_kind[f] == LBP_FACTOR_AND;
+                ft.nact = 1;
+                ft.m_off = (int32_t)M;
+                ft.vb_off = (int32_t)L->fvb.size();
+                add_vb_rows(chunks);
+                for (int32_t j = 0; j < k; ++j) {
+                    const int32_t ch = j / kLanes, l = j % kLanes;
+                    L->edge_maddr[e0 + j] = (int32_t)(M + (int64_t)ch * 2 * kLanes + l);
+                    L->fvb[ft.vb_off + j] = vaddr[d->edge_var[e0 + j]];
+                }
+                M += (int64_t)chunks * 2 * kLanes;
+                if ((rc = check(M, "message array"))) return rc;
+                grp.tiles.push_back((int32_t)L->ftile.size());
+                L->ftile.push_back(ft);
+            }
+        } else {  // TK_GEN
+            const int32_t k = std::get<1>(class_key[c]);
+            const int32_t t = std::get<3>(class_key[c]);
+            const std::vector<int32_t> &ns = std::get<4>(class_key[c]);
+            GenClass gc{};
+            gc.arity = k;
+            int32_t rows = 0;
+            for (int32_t j = 0; j < k; ++j) {
+                gc.slot_n[j] = ns[j];
+                gc.slot_row[j] = rows;
+                rows += ns[j];
+            }
+            gc.nrows = rows;
+            gc.rows_off = (int32_t)L->grows.size();
+            if (t < 0) {  // dense: every joint state, last slot fastest
+                int64_t ncfg = 1;
+                for (int32_t j = 0; j < k; ++j) ncfg *= ns[j];
+                gc.ncfg = (int32_t)ncfg;
+                for (int64_t cfg = 0; cfg < ncfg; ++cfg) {
+                    int64_t r = cfg;
+                    std::vector<int32_t> st(k);
+                    for (int32_t j = k - 1; j >= 0; --j) {
+                        st[j] = (int32_t)(r % ns[j]);
+                        r /= ns[j];
+                    }
+                    for (int32_t j = 0; j < k; ++j) L->grows.push_back((uint8_t)(gc.slot_row[j] + st[j]));
+                }
+            } else {
+                gc.ncfg = d->cfg_table_num_cfgs[t];
+                const int32_t *st = d->cfg_table_states + d->cfg_table_off[t];
+                for (int64_t cfg = 0; cfg < gc.ncfg; ++cfg)
+                    for (int32_t j = 0; j < k; ++j)
+                        L->grows.push_back((uint8_t)(gc.slot_row[j] + st[cfg * k + j]));
+            }
+            const int32_t gidx = (int32_t)L->gcls.size();
+            L->gcls.push_back(gc);
+            for (size_t i0 = 0; i0 < facs.size(); i0 += kLanes) {
+                FTile ft{};
+                ft.kind = TK_GEN;
+                ft.a = gidx;
+                ft.nact = (int32_t)std::min<size_t>(kLanes, facs.size() - i0);
+                ft.m_off = (int32_t)M;
+                ft.phi_off = (int32_t)P;
+                ft.vb_off = (int32_t)L->fvb.size();
+                add_vb_rows(k);
+                for (int32_t l = 0; l < ft.nact; ++l) {
+                    const int64_t f = facs[i0 + l], e0 = d->factor_edge_off[f];
+                    for (int32_t j = 0; j < k; ++j) {
+                        L->edge_maddr[e0 + j] = (int32_t)(M + (int64_t)gc.slot_row[j] * kLanes + l);
+                        L->fvb[ft.vb_off + j * kLanes + l] = vaddr[d->edge_var[e0 + j]];
+                    }
+                    L->fac_phi[f] = (int32_t)(P + l);
+                }
+                M += (int64_t)kLanes * rows;
+                P += (int64_t)kLanes * gc.ncfg;
+                if ((rc = check(M, "message array")) || (rc = check(P, "potential array"))) return rc;
+                grp.tiles.push_back((int32_t)L->ftile.size());
+                L->ftile.push_back(ft);
+            }
+        }
+        // LOGW groups of the same bucket merge; others are one class each
+        bool merged = false;
+        if (kind == TK_LOGW)
+            for (FGroup &g : L->fgroups)
+                if (g.kind == TK_LOGW && g.a == grp.a) {
+                    g.tiles.insert(g.tiles.end(), grp.tiles.begin(), grp.tiles.end());
+                    merged = true;
+                }
+        if (!merged) L->fgroups.push_back(grp);
+    }
+    L->zero_addr = (int32_t)M;
+    M += (int64_t)kLanes * kLowStatesMax;
+    L->M = M;
+    L->P = P > 0 ? P : kLanes;
+
+    // ------------------------------------------------ variable edge-address rows
+    L->vns.assign(nvt * kLanes, 0);
+    std::map<int32_t, size_t> vgroup_of;
+    for (int64_t t = 0; t < nvt; ++t) {
+        int32_t kmax = 0, nlow = 0;
+        const int64_t v0 = t * kLanes, v1 = std::min<int64_t>(V, v0 + kLanes);
+        for (int64_t v = v0; v < v1; ++v) {
+            int64_t deg = adj_off[v + 1] - adj_off[v];
+            bool low = deg <= kLowDegMax && L->vn[v] <= kLowStatesMax;
+            if (low) {
+                kmax = std::max<int32_t>(kmax, (int32_t)deg);
+                nlow = std::max<int32_t>(nlow, L->vn[v]);
+                L->vns[v] = L->vn[v];
+            } else {
+                HVar h{};
+                h.b_addr = vaddr[v];
+                h.n = L->vn[v];
+                h.e_begin = (int32_t)L->hedge.size();
+                for (int64_t i = adj_off[v]; i < adj_off[v + 1]; ++i) L->hedge.push_back(L->edge_maddr[adj[i]]);
+                h.e_end = (int32_t)L->hedge.size();
+                L->hvar.push_back(h);
+            }
+        }
+        VTile &vt = L->vtile[t];
+        vt.kmax = kmax;
+        vt.e_off = (int32_t)L->vedge.size();
+        L->vedge.resize(L->vedge.size() + (size_t)kmax * kLanes);
+        for (int32_t k = 0; k < kmax; ++k)
+            for (int32_t l = 0; l < kLanes; ++l) {
+                const int64_t v = v0 + l;
+                int32_t a = L->zero_addr + l;
+                if (v < v1 && L->vns[v] > 0 && k < adj_off[v + 1] - adj_off[v])
+                    a = L->edge_maddr[adj[adj_off[v] + k]];
+                L->vedge[vt.e_off + (size_t)k * kLanes + l] = a;
+            }
+        if (nlow > 0) {
+            int32_t b = state_bucket(nlow);
+            auto it = vgroup_of.find(b);
+            if (it == vgroup_of.end()) {
+                vgroup_of[b] = L->vgroups.size();
+                L->vgroups.push_back(VGroup{b, {}});
+                it = vgroup_of.find(b);
+            }
+            L->vgroups[it->second].tiles.push_back((int32_t)t);
+        }
+    }
+    if (L->vedge.size() >= (size_t)INT32_MAX || L->hedge.size() >= (size_t)INT32_MAX ||
+        L->fvb.size() >= (size_t)INT32_MAX)
+        return bad(err, "index tables exceed 2^31 entries", LBP_E_UNSUPPORTED);
+
+    // -------------------------------------------------------------- values
+    L->theta_panel.assign(L->VB, 0.0f);
+    if (d->evidence)
+        for (int64_t v = 0; v < V; ++v)
+            for (int32_t s = 0; s < L->vn[v]; ++s)
+                L->theta_panel[vaddr[v] + (int64_t)s * kLanes] = d->evidence[L->vs_off[v] + s];
+    L->phi_panel.assign(L->P, 0.0f);
+    for (int64_t f = 0; f < F; ++f) {
+        if (L->fac_phi[f] < 0) continue;
+        for (int64_t c = 0; c < L->lp_off[f + 1] - L->lp_off[f]; ++c)
+            L->phi_panel[L->fac_phi[f] + c * kLanes] = d->log_potentials[L->lp_off[f] + c];
+    }
+    return LBP_OK;
+}
+
+// Replays the address arithmetic of every kernel over the compiled layout and
+// checks each access against its array's size.  Host only.
+int check_layout(const HostLayout &L, std::string *err) {
+    const int64_t M = L.M, VB = L.VB, P = L.P;
+    auto oob = [&](const std::string &what) { return bad(err, "layout check: " + what); };
+    auto in = [](int64_t a, int64_t n) { return a >= 0 && a < n; };
+    // variable phase, low-degree lanes
+    for (const VGroup &vg : L.vgroups)
+        for (int32_t t : vg.tiles) {
+            if (!in(t, (int64_t)L.vtile.size())) return oob("var tile index");
+            const VTile &vt = L.vtile[t];
+            for (int32_t l = 0; l < kLanes; ++l) {
+                const int32_t n = L.vns[(size_t)t * kLanes + l];
+                if (n > vg.bucket || n > vt.n) return oob("lane states exceed bucket/panel");
+                for (int32_t s = 0; s < n; ++s)
+                    if (!in(vt.b_off + l + (int64_t)s * kLanes, VB)) return oob("belief-low B/theta");
+                for (int32_t k = 0; k < vt.kmax; ++k) {
+                    const int64_t ei = vt.e_off + (int64_t)k * kLanes + l;
+                    if (!in(ei, (int64_t)L.vedge.size())) return oob("vedge index");
+                    for (int32_t s = 0; s < n; ++s)
+                        if (!in(L.vedge[ei] + (int64_t)s * kLanes, M)) return oob("belief-low message");
+                }
+            }
+        }
+    // variable phase, high-degree variables
+    for (const HVar &h : L.hvar) {
+        if (h.e_begin < 0 || h.e_end < h.e_begin || h.e_end > (int64_t)L.hedge.size()) return oob("hedge range");
+        for (int32_t s = 0; s < h.n; ++s) {
+            if (!in(h.b_addr + (int64_t)s * kLanes, VB)) return oob("belief-high B/theta");
+            for (int32_t k = h.e_begin; k < h.e_end; ++k)
+                if (!in(L.hedge[k] + (int64_t)s * kLanes, M)) return oob("belief-high message");
+        }
+    }
+    // factor phase
+    auto vb_rows = [&](const FTile &ft, int32_t rows, const int32_t *row_n) -> bool {
+        for (int32_t r = 0; r < rows; ++r)
+            for (int32_t l = 0; l < kLanes; ++l) {
+                const int64_t i = ft.vb_off + (int64_t)r * kLanes + l;
+                if (!in(i, (int64_t)L.fvb.size())) return false;
+                for (int32_t s = 0; s < row_n[r]; ++s)
+                    if (!in(L.fvb[i] + (int64_t)s * kLanes, VB)) return false;
+            }
+        return true;
+    };
+    for (const FGroup &fg : L.fgroups)
+        for (int32_t t : fg.tiles) {
+            if (!in(t, (int64_t)L.ftile.size())) return oob("factor tile index");
+            const FTile &ft = L.ftile[t];
+            if (ft.kind != fg.kind) return oob("tile kind differs from its launch group");
+            if (ft.kind == TK_PAIR) {
+                const int32_t ns[2] = {ft.a, ft.b};
+                if (ft.a > kPairStatesMax || ft.b > kPairStatesMax) return oob("pair states");
+                if (fg.a != ft.a || fg.b != ft.b) return oob("pair group shape");
+                if (!vb_rows(ft, 2, ns)) return oob("pair belief rows");
+                if (!in(ft.m_off + (int64_t)(ft.a + ft.b) * kLanes - 1, M)) return oob("pair messages");
+                if (!in(ft.phi_off + (int64_t)ft.a * ft.b * kLanes - 1, P)) return oob("pair potentials");
+            } else if (ft.kind == TK_LOGL) {
+                if (ft.a < 2 || ft.a > kLogLaneArityMax) return oob("lane logical arity");
+                const int32_t ns[kLogLaneArityMax] = {2, 2, 2, 2, 2, 2, 2, 2};
+                if (!vb_rows(ft, ft.a, ns)) return oob("lane logical belief rows");
+                if (!in(ft.m_off + (int64_t)2 * ft.a * kLanes - 1, M)) return oob("lane logical messages");
+            } else if (ft.kind == TK_LOGW) {
+                const int32_t ch = (ft.a + kLanes - 1) / kLanes;
+                if (ft.a < 2 || ft.a > kLogWaveArityMax || ch > fg.a) return oob("wave logical arity/bucket");
+                for (int32_t j = 0; j < ft.a; ++j) {
+                    const int64_t i = ft.vb_off + j;
+                    if (!in(i, (int64_t)L.fvb.size()) || !in(L.fvb[i] + kLanes, VB)) return oob("wave logical beliefs");
+                }
+                if (!in(ft.m_off + (int64_t)ch * 2 * kLanes - 1, M)) return oob("wave logical messages");
+            } else if (ft.kind == TK_GEN) {
+                if (!in(ft.a, (int64_t)L.gcls.size())) return oob("generic class index");
+                const GenClass &gc = L.gcls[ft.a];
+                if (gc.arity > kGenArityMax || gc.ncfg > kGenCfgMax || gc.nrows > kGenRowsMax) return oob("generic limits");
+                if (gc.rows_off + (int64_t)gc.ncfg * gc.arity > (int64_t)L.grows.size()) return oob("generic rows");
+                for (int64_t i = 0; i < (int64_t)gc.ncfg * gc.arity; ++i)
+                    if (L.grows[gc.rows_off + i] >= gc.nrows) return oob("generic row entry");
+                if (!vb_rows(ft, gc.arity, gc.slot_n)) return oob("generic belief rows");
+                if (!in(ft.m_off + (int64_t)gc.nrows * kLanes - 1, M)) return oob("generic messages");
+                if (!in(ft.phi_off + (int64_t)gc.ncfg * kLanes - 1, P)) return oob("generic potentials");
+            } else {
+                return oob("unknown tile kind");
+            }
+        }
+    // read-out and flat-order exchange
+    for (int64_t v = 0; v < L.V; ++v) {
+        const VTile &vt = L.vtile[v / kLanes];
+        if (L.vn[v] > vt.n) return oob("read-out panel rows");
+        if (!in(vt.b_off + v % kLanes + (int64_t)(L.vn[v] - 1) * kLanes, VB)) return oob("read-out beliefs");
+    }
+    for (int64_t e = 0; e < L.E; ++e) {
+        const int64_t n = L.es_off[e + 1] - L.es_off[e];
+        if (!in(L.edge_maddr[e] + (n - 1) * kLanes, M)) return oob("edge message address");
+    }
+    for (int64_t f = 0; f < L.F; ++f)
+        if (L.fac_phi[f] >= 0 && !in(L.fac_phi[f] + (L.lp_off[f + 1] - L.lp_off[f] - 1) * kLanes, P))
+            return oob("factor potential address");
+    if (!in(L.zero_addr + (int64_t)kLowStatesMax * kLanes - 1, M)) return oob("zero panel");
+    return LBP_OK;
+}
+
+}  // namespace lbp

@@ -1,0 +1,59 @@
+// Host-side validation of an lbp_graph_desc and its compilation into the
+// 64-lane panel layout described in lbp_internal.h.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbp.h"
+#include "lbp_internal.h"
+
+namespace lbp {
+
+// Factor tiles launched together: same kernel, same shape.
+struct FGroup {
+    int32_t kind;  // TK_*
+    int32_t a, b;  // PAIR: slot state counts; LOGW: chunk count bucket; otherwise 0
+    std::vector<int32_t> tiles;
+};
+
+// Variable tiles launched together in the low-degree belief kernel.
+struct VGroup {
+    int32_t bucket;  // register bucket: max states over the tiles' low-degree lanes
+    std::vector<int32_t> tiles;
+};
+
+struct HostLayout {
+    int64_t V = 0, VS = 0, F = 0, E = 0, ES = 0, Tn = 0;
+    int64_t M = 0, VB = 0, P = 0;  // floats in the message, belief and potential arrays
+    int32_t zero_addr = 0;
+    std::vector<FTile> ftile;
+    std::vector<int32_t> fvb;
+    std::vector<VTile> vtile;
+    std::vector<int32_t> vedge, vns;
+    std::vector<HVar> hvar;
+    std::vector<int32_t> hedge;
+    std::vector<GenClass> gcls;
+    std::vector<uint8_t> grows;
+    std::vector<int32_t> edge_maddr;
+    std::vector<int64_t> es_off, vs_off;
+    std::vector<int32_t> vn, fac_phi;
+    std::vector<int64_t> lp_off;
+    std::vector<float> theta_panel, phi_panel;
+    std::vector<FGroup> fgroups;
+    std::vector<VGroup> vgroups;
+};
+
+// Returns LBP_OK or an LBP_E_* code with a message in *err.
+int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err);
+int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err);
+// Host replay of every kernel's addresses against the layout's array sizes.
+int check_layout(const HostLayout &L, std::string *err);
+
+// Bucket of the low-degree belief kernel for a tile whose low lanes have at
+// most n states.
+inline int32_t state_bucket(int32_t n) { return n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : 16; }
+// Chunk bucket of the wave-per-factor logical kernel.
+inline int32_t chunk_bucket(int32_t chunks) { return chunks <= 1 ? 1 : chunks <= 4 ? 4 : 16; }
+
+}  // namespace lbp

@@ -1,0 +1,38 @@
+// Launchers of the HIP kernels (kernels.hip).  Each returns the HIP error of
+// the launch; item arrays and graph arrays are device pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbp_internal.h"
+
+namespace lbp {
+
+// Per-launch constants of an iteration at damping d and temperature T.
+struct TParams {
+    float d, omd;  // weight of the previous message and 1 - d
+    float T, invT;
+    float c, r;    // log2(e) / T and T ln 2 (LSE_T in base 2)
+};
+
+TParams make_params(float damping, float temperature);
+
+hipError_t launch_belief_low(const DevGraph *gs, const WorkItem *items, int n, int bucket, hipStream_t st);
+hipError_t launch_belief_high(const DevGraph *gs, const WorkItem *items, int n, hipStream_t st);
+hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
+                       const TParams &P, hipStream_t st);
+hipError_t launch_logl(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
+                       hipStream_t st);
+hipError_t launch_logw(const DevGraph *gs, const WorkItem *items, int n, int chunk_bucket, bool maxp,
+                       const TParams &P, hipStream_t st);
+hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
+                      hipStream_t st);
+// Read-out of a single graph (gs[0]).
+hipError_t launch_readout(const DevGraph *gs, int nvtiles, bool maxp, const TParams &P, float *q, int normalized,
+                          int32_t *map, hipStream_t st);
+hipError_t launch_msgs_out(const DevGraph *gs, int E, float *out, hipStream_t st);
+hipError_t launch_msgs_in(const DevGraph *gs, int E, const float *in, hipStream_t st);
+hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStream_t st);
+hipError_t launch_logpot_in(const DevGraph *gs, int F, const float *in, hipStream_t st);
+
+}  // namespace lbp

@@ -1,0 +1,755 @@
+// HIP kernels of one damped log-domain LBP iteration on gfx950 (CDNA4).
+//
+// An iteration (parallel updates with damping, PGMax Sec. "Package
+// features") runs in two phases:
+//   variable phase  B[v,s] = theta[v,s] + sum_{e in N(v)} m[e,s]
+//                   (segmented sum over the variable's edge rows, edges in
+//                   increasing order, no atomics)
+//   factor phase    n = B[var(e)] - m[e]  (formed on the fly, never stored),
+//                   factor-to-variable update u (max / LSE_T over the
+//                   factor's configurations, or the OR/AND closed forms),
+//                   then m <- d m + (1-d) u and m -= max_s m, written in
+//                   place.  Each message row is read and written by the one
+//                   lane that owns its factor, after the variable phase has
+//                   consumed the old values, so no barrier is needed inside
+//                   the phase.
+// The work is memory-bound: there is no dense contraction, hence no MFMA.
+// Data sit in 64-lane panels (lbp_internal.h) so that a wavefront's loads
+// and stores are unit-stride 256-byte accesses.
+//
+// Every per-element result is computed by one device function in a fixed
+// order whichever kernel, batch or launch shape runs it, and the library is
+// built with -ffp-contract=off, so a graph gives the same bits alone and in a
+// batch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace lbp {
+
+namespace {
+
+__device__ __forceinline__ int wave_index(int waves_per_block) {
+    return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * waves_per_block + (threadIdx.x >> 6)));
+}
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+
+// T log(1 + e^{x/T}) = LSE_T(0, x); 0 at x = -inf.
+__device__ __forceinline__ float softplus_t(float x, const TParams &P) {
+    if (x == -INFINITY) return 0.0f;
+    float pos = x > 0.0f ? x : 0.0f;
+    return pos + P.T * log1pf(expf(-fabsf(x) * P.invT));
+}
+// T log(e^{a/T} - 1) for a >= 0; -inf at a = 0.
+__device__ __forceinline__ float lem_t(float a, const TParams &P) {
+    if (!(a > 0.0f)) return -INFINITY;
+    return a + P.T * logf(-expm1f(-a * P.invT));
+}
+
+// damp, normalise and store one message row of n states held in registers
+template <int N>
+__device__ __forceinline__ void damp_store(float *row, const float (&mo)[N], const float (&u)[N], int n,
+                                           const TParams &P) {
+    float mn[N];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int s = 0; s < N; ++s)
+        if (s < n) {
+            float a = P.d * mo[s];
+            float b = P.omd * u[s];
+            mn[s] = a + b;
+            mx = fmaxf(mx, mn[s]);
+        }
+#pragma unroll
+    for (int s = 0; s < N; ++s)
+        if (s < n) row[s * kLanes] = mn[s] - mx;
+}
+
+// --------------------------------------------------------------------------
+// variable phase
+// --------------------------------------------------------------------------
+
+// One wavefront per variable tile, one lane per variable; NB >= states of
+// every low-degree lane of the tile.
+template <int NB>
+__global__ __launch_bounds__(256) void k_belief_low(const DevGraph *__restrict__ gs,
+                                                    const WorkItem *__restrict__ items, int nitems) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const int lane = lane_id();
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const VTile vt = G.vtile[it.t];
+    const int n = G.vns[it.t * kLanes + lane];
+    const int base = vt.b_off + lane;
+    float acc[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) acc[s] = (s < n) ? G.theta[base + s * kLanes] : 0.0f;
+    const int32_t *ea = G.vedge + vt.e_off + lane;
+    for (int k = 0; k < vt.kmax; ++k) {
+        const float *row = G.m + ea[k * kLanes];
+#pragma unroll
+        for (int s = 0; s < NB; ++s)
+            if (s < n) acc[s] += row[s * kLanes];
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s)
+        if (s < n) G.B[base + s * kLanes] = acc[s];
+}
+
+// One wavefront per high-degree variable: lanes take edges k = lane, lane+64,
+// ..., then a butterfly reduction (every lane ends with the same bits).
+__global__ __launch_bounds__(256) void k_belief_high(const DevGraph *__restrict__ gs,
+                                                     const WorkItem *__restrict__ items, int nitems) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const int lane = lane_id();
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const HVar h = G.hvar[it.t];
+    for (int s0 = 0; s0 < h.n; s0 += 8) {
+        float part[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) part[j] = 0.0f;
+        for (int k = h.e_begin + lane; k < h.e_end; k += kLanes) {
+            const float *row = G.m + G.hedge[k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (s0 + j < h.n) part[j] += row[(s0 + j) * kLanes];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) part[j] += __shfl_xor(part[j], off, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (s0 + j < h.n) {
+                    const int a = h.b_addr + (s0 + j) * kLanes;
+                    G.B[a] = G.theta[a] + part[j];
+                }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// factor phase: dense pairwise enumeration factors (one lane per factor)
+// --------------------------------------------------------------------------
+// u0[i] = LSE_T,j (phi(i,j) + n1[j]),  u1[j] = LSE_T,i (phi(i,j) + n0[i]);
+// equal to LSE over the configurations with that slot fixed, minus the slot's
+// own incoming term.  EXACT: NA x NB known at compile time; otherwise the
+// tile's (a, b) <= (NA, NB) are read at run time with the same arithmetic.
+template <int NA, int NB, bool EXACT, bool MAXP>
+__device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+    const int na = EXACT ? NA : ft.a;
+    const int nb = EXACT ? NB : ft.b;
+    const int va = G.fvb[ft.vb_off + lane];
+    const int vb = G.fvb[ft.vb_off + kLanes + lane];
+    float *r0 = G.m + ft.m_off + lane;
+    float *r1 = r0 + na * kLanes;
+    float m0[NA], m1[NB], x0[NA], x1[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+        if (i < na) {
+            m0[i] = r0[i * kLanes];
+            x0[i] = G.B[va + i * kLanes] - m0[i];
+        }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (j < nb) {
+            m1[j] = r1[j * kLanes];
+            x1[j] = G.B[vb + j * kLanes] - m1[j];
+        }
+    const float *ph = G.phi + ft.phi_off + lane;
+    float p[NA][NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (i < na && j < nb) p[i][j] = ph[(i * nb + j) * kLanes];
+    float u0[NA], u1[NB];
+    // to slot 0
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+        if (i < na) {
+            float t[NB];
+            float M = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (j < nb) {
+                    t[j] = p[i][j] + x1[j];
+                    M = fmaxf(M, t[j]);
+                }
+            if (MAXP) {
+                u0[i] = M;
+            } else {
+                float s = 0.0f;
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    if (j < nb) s += fexp2((t[j] - M) * P.c);
+                u0[i] = M + flog2(s) * P.r;
+            }
+        }
+    // to slot 1
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (j < nb) {
+            float t[NA];
+            float M = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+                if (i < na) {
+                    t[i] = p[i][j] + x0[i];
+                    M = fmaxf(M, t[i]);
+                }
+            if (MAXP) {
+                u1[j] = M;
+            } else {
+                float s = 0.0f;
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+                    if (i < na) s += fexp2((t[i] - M) * P.c);
+                u1[j] = M + flog2(s) * P.r;
+            }
+        }
+    damp_store<NA>(r0, m0, u0, na, P);
+    damp_store<NB>(r1, m1, u1, nb, P);
+}
+
+template <int NA, int NB, bool EXACT, bool MAXP>
+__global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                              int nitems, TParams P) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    pair_tile<NA, NB, EXACT, MAXP>(G, ft, lane_id(), P);
+}
+
+// --------------------------------------------------------------------------
+// factor phase: OR / AND, closed forms (PGMax Sec. "Package features":
+// logical factors with updates linear in their arity)
+// --------------------------------------------------------------------------
+// With delta_j = n[j,1] - n[j,0] (negated for AND, De Morgan), parents j < p,
+// child p:
+//   T = 0: S_-i = sum_{j != i} relu(delta_j), M_-i = max_{j != i} delta_j
+//          child  u = (0, S + min(0, max_j delta_j))
+//          parent u = (max(0, delta_c + S_-i + min(0, M_-i)), delta_c + S_-i)
+//   T > 0: A_-i = sum_{j != i} sp_T(delta_j)
+//          child  u = (0, lem_T(A))
+//          parent u = (sp_T(delta_c + lem_T(A_-i)), delta_c + A_-i)
+// The leave-one-out sums are exclusive prefix + suffix sums, never total minus
+// own term.  For AND the two entries of u are swapped.
+
+// one lane per factor, at most kLogLaneArityMax edges
+template <bool MAXP>
+__global__ __launch_bounds__(256) void k_logl(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                              int nitems, TParams P) {
+    constexpr int K = kLogLaneArityMax;
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const int lane = lane_id();
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    const int k = ft.a, p = k - 1;
+    const bool flip = ft.b != 0;
+    float *rows = G.m + ft.m_off + lane;
+    float m0[K], m1[K], dl[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < k) {
+            m0[j] = rows[(2 * j) * kLanes];
+            m1[j] = rows[(2 * j + 1) * kLanes];
+            const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
+            const float n0 = G.B[vb] - m0[j];
+            const float n1 = G.B[vb + kLanes] - m1[j];
+            dl[j] = flip ? (n0 - n1) : (n1 - n0);
+        }
+    float dc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j == p) dc = dl[j];
+    float t[K], pre[K], suf[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < p) t[j] = MAXP ? fmaxf(dl[j], 0.0f) : softplus_t(dl[j], P);
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < p) {
+            pre[j] = acc;
+            acc += t[j];
+        }
+    const float total = acc;
+    acc = 0.0f;
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j)
+        if (j < p) {
+            suf[j] = acc;
+            acc += t[j];
+        }
+    float max1 = -INFINITY, max2 = -INFINITY;
+    int amax = 0;
+    if (MAXP) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < p && dl[j] > max1) {
+                max1 = dl[j];
+                amax = j;
+            }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < p && j != amax) max2 = fmaxf(max2, dl[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < k) {
+            float a0, a1;
+            if (j == p) {
+                a0 = 0.0f;
+                a1 = MAXP ? total + fminf(0.0f, max1) : lem_t(total, P);
+            } else {
+                const float loo = pre[j] + suf[j];
+                a1 = dc + loo;
+                if (MAXP) {
+                    const float mo = (j == amax) ? max2 : max1;
+                    a0 = fmaxf(0.0f, dc + loo + fminf(0.0f, mo));
+                } else {
+                    a0 = softplus_t(dc + lem_t(loo, P), P);
+                }
+            }
+            const float u0 = flip ? a1 : a0, u1 = flip ? a0 : a1;
+            const float w0 = P.d * m0[j] + P.omd * u0, w1 = P.d * m1[j] + P.omd * u1;
+            const float mx = fmaxf(w0, w1);
+            rows[(2 * j) * kLanes] = w0 - mx;
+            rows[(2 * j + 1) * kLanes] = w1 - mx;
+        }
+}
+
+// one wavefront per factor; edge j sits in chunk j/64 at lane j%64
+template <int CH, bool MAXP>
+__global__ __launch_bounds__(256) void k_logw(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                              int nitems, TParams P) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const int lane = lane_id();
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    const int k = ft.a, p = k - 1;
+    const int nch = (k + kLanes - 1) / kLanes;
+    const bool flip = ft.b != 0;
+    float m0[CH], m1[CH], dl[CH], t[CH], pre[CH], suf[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int j = c * kLanes + lane;
+        dl[c] = 0.0f;
+        t[c] = 0.0f;
+        if (c < nch && j < k) {
+            float *row = G.m + ft.m_off + c * 2 * kLanes + lane;
+            m0[c] = row[0];
+            m1[c] = row[kLanes];
+            const int vb = G.fvb[ft.vb_off + j];
+            const float n0 = G.B[vb] - m0[c];
+            const float n1 = G.B[vb + kLanes] - m1[c];
+            dl[c] = flip ? (n0 - n1) : (n1 - n0);
+            if (j < p) t[c] = MAXP ? fmaxf(dl[c], 0.0f) : softplus_t(dl[c], P);
+        }
+    }
+    // child delta
+    float dc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+        if (c == p / kLanes) dc = __shfl(dl[c], p % kLanes, 64);
+    // exclusive prefix sums over parents, chunk-major
+    float carry = 0.0f;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+        if (c < nch) {
+            float x = t[c];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const float y = __shfl_up(x, off, 64);
+                if (lane >= off) x += y;
+            }
+            float ex = __shfl_up(x, 1, 64);
+            if (lane == 0) ex = 0.0f;
+            pre[c] = carry + ex;
+            carry += __shfl(x, 63, 64);
+        }
+    const float total = carry;
+    // exclusive suffix sums
+    carry = 0.0f;
+#pragma unroll
+    for (int c = CH - 1; c >= 0; --c)
+        if (c < nch) {
+            float x = t[c];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const float y = __shfl_down(x, off, 64);
+                if (lane + off < 64) x += y;
+            }
+            float ex = __shfl_down(x, 1, 64);
+            if (lane == 63) ex = 0.0f;
+            suf[c] = carry + ex;
+            carry += __shfl(x, 0, 64);
+        }
+    float max1 = -INFINITY, max2 = -INFINITY;
+    int amax = 0x7fffffff;
+    if (MAXP) {
+        // largest parent delta, lowest index on ties
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int j = c * kLanes + lane;
+            if (c < nch && j < p && (dl[c] > max1 || (dl[c] == max1 && j < amax))) {
+                max1 = dl[c];
+                amax = j;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float ov = __shfl_xor(max1, off, 64);
+            const int oi = __shfl_xor(amax, off, 64);
+            if (ov > max1 || (ov == max1 && oi < amax)) {
+                max1 = ov;
+                amax = oi;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int j = c * kLanes + lane;
+            if (c < nch && j < p && j != amax) max2 = fmaxf(max2, dl[c]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) max2 = fmaxf(max2, __shfl_xor(max2, off, 64));
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int j = c * kLanes + lane;
+        if (c < nch && j < k) {
+            float a0, a1;
+            if (j == p) {
+                a0 = 0.0f;
+                a1 = MAXP ? total + fminf(0.0f, max1) : lem_t(total, P);
+            } else {
+                const float loo = pre[c] + suf[c];
+                a1 = dc + loo;
+                if (MAXP) {
+                    const float mo = (j == amax) ? max2 : max1;
+                    a0 = fmaxf(0.0f, dc + loo + fminf(0.0f, mo));
+                } else {
+                    a0 = softplus_t(dc + lem_t(loo, P), P);
+                }
+            }
+            const float u0 = flip ? a1 : a0, u1 = flip ? a0 : a1;
+            const float w0 = P.d * m0[c] + P.omd * u0, w1 = P.d * m1[c] + P.omd * u1;
+            const float mx = fmaxf(w0, w1);
+            float *row = G.m + ft.m_off + c * 2 * kLanes + lane;
+            row[0] = w0 - mx;
+            row[kLanes] = w1 - mx;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// factor phase: generic enumeration factors (explicit configuration tables or
+// dense tables of arity != 2 / larger state counts).  One wavefront per
+// block, one lane per factor; the class's configuration table is staged in
+// LDS, incoming terms and per-(slot,state) accumulators live in LDS.
+// u[e_j,s] = LSE_T{score(c) : c_j = s} - n[e_j,s],  score(c) = phi(c) + sum_l n[e_l,c_l]
+// --------------------------------------------------------------------------
+template <bool MAXP>
+__global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                            int nitems, TParams P) {
+    __shared__ uint8_t rows[kGenCfgMax * kGenArityMax];
+    __shared__ float nv[kGenRowsMax][kLanes];
+    __shared__ float acc[kGenRowsMax][kLanes];
+    __shared__ float sacc[kGenRowsMax][kLanes];
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+    if (w >= nitems) return;
+    const int lane = lane_id();
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    const GenClass gc = G.gcls[ft.a];
+    const int A = gc.arity, C = gc.ncfg, R = gc.nrows;
+    for (int i = lane; i < C * A; i += kLanes) rows[i] = G.grows[gc.rows_off + i];
+    float *mrow = G.m + ft.m_off + lane;
+    for (int j = 0; j < A; ++j) {
+        const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
+        for (int s = 0; s < gc.slot_n[j]; ++s) {
+            const int r = gc.slot_row[j] + s;
+            nv[r][lane] = G.B[vb + s * kLanes] - mrow[r * kLanes];
+            acc[r][lane] = -INFINITY;
+            sacc[r][lane] = 0.0f;
+        }
+    }
+    __syncthreads();
+    const float *ph = G.phi + ft.phi_off + lane;
+    for (int c = 0; c < C; ++c) {
+        float sc = ph[c * kLanes];
+        for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j]][lane];
+        for (int j = 0; j < A; ++j) {
+            const int r = rows[c * A + j];
+            acc[r][lane] = fmaxf(acc[r][lane], sc);
+        }
+    }
+    if (!MAXP) {
+        for (int c = 0; c < C; ++c) {
+            float sc = ph[c * kLanes];
+            for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j]][lane];
+            for (int j = 0; j < A; ++j) {
+                const int r = rows[c * A + j];
+                sacc[r][lane] += fexp2((sc - acc[r][lane]) * P.c);
+            }
+        }
+    }
+    for (int j = 0; j < A; ++j) {
+        const int r0 = gc.slot_row[j], n = gc.slot_n[j];
+        float mx = -INFINITY;
+        for (int s = 0; s < n; ++s) {
+            const int r = r0 + s;
+            const float lse = MAXP ? acc[r][lane] : acc[r][lane] + flog2(sacc[r][lane]) * P.r;
+            const float u = lse - nv[r][lane];
+            const float mn = P.d * mrow[r * kLanes] + P.omd * u;
+            sacc[r][lane] = mn;  // reuse as staging for the normalisation
+            mx = fmaxf(mx, mn);
+        }
+        for (int s = 0; s < n; ++s) {
+            const int r = r0 + s;
+            mrow[r * kLanes] = sacc[r][lane] - mx;
+        }
+    }
+    (void)R;
+}
+
+// --------------------------------------------------------------------------
+// read-out and flat-order exchange
+// --------------------------------------------------------------------------
+// q[v,s] = B[v,s] - LSE_T(B[v,:]) (or B), MAP = lowest-index argmax.
+template <bool MAXP>
+__global__ __launch_bounds__(256) void k_readout(const DevGraph *__restrict__ gs, int ntiles, TParams P,
+                                                 float *__restrict__ qout, int normalized,
+                                                 int32_t *__restrict__ mapout) {
+    const int w = wave_index(4);
+    if (w >= ntiles) return;
+    const int lane = lane_id();
+    const DevGraph &G = gs[0];
+    const int v = w * kLanes + lane;
+    if (v >= G.V) return;
+    const VTile vt = G.vtile[w];
+    const int n = G.vn[v];
+    const float *b = G.B + vt.b_off + lane;
+    float M = -INFINITY;
+    int best = 0;
+    bool finite = true;
+    for (int s = 0; s < n; ++s) {
+        const float x = b[s * kLanes];
+        finite = finite && isfinite(x);
+        if (x > M) {
+            M = x;
+            best = s;
+        }
+    }
+    if (!finite) G.flag[0] = 1;
+    if (mapout) mapout[v] = best;
+    if (qout) {
+        float z = 0.0f;
+        if (normalized) {
+            if (MAXP) {
+                z = M;
+            } else {
+                float s = 0.0f;
+                for (int t = 0; t < n; ++t) s += fexp2((b[t * kLanes] - M) * P.c);
+                z = M + flog2(s) * P.r;
+            }
+        }
+        float *q = qout + G.vs_off[v];
+        for (int s = 0; s < n; ++s) q[s] = b[s * kLanes] - z;
+    }
+}
+
+__global__ void k_msgs_out(const DevGraph *__restrict__ gs, float *__restrict__ out) {
+    const DevGraph &G = gs[0];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= G.E) return;
+    const float *row = G.m + G.edge_maddr[e];
+    const int64_t o = G.es_off[e];
+    const int n = (int)(G.es_off[e + 1] - o);
+    for (int s = 0; s < n; ++s) out[o + s] = row[s * kLanes];
+}
+
+__global__ void k_msgs_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
+    const DevGraph &G = gs[0];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= G.E) return;
+    float *row = G.m + G.edge_maddr[e];
+    const int64_t o = G.es_off[e];
+    const int n = (int)(G.es_off[e + 1] - o);
+    for (int s = 0; s < n; ++s) row[s * kLanes] = in[o + s];
+}
+
+__global__ void k_evidence_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
+    const DevGraph &G = gs[0];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= G.V) return;
+    float *row = G.theta + G.vtile[v / kLanes].b_off + (v % kLanes);
+    const int64_t o = G.vs_off[v];
+    for (int s = 0; s < G.vn[v]; ++s) row[s * kLanes] = in[o + s];
+}
+
+__global__ void k_logpot_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
+    const DevGraph &G = gs[0];
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= G.F) return;
+    const int base = G.fac_phi[f];
+    if (base < 0) return;
+    const int64_t o = G.lp_off[f];
+    const int n = (int)(G.lp_off[f + 1] - o);
+    for (int c = 0; c < n; ++c) G.phi[base + c * kLanes] = in[o + c];
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+hipError_t launch_belief_low(const DevGraph *gs, const WorkItem *items, int n, int bucket, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid(blocks_for(n, 4)), block(256);
+    switch (bucket) {
+    case 2: hipLaunchKernelGGL((k_belief_low<2>), grid, block, 0, st, gs, items, n); break;
+    case 4: hipLaunchKernelGGL((k_belief_low<4>), grid, block, 0, st, gs, items, n); break;
+    case 8: hipLaunchKernelGGL((k_belief_low<8>), grid, block, 0, st, gs, items, n); break;
+    default: hipLaunchKernelGGL((k_belief_low<16>), grid, block, 0, st, gs, items, n); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_belief_high(const DevGraph *gs, const WorkItem *items, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_belief_high, dim3(blocks_for(n, 4)), dim3(256), 0, st, gs, items, n);
+    return hipGetLastError();
+}
+
+template <bool MAXP>
+static void pair_dispatch(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, const TParams &P,
+                          hipStream_t st) {
+    dim3 grid(blocks_for(n, 4)), block(256);
+    if (na == nb) {
+        switch (na) {
+        case 2: hipLaunchKernelGGL((k_pair<2, 2, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        case 3: hipLaunchKernelGGL((k_pair<3, 3, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        case 4: hipLaunchKernelGGL((k_pair<4, 4, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        case 5: hipLaunchKernelGGL((k_pair<5, 5, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        case 6: hipLaunchKernelGGL((k_pair<6, 6, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        case 7: hipLaunchKernelGGL((k_pair<7, 7, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        case 8: hipLaunchKernelGGL((k_pair<8, 8, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        default: break;
+        }
+    }
+    hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP>), grid, block, 0, st, gs, items, n, P);
+}
+
+hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
+                       const TParams &P, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (maxp) pair_dispatch<true>(gs, items, n, na, nb, P, st);
+    else pair_dispatch<false>(gs, items, n, na, nb, P, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_logl(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
+                       hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid(blocks_for(n, 4)), block(256);
+    if (maxp) hipLaunchKernelGGL((k_logl<true>), grid, block, 0, st, gs, items, n, P);
+    else hipLaunchKernelGGL((k_logl<false>), grid, block, 0, st, gs, items, n, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_logw(const DevGraph *gs, const WorkItem *items, int n, int chunk_bucket, bool maxp,
+                       const TParams &P, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid(blocks_for(n, 4)), block(256);
+#define LOGW_CASE(CHV)                                                                          \
+    if (maxp) hipLaunchKernelGGL((k_logw<CHV, true>), grid, block, 0, st, gs, items, n, P);    \
+    else hipLaunchKernelGGL((k_logw<CHV, false>), grid, block, 0, st, gs, items, n, P);
+    if (chunk_bucket <= 1) {
+        LOGW_CASE(1)
+    } else if (chunk_bucket <= 4) {
+        LOGW_CASE(4)
+    } else {
+        LOGW_CASE(16)
+    }
+#undef LOGW_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
+                      hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (maxp) hipLaunchKernelGGL((k_gen<true>), dim3(n), dim3(64), 0, st, gs, items, n, P);
+    else hipLaunchKernelGGL((k_gen<false>), dim3(n), dim3(64), 0, st, gs, items, n, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout(const DevGraph *gs, int nvtiles, bool maxp, const TParams &P, float *q, int normalized,
+                          int32_t *map, hipStream_t st) {
+    if (nvtiles <= 0) return hipSuccess;
+    dim3 grid(blocks_for(nvtiles, 4)), block(256);
+    if (maxp) hipLaunchKernelGGL((k_readout<true>), grid, block, 0, st, gs, nvtiles, P, q, normalized, map);
+    else hipLaunchKernelGGL((k_readout<false>), grid, block, 0, st, gs, nvtiles, P, q, normalized, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_msgs_out(const DevGraph *gs, int E, float *out, hipStream_t st) {
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_msgs_out, dim3(blocks_for(E, 256)), dim3(256), 0, st, gs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_msgs_in(const DevGraph *gs, int E, const float *in, hipStream_t st) {
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_msgs_in, dim3(blocks_for(E, 256)), dim3(256), 0, st, gs, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStream_t st) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_evidence_in, dim3(blocks_for(V, 256)), dim3(256), 0, st, gs, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_logpot_in(const DevGraph *gs, int F, const float *in, hipStream_t st) {
+    if (F <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_logpot_in, dim3(blocks_for(F, 256)), dim3(256), 0, st, gs, in);
+    return hipGetLastError();
+}
+
+TParams make_params(float damping, float temperature) {
+    TParams P;
+    P.d = damping;
+    P.omd = 1.0f - damping;
+    P.T = temperature;
+    if (temperature > 0.0f) {
+        P.invT = 1.0f / temperature;
+        P.c = (float)(1.4426950408889634 / (double)temperature);  // log2(e) / T
+        P.r = (float)((double)temperature * 0.6931471805599453);  // T ln 2
+    } else {
+        P.invT = 0.0f;
+        P.c = 0.0f;
+        P.r = 0.0f;
+    }
+    return P;
+}
+
+}  // namespace lbp

@@ -1,0 +1,287 @@
+"""Python binding of liblbp.so (include/lbp.h): argument marshalling only.
+
+Every step of belief propagation runs in the library's HIP kernels; this
+module converts numpy arrays / torch tensors to pointers and error codes to
+exceptions.  torch supplies device memory and the HIP stream: a Context uses
+``torch.cuda.current_stream()`` unless told otherwise, so library work is
+ordered with torch work on that stream.
+
+Importing this module loads the library and fails loudly if it is missing;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbp.so")
+
+LBP_OK, LBP_E_INVALID, LBP_E_OOM, LBP_E_HIP, LBP_E_STATE, LBP_E_BUDGET, LBP_E_NONFINITE, \
+    LBP_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+ERROR_NAMES = {0: "LBP_OK", -1: "LBP_E_INVALID", -2: "LBP_E_OOM", -3: "LBP_E_HIP", -4: "LBP_E_STATE",
+               -5: "LBP_E_BUDGET", -6: "LBP_E_NONFINITE", -7: "LBP_E_UNSUPPORTED"}
+
+
+class LBPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERROR_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("liblbp.so is not built (%s); run python -m paper_2202_04110_amd.build" % LIB_PATH)
+
+_lib = C.CDLL(LIB_PATH)
+_P = C.c_void_p
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [
+        ("num_vars", C.c_int32), ("var_num_states", _P), ("evidence", _P),
+        ("num_factors", C.c_int32), ("factor_kind", _P), ("factor_edge_off", _P), ("edge_var", _P),
+        ("factor_cfg_table", _P), ("num_cfg_tables", C.c_int32), ("cfg_table_num_cfgs", _P),
+        ("cfg_table_arity", _P), ("cfg_table_off", _P), ("cfg_table_states", _P),
+        ("logpot_off", _P), ("log_potentials", _P),
+    ]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("lbp_last_error", C.c_char_p, [])
+_sig("lbp_validate", C.c_int, [C.POINTER(GraphDesc), _P])
+_sig("lbp_check_layout", C.c_int, [C.POINTER(GraphDesc), _P])
+_sig("lbp_ctx_create", C.c_int, [C.c_int, _P, C.POINTER(_P)])
+_sig("lbp_ctx_set_stream", C.c_int, [_P, _P])
+_sig("lbp_ctx_synchronize", C.c_int, [_P])
+_sig("lbp_ctx_destroy", None, [_P])
+_sig("lbp_graph_upload", C.c_int, [_P, C.POINTER(GraphDesc), C.POINTER(_P)])
+_sig("lbp_graph_free", None, [_P])
+_sig("lbp_graph_sizes", C.c_int, [_P, _P])
+_sig("lbp_set_evidence", C.c_int, [_P, _P, C.c_int])
+_sig("lbp_set_log_potentials", C.c_int, [_P, _P, C.c_int])
+_sig("lbp_reset_messages", C.c_int, [_P])
+_sig("lbp_run_bp", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
+_sig("lbp_get_beliefs", C.c_int, [_P, _P, C.c_int, C.c_int])
+_sig("lbp_decode_map", C.c_int, [_P, _P, C.c_int])
+_sig("lbp_graph_status", C.c_int, [_P])
+_sig("lbp_get_messages", C.c_int, [_P, _P, C.c_int])
+_sig("lbp_set_messages", C.c_int, [_P, _P, C.c_int])
+_sig("lbp_batch_create", C.c_int, [_P, _P, C.c_int32, C.POINTER(_P)])
+_sig("lbp_batch_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
+_sig("lbp_batch_free", None, [_P])
+_sig("lbp_time_phase", C.c_int, [_P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.POINTER(C.c_float)])
+
+EXPORTS = [n for n in dir(_lib) if n.startswith("lbp_")]
+
+
+def last_error() -> str:
+    return (_lib.lbp_last_error() or b"").decode()
+
+
+def check(rc):
+    if rc != LBP_OK:
+        raise LBPError(rc, last_error())
+    return rc
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(_P)
+    return C.c_void_p(a.data_ptr())  # torch tensor
+
+
+def make_desc(spec):
+    """lbp_graph_desc over a GraphSpec's arrays; returns (desc, keep-alive list)."""
+    keep = [
+        np.ascontiguousarray(spec.var_num_states, np.int32),
+        np.ascontiguousarray(spec.evidence, np.float32),
+        np.ascontiguousarray(spec.factor_kind, np.int32),
+        np.ascontiguousarray(spec.factor_edge_off, np.int64),
+        np.ascontiguousarray(spec.edge_var, np.int32),
+        np.ascontiguousarray(spec.factor_cfg_table, np.int32),
+        np.ascontiguousarray(spec.cfg_table_num_cfgs, np.int32),
+        np.ascontiguousarray(spec.cfg_table_arity, np.int32),
+        np.ascontiguousarray(spec.cfg_table_off, np.int64),
+        np.ascontiguousarray(spec.cfg_table_states, np.int32),
+        np.ascontiguousarray(spec.logpot_off, np.int64),
+        np.ascontiguousarray(spec.log_potentials, np.float32),
+    ]
+    d = GraphDesc()
+    d.num_vars = keep[0].shape[0]
+    d.var_num_states = _ptr(keep[0])
+    d.evidence = _ptr(keep[1])
+    d.num_factors = keep[2].shape[0]
+    d.factor_kind = _ptr(keep[2])
+    d.factor_edge_off = _ptr(keep[3])
+    d.edge_var = _ptr(keep[4])
+    d.factor_cfg_table = _ptr(keep[5])
+    d.num_cfg_tables = keep[6].shape[0]
+    d.cfg_table_num_cfgs = _ptr(keep[6])
+    d.cfg_table_arity = _ptr(keep[7])
+    d.cfg_table_off = _ptr(keep[8])
+    d.cfg_table_states = _ptr(keep[9])
+    d.logpot_off = _ptr(keep[10])
+    d.log_potentials = _ptr(keep[11])
+    return d, keep
+
+
+def validate(spec) -> dict:
+    """Host-only validation (no GPU needed). Returns the sizes."""
+    d, keep = make_desc(spec)
+    sizes = np.zeros(6, np.int64)
+    check(_lib.lbp_validate(C.byref(d), _ptr(sizes)))
+    return dict(zip(("V", "VS", "F", "E", "ES", "Tn"), (int(x) for x in sizes)))
+
+
+def check_layout(spec) -> dict:
+    """Host-only replay of every kernel's addresses against the layout."""
+    d, keep = make_desc(spec)
+    info = np.zeros(4, np.int64)
+    check(_lib.lbp_check_layout(C.byref(d), _ptr(info)))
+    return dict(zip(("M", "VB", "P", "tiles"), (int(x) for x in info)))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Context:
+    """A device and a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        torch.cuda.set_device(device)
+        h = _P()
+        check(_lib.lbp_ctx_create(device, _stream_handle(stream), C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def set_stream(self, stream):
+        check(_lib.lbp_ctx_set_stream(self.h, _stream_handle(stream)))
+
+    def synchronize(self):
+        check(_lib.lbp_ctx_synchronize(self.h))
+
+    def close(self):
+        if self.h:
+            _lib.lbp_ctx_destroy(self.h)
+            self.h = None
+
+
+def _is_dev(x):
+    return x is not None and not isinstance(x, np.ndarray)
+
+
+class Graph:
+    """A factor graph uploaded to the device; messages persist across runs."""
+
+    def __init__(self, ctx: Context, spec):
+        d, keep = make_desc(spec)
+        h = _P()
+        check(_lib.lbp_graph_upload(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        s = np.zeros(8, np.int64)
+        check(_lib.lbp_graph_sizes(h, _ptr(s)))
+        (self.V, self.VS, self.F, self.E, self.ES, self.Tn, self.device_bytes,
+         self.padded_edge_states) = (int(x) for x in s)
+
+    def free(self):
+        if getattr(self, "h", None):
+            _lib.lbp_graph_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def run_bp(self, iters: int, damping: float, temperature: float):
+        check(_lib.lbp_run_bp(self.h, int(iters), float(damping), float(temperature)))
+
+    def reset_messages(self):
+        check(_lib.lbp_reset_messages(self.h))
+
+    def get_beliefs(self, normalized: bool = True, out=None):
+        """Host numpy array (synchronous) unless ``out`` is a device tensor."""
+        if out is None:
+            out = np.zeros(self.VS, np.float32)
+        check(_lib.lbp_get_beliefs(self.h, _ptr(out), int(bool(normalized)), int(_is_dev(out))))
+        return out
+
+    def decode_map(self, out=None):
+        if out is None:
+            out = np.zeros(self.V, np.int32)
+        check(_lib.lbp_decode_map(self.h, _ptr(out), int(_is_dev(out))))
+        return out
+
+    def status(self):
+        check(_lib.lbp_graph_status(self.h))
+
+    def get_messages(self, out=None):
+        if out is None:
+            out = np.zeros(self.ES, np.float32)
+        check(_lib.lbp_get_messages(self.h, _ptr(out), int(_is_dev(out))))
+        return out
+
+    def set_messages(self, values):
+        if not _is_dev(values):
+            values = np.ascontiguousarray(values, np.float32)
+        check(_lib.lbp_set_messages(self.h, _ptr(values), int(_is_dev(values))))
+
+    def set_evidence(self, values):
+        if not _is_dev(values):
+            values = np.ascontiguousarray(values, np.float32)
+        check(_lib.lbp_set_evidence(self.h, _ptr(values), int(_is_dev(values))))
+
+    def set_log_potentials(self, values):
+        if not _is_dev(values):
+            values = np.ascontiguousarray(values, np.float32)
+        check(_lib.lbp_set_log_potentials(self.h, _ptr(values), int(_is_dev(values))))
+
+    def time_phase(self, phase: int, reps: int, damping: float, temperature: float) -> float:
+        ms = C.c_float()
+        check(_lib.lbp_time_phase(self.h, int(phase), int(reps), float(damping), float(temperature),
+                                  C.byref(ms)))
+        return float(ms.value)
+
+
+class Batch:
+    """Graphs advanced together in shared launches (same bits as alone)."""
+
+    def __init__(self, ctx: Context, graphs):
+        self.graphs = list(graphs)
+        arr = (_P * max(1, len(self.graphs)))(*[g.h for g in self.graphs])
+        h = _P()
+        check(_lib.lbp_batch_create(ctx.h, arr, len(self.graphs), C.byref(h)))
+        self.h = h
+
+    def run_bp(self, iters: int, damping: float, temperature: float):
+        check(_lib.lbp_batch_run(self.h, int(iters), float(damping), float(temperature)))
+
+    def free(self):
+        if getattr(self, "h", None):
+            _lib.lbp_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

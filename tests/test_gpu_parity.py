@@ -1,0 +1,386 @@
+"""HIP path (through the C-ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (written here, derived in the design notes):
+* normalised log-beliefs q: 1e-4 absolute (FP32 path vs FP64 oracle);
+* one or a few iterations from an identical FP32 message state: 5e-5
+  absolute plus 1e-6 relative (about 16 FP32 ulps) on the messages; wide
+  OR/AND factors sum hundreds of terms into messages of magnitude ~500;
+* MAP: bit-exact on every variable whose oracle top-2 belief margin exceeds
+  2e-4 (twice the belief tolerance, so FP32 rounding cannot flip it); on the
+  rest the GPU's choice must be within 2e-4 of the oracle's best belief.
+* Loopy max-product need not converge.  When the oracle's last residual
+  exceeds 1e-6 the end state is reported, not asserted; the asserted gates are
+  then parity over the first iterations and one-step parity from the GPU's
+  own final state.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import OracleGraph
+from paper_2202_04110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_Q = 1e-4
+TOL_STEP = 5e-5
+RTOL_STEP = 1e-6
+MARGIN = 2e-4
+NT = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def lbp(gpu_lib):
+    return gpu_lib
+
+
+@pytest.fixture(scope="module")
+def ctx(lbp):
+    return lbp.Context(0)
+
+
+def _qmat(spec, q):
+    """list of per-variable arrays"""
+    off = spec.var_state_off()
+    return [q[off[v]:off[v + 1]] for v in range(spec.num_vars)]
+
+
+def check_map(spec, q_or, map_or, map_gpu):
+    rows = _qmat(spec, q_or)
+    bad_sure, near = [], 0
+    for v, r in enumerate(rows):
+        srt = np.sort(r)
+        margin = srt[-1] - srt[-2]
+        if margin > MARGIN:
+            if map_gpu[v] != map_or[v]:
+                bad_sure.append(v)
+        else:
+            near += 1
+            assert r[map_gpu[v]] >= r.max() - MARGIN, (v, r, map_gpu[v])
+    assert not bad_sure, "MAP differs on %d clear-margin variables, e.g. %s" % (len(bad_sure), bad_sure[:5])
+    return near
+
+
+def random_state(og, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(0, scale, og.ES)).astype(np.float32)
+
+
+def step_parity(lbp, ctx, spec, T, d=0.5, steps=1, seed=0, tol=TOL_STEP):
+    g = lbp.Graph(ctx, spec)
+    og = OracleGraph(spec)
+    m0 = random_state(og, seed)
+    g.set_messages(m0)
+    g.run_bp(steps, d, T)
+    mg = g.get_messages()
+    mo = og.run(steps, d, T, m0=m0.astype(np.float64), threads=NT)
+    err = np.abs(mg - mo).max() if mg.size else 0.0
+    excess = (np.abs(mg - mo) - RTOL_STEP * np.abs(mo)).max() if mg.size else 0.0
+    print("%s T=%g steps=%d: max |m_gpu - m_oracle| = %.3g (max |m| %.3g)" %
+          (spec.name, T, steps, err, np.abs(mo).max() if mg.size else 0.0))
+    assert excess <= tol, (err, excess)
+    # every message row has max exactly 0
+    off = spec.edge_state_off()
+    if spec.num_edges:
+        mx = np.maximum.reduceat(mg, off[:-1])
+        assert np.all(mx == 0.0)
+    g.free()
+    return err
+
+
+# --------------------------------------------------------------- shapes
+def mixed_graph(seed, **kw):
+    return W.random_factor_graph(seed, num_vars=kw.pop("num_vars", 150), tree=False,
+                                 extra_factors=kw.pop("extra", 120), max_arity=kw.pop("max_arity", 3),
+                                 logical_frac=kw.pop("logical_frac", 0.25), explicit_frac=0.4,
+                                 max_states=kw.pop("max_states", 4), name="mixed%d" % seed, **kw)
+
+
+def big_logical(seed, parents=150, nfac=5, kind=W.OR):
+    """several wide OR/AND factors sharing parents (wave-per-factor path)"""
+    rng = np.random.default_rng(seed)
+    V = parents + nfac
+    ev = rng.normal(0, 1.5, V * 2).astype(np.float32)
+    facs = []
+    for f in range(nfac):
+        par = list(rng.choice(parents, size=int(rng.integers(9, parents)), replace=False))
+        facs.append({"kind": kind if f % 2 == 0 else (W.AND if kind == W.OR else W.OR),
+                     "vars": par + [parents + f]})
+    return W._general_graph(np.full(V, 2, np.int32), ev, facs, "biglogic%d" % seed)
+
+
+def star(seed, deg=300, n=3):
+    """one hub variable with many pairwise factors (wave-per-variable path)"""
+    rng = np.random.default_rng(seed)
+    V = deg + 1
+    ev = rng.normal(0, 1, V * n).astype(np.float32)
+    pairs = np.stack([np.zeros(deg, np.int64), np.arange(1, deg + 1)], 1)
+    tab = rng.normal(0, 0.3, (deg, n * n))
+    return W._pairwise_graph(np.full(V, n, np.int32), ev, pairs, tab, "star%d" % deg)
+
+
+def rect_pairs(seed, na=3, nb=5, F=200):
+    rng = np.random.default_rng(seed)
+    V = 2 * F
+    ns = np.array([na, nb] * F, np.int32)
+    ev = rng.normal(0, 1, int(ns.sum())).astype(np.float32)
+    # chain-like: factor f joins var 2f (na states) and 2f+1 (nb states); plus links
+    pairs = [(2 * f, 2 * f + 1) for f in range(F)] + [(2 * f, 2 * f + 3) for f in range(F - 1)]
+    facs = [{"kind": W.ENUM, "vars": list(p), "logpot": rng.normal(0, 0.7, ns[p[0]] * ns[p[1]])}
+            for p in pairs]
+    return W._general_graph(ns, ev, facs, "rect%dx%d" % (na, nb))
+
+
+def wide_states(seed, n=16, L=6):
+    g = W.potts_grid(L, n, seed=seed)
+    g.name = "potts%dx%d" % (L, n)
+    return g
+
+
+STEP_CASES = [
+    ("ising32", lambda: W.ising_grid(32, 1), [0.0, 1.0]),
+    ("potts40x5", lambda: W.potts_grid(40, 5, 2), [1.0, 0.0]),
+    ("potts20x3", lambda: W.potts_grid(20, 3, 3), [0.3]),
+    ("potts12x8", lambda: W.potts_grid(12, 8, 4), [1.0, 0.0]),
+    ("rbm40x30", lambda: W.rbm(40, 30, 3), [0.0, 0.05]),
+    ("rbm100x90", lambda: W.rbm(100, 90, 5), [0.0]),
+    ("deconv_small", lambda: W.deconv(seed=4, K=2, tw=4, sd=10, img=12), [0.0, 0.5]),
+    ("mixed1", lambda: mixed_graph(1), [0.0, 0.7]),
+    ("mixed2", lambda: mixed_graph(2, max_arity=4, max_states=3), [0.0, 1.0]),
+    ("biglogic", lambda: big_logical(5, parents=150), [0.0, 0.3, 1.0]),
+    ("biglogic_wide", lambda: big_logical(6, parents=700, nfac=3), [0.0, 1.0]),
+    ("star300", lambda: star(7, 300, 3), [0.0, 1.0]),
+    ("rect3x5", lambda: rect_pairs(8, 3, 5), [0.0, 1.0]),
+    ("potts6x16", lambda: wide_states(9, 16, 6), [0.0, 1.0]),
+    ("potts4x30", lambda: wide_states(10, 30, 4), [1.0]),
+]
+
+
+@pytest.mark.parametrize("name,make,temps", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_single_step_parity(lbp, ctx, name, make, temps):
+    spec = make()
+    for T in temps:
+        for d in (0.5, 0.2):
+            step_parity(lbp, ctx, spec, T, d=d, steps=1, seed=int(T * 10) + int(d * 100))
+
+
+@pytest.mark.parametrize("name,make,temps", STEP_CASES[:8], ids=[c[0] for c in STEP_CASES[:8]])
+def test_three_step_parity(lbp, ctx, name, make, temps):
+    spec = make()
+    for T in temps:
+        step_parity(lbp, ctx, spec, T, steps=3, seed=5, tol=2e-4)
+
+
+# ----------------------------------------------------------- end to end
+def end_to_end(lbp, ctx, spec, iters, d, T, tol=TOL_Q):
+    og = OracleGraph(spec)
+    mo, res = og.run(iters, d, T, threads=NT, residuals=True)
+    _, qo, mapo = og.beliefs(mo, T)
+    g = lbp.Graph(ctx, spec)
+    g.run_bp(iters, d, T)
+    qg = g.get_beliefs()
+    mapg = g.decode_map()
+    err = float(np.abs(qg - qo).max()) if qg.size else 0.0
+    converged = (res[-1] if iters else 0.0) < 1e-6
+    print("%s T=%g iters=%d: oracle residual %.3g, max |q_gpu - q_oracle| = %.3g" %
+          (spec.name, T, iters, res[-1] if iters else 0.0, err))
+    out = {"err": err, "converged": converged, "g": g, "og": og, "resid": res}
+    if converged:
+        assert err <= tol, err
+        near = check_map(spec, qo, mapo, mapg)
+        print("  MAP: %d near-tie variables (margin <= %g), rest bit-exact" % (near, MARGIN))
+    return out
+
+
+def test_ising32_max_product(lbp, ctx):
+    """2-D Ising 32x32, max-product, damping 0.5, 100 iterations (FP32 vs FP64)."""
+    spec = W.ising_grid(32, 1)
+    r = end_to_end(lbp, ctx, spec, 100, 0.5, 0.0)
+    if not r["converged"]:
+        # frustrated loopy max-product: gate on the early iterations and on one
+        # step from the GPU's own final state
+        for it in (1, 10):
+            end_to_end(lbp, ctx, spec, it, 0.5, 0.0)
+        mg = r["g"].get_messages()
+        mo = r["og"].run(1, 0.5, 0.0, m0=mg.astype(np.float64))
+        r["g"].run_bp(1, 0.5, 0.0)
+        assert np.abs(r["g"].get_messages() - mo).max() <= TOL_STEP
+
+
+def test_potts_sum_product_converged(lbp, ctx):
+    """Potts 64x64x5 (the full-size generator at a side the oracle finishes
+    quickly), sum-product T=1, damping 0.5, 200 iterations."""
+    r = end_to_end(lbp, ctx, W.potts_grid(64, 5, 2), 200, 0.5, 1.0)
+    assert r["converged"]
+
+
+def test_potts_ragged_tail(lbp, ctx):
+    """Side 37: factor and variable counts are not multiples of 64."""
+    r = end_to_end(lbp, ctx, W.potts_grid(37, 4, 12), 150, 0.5, 1.0)
+    assert r["converged"]
+
+
+@pytest.mark.parametrize("T", [0.0, 0.05])
+def test_rbm(lbp, ctx, T):
+    """RBM factor graph (visible x hidden pairwise factors) at the full
+    784 x 500 shape, 200 iterations, damping 0.5."""
+    spec = W.rbm(784, 500, 3)
+    r = end_to_end(lbp, ctx, spec, 200, 0.5, T)
+    if not r["converged"]:
+        end_to_end(lbp, ctx, spec, 5, 0.5, T)
+
+
+def test_deconv_or_and(lbp, ctx):
+    """Binary deconvolution with OR/AND factors at the full shape, max-product,
+    damping 0.5, 1000 iterations."""
+    spec = W.deconv(seed=4)
+    r = end_to_end(lbp, ctx, spec, 1000, 0.5, 0.0)
+    if not r["converged"]:
+        for it in (1, 20):
+            end_to_end(lbp, ctx, spec, it, 0.5, 0.0)
+        mg = r["g"].get_messages()
+        mo = r["og"].run(1, 0.5, 0.0, m0=mg.astype(np.float64))
+        r["g"].run_bp(1, 0.5, 0.0)
+        assert np.abs(r["g"].get_messages() - mo).max() <= 2 * TOL_STEP
+
+
+def test_mixed_graph_end_to_end(lbp, ctx):
+    spec = mixed_graph(3, num_vars=300, extra=100, logical_frac=0.2)
+    end_to_end(lbp, ctx, spec, 100, 0.5, 1.0)
+
+
+def test_potts512_full_size(lbp, ctx):
+    """Potts 512x512x5 at full size: parity of the first iterations from zero
+    (every element), and the message-row invariant after 200 iterations."""
+    spec = W.potts_grid(512, 5, 2)
+    og = OracleGraph(spec)
+    g = lbp.Graph(ctx, spec)
+    g.run_bp(2, 0.5, 1.0)
+    mg = g.get_messages()
+    mo = og.run(2, 0.5, 1.0, threads=NT)
+    assert np.abs(mg - mo).max() <= TOL_STEP
+    _, qo, _ = og.beliefs(mo, 1.0)
+    assert np.abs(g.get_beliefs() - qo).max() <= TOL_Q
+    g.run_bp(198, 0.5, 1.0)
+    m = g.get_messages()
+    off = spec.edge_state_off()
+    assert np.all(np.maximum.reduceat(m, off[:-1]) == 0.0)
+    q = g.get_beliefs()
+    # normalised beliefs: logsumexp over each variable's states is 0
+    lse = np.log(np.exp(q.astype(np.float64)).reshape(-1, 5).sum(1))
+    assert np.abs(lse).max() < 1e-5
+    # one step from the GPU's final state matches the oracle
+    mo = og.run(1, 0.5, 1.0, m0=m.astype(np.float64), threads=NT)
+    g.run_bp(1, 0.5, 1.0)
+    assert np.abs(g.get_messages() - mo).max() <= TOL_STEP
+
+
+# ------------------------------------------------------- state semantics
+def test_warm_start_and_determinism(lbp, ctx):
+    spec = W.potts_grid(50, 4, 21)
+    a = lbp.Graph(ctx, spec)
+    a.run_bp(60, 0.5, 1.0)
+    b = lbp.Graph(ctx, spec)
+    b.run_bp(30, 0.5, 1.0)
+    b.run_bp(30, 0.5, 1.0)
+    np.testing.assert_array_equal(a.get_messages(), b.get_messages())
+    c = lbp.Graph(ctx, spec)
+    c.run_bp(60, 0.5, 1.0)
+    np.testing.assert_array_equal(a.get_beliefs(), c.get_beliefs())
+    c.reset_messages()
+    assert np.all(c.get_messages() == 0)
+
+
+def test_batch_matches_alone_bitwise(lbp, ctx):
+    specs = [W.potts_grid(17, 3, 31), W.potts_grid(40, 5, 32), W.ising_grid(9, 33), mixed_graph(34),
+             big_logical(35), W.rbm(30, 20, 36), W.potts_grid(23, 5, 37)]
+    for T in (0.0, 1.0):
+        alone = []
+        for s in specs:
+            g = lbp.Graph(ctx, s)
+            g.run_bp(25, 0.5, T)
+            alone.append((g.get_messages(), g.get_beliefs(), g.decode_map()))
+        gs = [lbp.Graph(ctx, s) for s in specs]
+        b = lbp.Batch(ctx, gs)
+        b.run_bp(25, 0.5, T)
+        for g, (m, q, mp) in zip(gs, alone):
+            np.testing.assert_array_equal(g.get_messages(), m)
+            np.testing.assert_array_equal(g.get_beliefs(), q)
+            np.testing.assert_array_equal(g.decode_map(), mp)
+        b.free()
+
+
+# ------------------------------------------------------------ edge cases
+def test_zero_iterations_and_isolated_variables(lbp, ctx):
+    spec = W.potts_grid(9, 3, 41)
+    g = lbp.Graph(ctx, spec)
+    g.run_bp(0, 0.5, 1.0)
+    og = OracleGraph(spec)
+    _, qo, mo = og.beliefs(og.zero_messages(), 1.0)
+    np.testing.assert_allclose(g.get_beliefs(), qo, atol=1e-6)
+    # variables without factors: beliefs are the normalised evidence
+    iso = W.disjoint_union([spec, W._general_graph(np.array([3, 5, 2], np.int32),
+                                                   np.arange(10, dtype=np.float32) * 0.3, [], "iso")])
+    g2 = lbp.Graph(ctx, iso)
+    g2.run_bp(10, 0.5, 1.0)
+    og2 = OracleGraph(iso)
+    _, qo2, _ = og2.beliefs(og2.run(10, 0.5, 1.0), 1.0)
+    np.testing.assert_allclose(g2.get_beliefs(), qo2, atol=TOL_Q)
+
+
+def test_empty_graph(lbp, ctx):
+    g = lbp.Graph(ctx, W.disjoint_union([]))
+    g.run_bp(5, 0.5, 1.0)
+    assert g.get_beliefs().size == 0 and g.decode_map().size == 0 and g.get_messages().size == 0
+
+
+def test_set_inputs_round_trip(lbp, ctx):
+    import torch
+    spec = W.potts_grid(20, 4, 51)
+    g = lbp.Graph(ctx, spec)
+    rng = np.random.default_rng(0)
+    spec2 = spec.copy()
+    spec2.evidence = rng.normal(0, 1, spec.evidence.shape).astype(np.float32)
+    spec2.log_potentials = rng.normal(0, 0.5, spec.log_potentials.shape).astype(np.float32)
+    g.set_evidence(spec2.evidence)
+    g.set_log_potentials(torch.from_numpy(spec2.log_potentials).cuda())
+    g.run_bp(80, 0.5, 1.0)
+    og = OracleGraph(spec2)
+    _, qo, _ = og.beliefs(og.run(80, 0.5, 1.0), 1.0)
+    assert np.abs(g.get_beliefs() - qo).max() <= TOL_Q
+    # device outputs
+    qd = torch.empty(g.VS, device="cuda", dtype=torch.float32)
+    g.get_beliefs(out=qd)
+    md = torch.empty(g.V, device="cuda", dtype=torch.int32)
+    g.decode_map(out=md)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(qd.cpu().numpy(), g.get_beliefs())
+    np.testing.assert_array_equal(md.cpu().numpy(), g.decode_map())
+
+
+def test_nonfinite_is_reported(lbp, ctx):
+    import torch
+    spec = W.potts_grid(8, 3, 61)
+    g = lbp.Graph(ctx, spec)
+    ev = torch.from_numpy(spec.evidence.copy())
+    ev[5] = float("nan")
+    g.set_evidence(ev.cuda())
+    g.run_bp(3, 0.5, 1.0)
+    with pytest.raises(lbp.LBPError) as ei:
+        g.get_beliefs()
+    assert ei.value.code == lbp.LBP_E_NONFINITE
+    g.set_evidence(spec.evidence)
+    g.reset_messages()
+    g.run_bp(3, 0.5, 1.0)
+    g.get_beliefs()  # clean again
+
+
+def test_argument_errors(lbp, ctx):
+    g = lbp.Graph(ctx, W.potts_grid(4, 2, 71))
+    for args in ((-1, 0.5, 1.0), (1, 1.5, 1.0), (1, -0.1, 0.0), (1, 0.5, -1.0), (1, 0.5, float("nan"))):
+        with pytest.raises(lbp.LBPError) as ei:
+            g.run_bp(*args)
+        assert ei.value.code == lbp.LBP_E_INVALID
+    with pytest.raises(lbp.LBPError):
+        g.set_evidence(np.full(g.VS, np.inf, np.float32))
