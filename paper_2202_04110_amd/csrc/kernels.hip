@@ -75,10 +75,12 @@ __device__ __forceinline__ void damp_store(float *row, const float (&mo)[N], con
 // --------------------------------------------------------------------------
 
 // One wavefront per variable tile, one lane per variable; NB >= states of
-// every low-degree lane of the tile.
+// every low-degree lane of the tile.  Edge rows are fetched KU at a time (all
+// address loads, then all message loads in flight) and added in edge order.
 template <int NB>
 __global__ __launch_bounds__(256) void k_belief_low(const DevGraph *__restrict__ gs,
                                                     const WorkItem *__restrict__ items, int nitems) {
+    constexpr int KU = NB <= 4 ? 8 : 4;
     const int w = wave_index(4);
     if (w >= nitems) return;
     const int lane = lane_id();
@@ -91,11 +93,20 @@ __global__ __launch_bounds__(256) void k_belief_low(const DevGraph *__restrict__
 #pragma unroll
     for (int s = 0; s < NB; ++s) acc[s] = (s < n) ? G.theta[base + s * kLanes] : 0.0f;
     const int32_t *ea = G.vedge + vt.e_off + lane;
-    for (int k = 0; k < vt.kmax; ++k) {
-        const float *row = G.m + ea[k * kLanes];
+    for (int k0 = 0; k0 < vt.kmax; k0 += KU) {
+        int a[KU];
 #pragma unroll
-        for (int s = 0; s < NB; ++s)
-            if (s < n) acc[s] += row[s * kLanes];
+        for (int u = 0; u < KU; ++u) a[u] = (k0 + u < vt.kmax) ? ea[(k0 + u) * kLanes] : -1;
+        float x[KU][NB];
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+            for (int s = 0; s < NB; ++s) x[u][s] = (a[u] >= 0 && s < n) ? G.m[a[u] + s * kLanes] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+            for (int s = 0; s < NB; ++s)
+                if (a[u] >= 0 && s < n) acc[s] += x[u][s];
     }
 #pragma unroll
     for (int s = 0; s < NB; ++s)

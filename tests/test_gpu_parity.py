@@ -3,8 +3,9 @@
 Tolerances (written here, derived in the design notes):
 * normalised log-beliefs q: 1e-4 absolute (FP32 path vs FP64 oracle);
 * one or a few iterations from an identical FP32 message state: 5e-5
-  absolute plus 1e-6 relative (about 16 FP32 ulps) on the messages; wide
-  OR/AND factors sum hundreds of terms into messages of magnitude ~500;
+  absolute plus 4 FP32 ulps (4 * 2^-23) of the largest message magnitude:
+  normalised messages are differences of unnormalised ones, and wide OR/AND
+  factors sum hundreds of terms into values of magnitude ~500;
 * MAP: bit-exact on every variable whose oracle top-2 belief margin exceeds
   2e-4 (twice the belief tolerance, so FP32 rounding cannot flip it); on the
   rest the GPU's choice must be within 2e-4 of the oracle's best belief.
@@ -25,7 +26,7 @@ pytestmark = pytest.mark.gpu
 
 TOL_Q = 1e-4
 TOL_STEP = 5e-5
-RTOL_STEP = 1e-6
+ULP32 = 2.0 ** -23
 MARGIN = 2e-4
 NT = max(1, min(16, os.cpu_count() or 1))
 
@@ -76,10 +77,9 @@ def step_parity(lbp, ctx, spec, T, d=0.5, steps=1, seed=0, tol=TOL_STEP):
     mg = g.get_messages()
     mo = og.run(steps, d, T, m0=m0.astype(np.float64), threads=NT)
     err = np.abs(mg - mo).max() if mg.size else 0.0
-    excess = (np.abs(mg - mo) - RTOL_STEP * np.abs(mo)).max() if mg.size else 0.0
-    print("%s T=%g steps=%d: max |m_gpu - m_oracle| = %.3g (max |m| %.3g)" %
-          (spec.name, T, steps, err, np.abs(mo).max() if mg.size else 0.0))
-    assert excess <= tol, (err, excess)
+    scale = float(np.abs(mo).max()) if mg.size else 0.0
+    print("%s T=%g steps=%d: max |m_gpu - m_oracle| = %.3g (max |m| %.3g)" % (spec.name, T, steps, err, scale))
+    assert err <= tol + 4 * ULP32 * scale, (err, scale)
     # every message row has max exactly 0
     off = spec.edge_state_off()
     if spec.num_edges:
