@@ -148,6 +148,11 @@ int lbp_check_layout(const lbp_graph_desc *desc, int64_t info_out[4]);
 int lbp_ctx_create(int device, void *hip_stream, lbp_ctx **out);
 /* Changes the stream used by later calls on this context. */
 int lbp_ctx_set_stream(lbp_ctx *ctx, void *hip_stream);
+/* Whether lbp_run_bp / lbp_batch_run replay fixed-iteration loops as
+ * captured HIP graphs (default on; the environment variable LBP_NO_GRAPHS=1
+ * turns the default off).  Captured and eager launches run the same kernels
+ * with the same arguments, so results are identical. */
+int lbp_ctx_use_graphs(lbp_ctx *ctx, int enable);
 /* Waits for all work queued on the context's stream. */
 int lbp_ctx_synchronize(lbp_ctx *ctx);
 /* Frees the context; every graph and batch made with it must be freed first. */
@@ -200,6 +205,29 @@ int lbp_graph_status(lbp_graph *g);
  * for starting several runs from one state. */
 int lbp_get_messages(lbp_graph *g, float *out, int on_device);
 int lbp_set_messages(lbp_graph *g, const float *values, int on_device);
+
+/*
+ * Differentiation through the solver (the paper's Sec. "Exciting new
+ * possibilities": LBP as part of an end-to-end differentiable system).
+ *
+ * lbp_run_bp_record runs like lbp_run_bp (from the current messages) and
+ * keeps a checkpoint of the messages every ckpt_every iterations.  It needs
+ * temperature > 0 (max-product is not differentiable) and a graph of
+ * enumeration factors only (LBP_E_UNSUPPORTED otherwise).  Device memory:
+ * about (iters/ckpt_every + ckpt_every + 2) message arrays, owned by the
+ * graph until it is freed.
+ *
+ * lbp_run_bp_backward computes, for the loss L = sum_{v,s} grad_q[v,s] q[v,s]
+ * with q the normalised beliefs after the recorded run, dL/dphi into
+ * grad_logpot (Tn floats, log_potentials order) and dL/dtheta into
+ * grad_evidence (VS floats, or NULL to skip).  All three are device pointers,
+ * used in stream order.  The derivative is that of the recorded unrolled
+ * iterations (reverse mode: each segment's iterates are recomputed from its
+ * checkpoint).  LBP_E_STATE if the graph's messages or inputs changed since
+ * the record.  The record stays valid, so backward may be called again.
+ */
+int lbp_run_bp_record(lbp_graph *g, int32_t iters, float damping, float temperature, int32_t ckpt_every);
+int lbp_run_bp_backward(lbp_graph *g, const float *grad_q, float *grad_logpot, float *grad_evidence);
 
 /*
  * Batches (the paper's Sec. "Exciting new possibilities": processing batches

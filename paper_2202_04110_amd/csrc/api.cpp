@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -87,8 +88,72 @@ hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, c
 
 struct lbp_ctx {
     int device;
-    hipStream_t stream;
+    hipStream_t stream;          // the caller's stream (borrowed)
+    hipStream_t capture = nullptr;  // private stream used only to record launch graphs
+    bool use_graphs = true;
 };
+
+namespace {
+
+// A captured fixed-iteration loop, replayed with hipGraphLaunch.
+struct CachedLoop {
+    int32_t iters;
+    float d, T;
+    hipGraphExec_t exec;
+};
+
+constexpr size_t kMaxCachedLoops = 4;
+
+void destroy_loops(std::vector<CachedLoop> &v) {
+    for (CachedLoop &c : v) (void)hipGraphExecDestroy(c.exec);
+    v.clear();
+}
+
+// Runs `iters` iterations on ctx->stream: through a cached captured graph
+// when enabled (the kernels and their arguments are the same as eager
+// launches), else by launching each kernel.
+hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const std::vector<Launch> &vl,
+                    const std::vector<Launch> &fl, int32_t iters, float d, float T) {
+    const TParams P = make_params(d, T);
+    const bool maxp = T == 0.0f;
+    const size_t per_iter = vl.size() + fl.size();
+    if (!ctx->use_graphs || iters < 2 || per_iter == 0) {
+        for (int32_t it = 0; it < iters; ++it) {
+            hipError_t e = launch_iteration(gs, vl, fl, P, maxp, ctx->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    for (const CachedLoop &c : cache)
+        if (c.iters == iters && c.d == d && c.T == T) return hipGraphLaunch(c.exec, ctx->stream);
+    if (!ctx->capture) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int32_t it = 0; it < iters && le == hipSuccess; ++it)
+        le = launch_iteration(gs, vl, fl, P, maxp, ctx->capture);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le != hipSuccess ? le : e;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (cache.size() >= kMaxCachedLoops) {
+        (void)hipGraphExecDestroy(cache.front().exec);
+        cache.erase(cache.begin());
+    }
+    cache.push_back(CachedLoop{iters, d, T, exec});
+    return hipGraphLaunch(exec, ctx->stream);
+}
+
+}  // namespace
 
 struct lbp_graph {
     lbp_ctx *ctx = nullptr;
@@ -103,9 +168,23 @@ struct lbp_graph {
     std::vector<Launch> vl, fl;   // variable-phase and factor-phase launches
     std::vector<FGroup> fgroups;  // shapes (batches merge by shape)
     std::vector<VGroup> vgroups;
-    std::vector<int32_t> ftile_count_by_group, hvar_count;
     int32_t nhvar = 0;
     float last_T = 0.0f;
+    std::vector<CachedLoop> loops;
+    bool has_logical = false;
+    uint64_t version = 0;  // bumped by every call that changes messages or inputs
+    // reverse-sweep workspace and the record it belongs to
+    struct Adjoint {
+        bool valid = false;
+        uint64_t version = 0;
+        int32_t iters = 0, k = 0, nseg = 0;
+        float d = 0.0f, T = 0.0f;
+        char *dmem = nullptr;
+        size_t bytes = 0;
+        float *ckpt = nullptr, *seg = nullptr, *A = nullptr, *nbar = nullptr, *Bbar = nullptr, *Bt = nullptr,
+              *zeros = nullptr, *thetabar = nullptr, *phibar = nullptr;
+        DevGraph *views = nullptr;  // [0, k): iterates in seg; [k]: current messages; [k+1]: adjoint view
+    } adj;
 };
 
 struct lbp_batch {
@@ -114,6 +193,7 @@ struct lbp_batch {
     char *dmem = nullptr;
     DevGraph *dgraphs = nullptr;
     std::vector<Launch> vl, fl;
+    std::vector<CachedLoop> loops;
 };
 
 extern "C" {
@@ -163,6 +243,8 @@ int lbp_ctx_create(int device, void *hip_stream, lbp_ctx **out) {
     if (!c) return fail(LBP_E_OOM, "host allocation failed");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    const char *env = getenv("LBP_NO_GRAPHS");
+    c->use_graphs = !(env && env[0] && env[0] != '0');
     *out = c;
     return LBP_OK;
 }
@@ -180,7 +262,20 @@ int lbp_ctx_synchronize(lbp_ctx *ctx) {
     return LBP_OK;
 }
 
-void lbp_ctx_destroy(lbp_ctx *ctx) { delete ctx; }
+void lbp_ctx_destroy(lbp_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->capture) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamDestroy(ctx->capture);
+    }
+    delete ctx;
+}
+
+int lbp_ctx_use_graphs(lbp_ctx *ctx, int enable) {
+    if (!ctx) return fail(LBP_E_INVALID, "ctx is NULL");
+    ctx->use_graphs = enable != 0;
+    return LBP_OK;
+}
 
 int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out) {
     if (!ctx || !out) return fail(LBP_E_INVALID, "ctx or out is NULL");
@@ -272,6 +367,7 @@ int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out) 
 
         DevGraph &h = g->host;
         h.m = (float *)ptr(i_m);
+        h.mo = h.m;
         h.B = (float *)ptr(i_B);
         h.theta = (float *)ptr(i_th);
         h.phi = (float *)ptr(i_phi);
@@ -317,6 +413,8 @@ int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out) 
             ++ip;
         }
         g->fgroups = L.fgroups;
+        for (const FGroup &fg : L.fgroups)
+            if (fg.kind == TK_LOGL || fg.kind == TK_LOGW) g->has_logical = true;
         g->vgroups = L.vgroups;
         g->nhvar = (int32_t)L.hvar.size();
         g->V = L.V; g->VS = L.VS; g->F = L.F; g->E = L.E; g->ES = L.ES; g->Tn = L.Tn;
@@ -337,6 +435,8 @@ void lbp_graph_free(lbp_graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
+    destroy_loops(g->loops);
+    if (g->adj.dmem) (void)hipFree(g->adj.dmem);
     (void)hipFree(g->dmem);
     delete g;
 }
@@ -379,16 +479,19 @@ static int copy_in(lbp_graph *g, const float *values, int on_device, int64_t cou
 
 int lbp_set_evidence(lbp_graph *g, const float *values, int on_device) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    ++g->version;
     return copy_in(g, values, on_device, g->VS, true, launch_evidence_in, (int)g->V);
 }
 
 int lbp_set_log_potentials(lbp_graph *g, const float *values, int on_device) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    ++g->version;
     return copy_in(g, values, on_device, g->Tn, true, launch_logpot_in, (int)g->F);
 }
 
 int lbp_set_messages(lbp_graph *g, const float *values, int on_device) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    ++g->version;
     return copy_in(g, values, on_device, g->ES, true, launch_msgs_in, (int)g->E);
 }
 
@@ -417,6 +520,7 @@ int lbp_get_messages(lbp_graph *g, float *out, int on_device) {
 
 int lbp_reset_messages(lbp_graph *g) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    ++g->version;
     HIP_TRY(hipSetDevice(g->ctx->device));
     HIP_TRY(hipMemsetAsync(g->host.m, 0, sizeof(float) * g->M, g->ctx->stream));
     return LBP_OK;
@@ -427,12 +531,9 @@ int lbp_run_bp(lbp_graph *g, int32_t iters, float damping, float temperature) {
     std::string why;
     if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
     HIP_TRY(hipSetDevice(g->ctx->device));
-    const TParams P = make_params(damping, temperature);
-    const bool maxp = temperature == 0.0f;
-    for (int32_t it = 0; it < iters; ++it) {
-        hipError_t e = launch_iteration(g->dgraph, g->vl, g->fl, P, maxp, g->ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "iteration launch");
-    }
+    ++g->version;
+    hipError_t e = run_loop(g->ctx, g->loops, g->dgraph, g->vl, g->fl, iters, damping, temperature);
+    if (e != hipSuccess) return hip_fail(e, "iteration launch");
     g->last_T = temperature;
     return LBP_OK;
 }
@@ -497,6 +598,7 @@ int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, flo
         return hip_fail(e, "hipEventCreate");
     }
     e = hipEventRecord(a, st);
+    if (phases & 2) ++g->version;
     for (int32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_iteration(g->dgraph, g->vl, g->fl, P, maxp, st, phases);
     if (e == hipSuccess) e = hipEventRecord(b, st);
     if (e == hipSuccess) e = hipEventSynchronize(b);
@@ -506,6 +608,138 @@ int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, flo
     (void)hipEventDestroy(b);
     if (e != hipSuccess) return hip_fail(e, "timing");
     *ms_out = ms / (float)reps;
+    return LBP_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+// Forward run that keeps the checkpoints the reverse sweep needs: m_t for
+// t = 0, k, 2k, ... (the start of each segment of k iterations).
+int lbp_run_bp_record(lbp_graph *g, int32_t iters, float damping, float temperature, int32_t ckpt_every) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    std::string why;
+    if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
+    if (!(temperature > 0.0f)) return fail(LBP_E_INVALID, "the adjoint needs temperature > 0 (sum-product)");
+    if (ckpt_every < 1) return fail(LBP_E_INVALID, "ckpt_every must be >= 1");
+    if (g->has_logical) return fail(LBP_E_UNSUPPORTED, "the adjoint supports enumeration factors only");
+    try {
+        HIP_TRY(hipSetDevice(g->ctx->device));
+        hipStream_t st = g->ctx->stream;
+        auto &J = g->adj;
+        J.valid = false;
+        const int32_t k = std::min<int32_t>(ckpt_every, std::max<int32_t>(iters, 1));
+        const int32_t nseg = (iters + k - 1) / k;
+        const size_t M = (size_t)g->M, VB = (size_t)g->VB, P = (size_t)g->P;
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off += align256(std::max<size_t>(bytes, 4));
+            return o;
+        };
+        const size_t o_ck = take(sizeof(float) * M * std::max(nseg, 1));
+        const size_t o_seg = take(sizeof(float) * M * k);
+        const size_t o_A = take(sizeof(float) * M), o_nb = take(sizeof(float) * M);
+        const size_t o_Bb = take(sizeof(float) * VB), o_Bt = take(sizeof(float) * VB);
+        const size_t o_z = take(sizeof(float) * VB), o_tb = take(sizeof(float) * VB);
+        const size_t o_pb = take(sizeof(float) * P);
+        const size_t o_v = take(sizeof(DevGraph) * (k + 2));
+        if (off > J.bytes) {
+            HIP_TRY(hipStreamSynchronize(st));
+            if (J.dmem) (void)hipFree(J.dmem);
+            J.dmem = nullptr;
+            J.bytes = 0;
+            hipError_t e = hipMalloc((void **)&J.dmem, off);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(LBP_E_OOM, "adjoint workspace of " + std::to_string(off) + " bytes");
+            }
+            J.bytes = off;
+        }
+        J.ckpt = (float *)(J.dmem + o_ck);
+        J.seg = (float *)(J.dmem + o_seg);
+        J.A = (float *)(J.dmem + o_A);
+        J.nbar = (float *)(J.dmem + o_nb);
+        J.Bbar = (float *)(J.dmem + o_Bb);
+        J.Bt = (float *)(J.dmem + o_Bt);
+        J.zeros = (float *)(J.dmem + o_z);
+        J.thetabar = (float *)(J.dmem + o_tb);
+        J.phibar = (float *)(J.dmem + o_pb);
+        J.views = (DevGraph *)(J.dmem + o_v);
+        // zero panels of the iterate buffers and of nbar must read as zero
+        HIP_TRY(hipMemsetAsync(J.seg, 0, sizeof(float) * M * k, st));
+        HIP_TRY(hipMemsetAsync(J.nbar, 0, sizeof(float) * M, st));
+        HIP_TRY(hipMemsetAsync(J.zeros, 0, sizeof(float) * VB, st));
+        std::vector<DevGraph> views(k + 2, g->host);
+        for (int32_t j = 0; j < k; ++j) {
+            views[j].m = J.seg + M * j;
+            views[j].mo = J.seg + M * std::min(j + 1, k - 1);
+            views[j].B = J.Bt;
+        }
+        views[k].B = J.Bt;
+        views[k + 1].m = J.nbar;
+        views[k + 1].mo = J.nbar;
+        views[k + 1].theta = J.zeros;
+        views[k + 1].B = J.Bbar;
+        HIP_TRY(hipMemcpyAsync(J.views, views.data(), sizeof(DevGraph) * (k + 2), hipMemcpyHostToDevice, st));
+        // the forward run, checkpointing each segment's first iterate
+        ++g->version;
+        for (int32_t sidx = 0; sidx < nseg; ++sidx) {
+            HIP_TRY(hipMemcpyAsync(J.ckpt + M * sidx, g->host.m, sizeof(float) * M, hipMemcpyDeviceToDevice, st));
+            const int32_t len = std::min(k, iters - sidx * k);
+            hipError_t e = run_loop(g->ctx, g->loops, g->dgraph, g->vl, g->fl, len, damping, temperature);
+            if (e != hipSuccess) return hip_fail(e, "recorded iteration launch");
+        }
+        HIP_TRY(hipStreamSynchronize(st));  // the host staging of the views must outlive its copy
+        g->last_T = temperature;
+        J.valid = true;
+        J.version = g->version;
+        J.iters = iters;
+        J.k = k;
+        J.nseg = nseg;
+        J.d = damping;
+        J.T = temperature;
+        return LBP_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(LBP_E_OOM, "host allocation failed");
+    }
+}
+
+int lbp_run_bp_backward(lbp_graph *g, const float *grad_q, float *grad_logpot, float *grad_evidence) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    if ((g->VS > 0 && !grad_q) || (g->Tn > 0 && !grad_logpot))
+        return fail(LBP_E_INVALID, "grad_q or grad_logpot is NULL");
+    auto &J = g->adj;
+    if (!J.valid || J.version != g->version)
+        return fail(LBP_E_STATE, "no lbp_run_bp_record since the graph's messages or inputs last changed");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t st = g->ctx->stream;
+    const TParams P = make_params(J.d, J.T);
+    const int64_t M = g->M;
+    const int k = J.k;
+    AdjBufs B{J.A, J.nbar, J.Bbar, J.phibar};
+    HIP_TRY(hipMemsetAsync(J.A, 0, sizeof(float) * M, st));
+    HIP_TRY(hipMemsetAsync(J.phibar, 0, sizeof(float) * g->P, st));
+    // read-out adjoint at the recorded final iterate (the graph's messages)
+    hipError_t e = launch_iteration(J.views + k, g->vl, g->fl, P, false, st, 1);
+    if (e == hipSuccess) e = launch_readout_adj(J.views + k, g->nvt, P, grad_q, J.Bbar, J.thetabar, st);
+    for (int32_t sidx = J.nseg - 1; sidx >= 0 && e == hipSuccess; --sidx) {
+        const int32_t len = std::min(k, J.iters - sidx * k);
+        e = hipMemcpyAsync(J.seg, J.ckpt + M * sidx, sizeof(float) * M, hipMemcpyDeviceToDevice, st);
+        for (int32_t j = 0; j + 1 < len && e == hipSuccess; ++j)
+            e = launch_iteration(J.views + j, g->vl, g->fl, P, false, st, 3);
+        for (int32_t j = len - 1; j >= 0 && e == hipSuccess; --j) {
+            e = launch_iteration(J.views + j, g->vl, g->fl, P, false, st, 1);  // B_t
+            for (const Launch &L : g->fl) {
+                if (e != hipSuccess) break;
+                if (L.kind == TK_PAIR) e = launch_pair_adj(J.views + j, L.items, L.n, L.a, L.b, P, B, st);
+                else e = launch_gen_adj(J.views + j, L.items, L.n, P, B, st);
+            }
+            if (e == hipSuccess) e = launch_iteration(J.views + k + 1, g->vl, g->fl, P, false, st, 1);  // Bbar_t
+            if (e == hipSuccess) e = launch_accumulate(J.thetabar, J.Bbar, g->VB, st);
+        }
+    }
+    if (e == hipSuccess) e = launch_logpot_out(g->dgraph, (int)g->F, J.phibar, grad_logpot, st);
+    if (e == hipSuccess && grad_evidence) e = launch_evidence_out(g->dgraph, (int)g->V, J.thetabar, grad_evidence, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
     return LBP_OK;
 }
 
@@ -606,13 +840,12 @@ int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature)
     std::string why;
     if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
     HIP_TRY(hipSetDevice(b->ctx->device));
-    const TParams P = make_params(damping, temperature);
-    const bool maxp = temperature == 0.0f;
-    for (int32_t it = 0; it < iters; ++it) {
-        hipError_t e = launch_iteration(b->dgraphs, b->vl, b->fl, P, maxp, b->ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "batch iteration launch");
+    hipError_t e = run_loop(b->ctx, b->loops, b->dgraphs, b->vl, b->fl, iters, damping, temperature);
+    if (e != hipSuccess) return hip_fail(e, "batch iteration launch");
+    for (lbp_graph *g : b->graphs) {
+        g->last_T = temperature;
+        ++g->version;
     }
-    for (lbp_graph *g : b->graphs) g->last_T = temperature;
     return LBP_OK;
 }
 
@@ -620,6 +853,7 @@ void lbp_batch_free(lbp_batch *b) {
     if (!b) return;
     (void)hipSetDevice(b->ctx->device);
     (void)hipStreamSynchronize(b->ctx->stream);
+    destroy_loops(b->loops);
     (void)hipFree(b->dmem);
     delete b;
 }

@@ -17,6 +17,15 @@ struct TParams {
 
 TParams make_params(float damping, float temperature);
 
+// Buffers of the reverse sweep (message panels A, nbar; belief panel Bbar;
+// potential panel phibar).
+struct AdjBufs {
+    float *A;
+    float *nbar;
+    const float *Bbar;
+    float *phibar;
+};
+
 hipError_t launch_belief_low(const DevGraph *gs, const WorkItem *items, int n, int bucket, hipStream_t st);
 hipError_t launch_belief_high(const DevGraph *gs, const WorkItem *items, int n, hipStream_t st);
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
@@ -34,5 +43,16 @@ hipError_t launch_msgs_out(const DevGraph *gs, int E, float *out, hipStream_t st
 hipError_t launch_msgs_in(const DevGraph *gs, int E, const float *in, hipStream_t st);
 hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStream_t st);
 hipError_t launch_logpot_in(const DevGraph *gs, int F, const float *in, hipStream_t st);
+
+// adjoint
+hipError_t launch_pair_adj(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, const TParams &P,
+                           const AdjBufs &J, hipStream_t st);
+hipError_t launch_gen_adj(const DevGraph *gs, const WorkItem *items, int n, const TParams &P, const AdjBufs &J,
+                          hipStream_t st);
+hipError_t launch_readout_adj(const DevGraph *gs, int nvtiles, const TParams &P, const float *gq, float *bbar,
+                              float *thetabar, hipStream_t st);
+hipError_t launch_accumulate(float *y, const float *x, int64_t n, hipStream_t st);
+hipError_t launch_logpot_out(const DevGraph *gs, int F, const float *panel, float *out, hipStream_t st);
+hipError_t launch_evidence_out(const DevGraph *gs, int V, const float *panel, float *out, hipStream_t st);
 
 }  // namespace lbp

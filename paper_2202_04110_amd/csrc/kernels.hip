@@ -113,39 +113,61 @@ __global__ __launch_bounds__(256) void k_belief_low(const DevGraph *__restrict__
         if (s < n) G.B[base + s * kLanes] = acc[s];
 }
 
-// One wavefront per high-degree variable: lanes take edges k = lane, lane+64,
-// ..., then a butterfly reduction (every lane ends with the same bits).
-__global__ __launch_bounds__(256) void k_belief_high(const DevGraph *__restrict__ gs,
-                                                     const WorkItem *__restrict__ items, int nitems) {
-    const int w = wave_index(4);
+// One 256-thread block per high-degree variable.  Thread i sums edges
+// i, i+256, ... in order (their addresses, then their rows, fetched together
+// in chunks of 4), then a fixed LDS tree combines the 256 partial sums; the
+// result does not depend on anything but the variable's edge list.
+constexpr int kHighThreads = 256;
+__global__ __launch_bounds__(kHighThreads) void k_belief_high(const DevGraph *__restrict__ gs,
+                                                              const WorkItem *__restrict__ items, int nitems) {
+    constexpr int SC = 8;  // states per pass
+    constexpr int KC = 4;  // edges per thread fetched together
+    __shared__ float red[SC][kHighThreads];
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
     if (w >= nitems) return;
-    const int lane = lane_id();
+    const int tid = threadIdx.x;
     const WorkItem it = items[w];
     const DevGraph &G = gs[it.g];
     const HVar h = G.hvar[it.t];
-    for (int s0 = 0; s0 < h.n; s0 += 8) {
-        float part[8];
+    for (int s0 = 0; s0 < h.n; s0 += SC) {
+        float part[SC];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) part[j] = 0.0f;
-        for (int k = h.e_begin + lane; k < h.e_end; k += kLanes) {
-            const float *row = G.m + G.hedge[k];
+        for (int j = 0; j < SC; ++j) part[j] = 0.0f;
+        for (int k0 = h.e_begin + tid; k0 < h.e_end; k0 += KC * kHighThreads) {
+            int a[KC];
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (s0 + j < h.n) part[j] += row[(s0 + j) * kLanes];
+            for (int u = 0; u < KC; ++u) {
+                const int k = k0 + u * kHighThreads;
+                a[u] = k < h.e_end ? G.hedge[k] : -1;
+            }
+            float x[KC][SC];
+#pragma unroll
+            for (int u = 0; u < KC; ++u)
+#pragma unroll
+                for (int j = 0; j < SC; ++j)
+                    x[u][j] = (a[u] >= 0 && s0 + j < h.n) ? G.m[a[u] + (s0 + j) * kLanes] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < KC; ++u)
+#pragma unroll
+                for (int j = 0; j < SC; ++j)
+                    if (a[u] >= 0 && s0 + j < h.n) part[j] += x[u][j];
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < SC; ++j) red[j][tid] = part[j];
+        __syncthreads();
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) part[j] += __shfl_xor(part[j], off, 64);
-        }
-        if (lane == 0) {
+        for (int half = kHighThreads / 2; half > 0; half >>= 1) {
+            if (tid < half) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (s0 + j < h.n) {
-                    const int a = h.b_addr + (s0 + j) * kLanes;
-                    G.B[a] = G.theta[a] + part[j];
-                }
+                for (int j = 0; j < SC; ++j) red[j][tid] += red[j][tid + half];
+            }
+            __syncthreads();
         }
+        if (tid < SC && s0 + tid < h.n) {
+            const int a = h.b_addr + (s0 + tid) * kLanes;
+            G.B[a] = G.theta[a] + red[tid][0];
+        }
+        __syncthreads();
     }
 }
 
@@ -162,8 +184,10 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
     const int nb = EXACT ? NB : ft.b;
     const int va = G.fvb[ft.vb_off + lane];
     const int vb = G.fvb[ft.vb_off + kLanes + lane];
-    float *r0 = G.m + ft.m_off + lane;
-    float *r1 = r0 + na * kLanes;
+    const float *r0 = G.m + ft.m_off + lane;
+    const float *r1 = r0 + na * kLanes;
+    float *w0 = G.mo + ft.m_off + lane;
+    float *w1 = w0 + na * kLanes;
     float m0[NA], m1[NB], x0[NA], x1[NB];
 #pragma unroll
     for (int i = 0; i < NA; ++i)
@@ -229,8 +253,8 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
                 u1[j] = M + flog2(s) * P.r;
             }
         }
-    damp_store<NA>(r0, m0, u0, na, P);
-    damp_store<NB>(r1, m1, u1, nb, P);
+    damp_store<NA>(w0, m0, u0, na, P);
+    damp_store<NB>(w1, m1, u1, nb, P);
 }
 
 template <int NA, int NB, bool EXACT, bool MAXP>
@@ -272,7 +296,8 @@ __global__ __launch_bounds__(256) void k_logl(const DevGraph *__restrict__ gs, c
     const FTile ft = G.ftile[it.t];
     const int k = ft.a, p = k - 1;
     const bool flip = ft.b != 0;
-    float *rows = G.m + ft.m_off + lane;
+    const float *rows = G.m + ft.m_off + lane;
+    float *wrows = G.mo + ft.m_off + lane;
     float m0[K], m1[K], dl[K];
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -340,8 +365,8 @@ __global__ __launch_bounds__(256) void k_logl(const DevGraph *__restrict__ gs, c
             const float u0 = flip ? a1 : a0, u1 = flip ? a0 : a1;
             const float w0 = P.d * m0[j] + P.omd * u0, w1 = P.d * m1[j] + P.omd * u1;
             const float mx = fmaxf(w0, w1);
-            rows[(2 * j) * kLanes] = w0 - mx;
-            rows[(2 * j + 1) * kLanes] = w1 - mx;
+            wrows[(2 * j) * kLanes] = w0 - mx;
+            wrows[(2 * j + 1) * kLanes] = w1 - mx;
         }
 }
 
@@ -365,7 +390,7 @@ __global__ __launch_bounds__(256) void k_logw(const DevGraph *__restrict__ gs, c
         dl[c] = 0.0f;
         t[c] = 0.0f;
         if (c < nch && j < k) {
-            float *row = G.m + ft.m_off + c * 2 * kLanes + lane;
+            const float *row = G.m + ft.m_off + c * 2 * kLanes + lane;
             m0[c] = row[0];
             m1[c] = row[kLanes];
             const int vb = G.fvb[ft.vb_off + j];
@@ -463,7 +488,7 @@ __global__ __launch_bounds__(256) void k_logw(const DevGraph *__restrict__ gs, c
             const float u0 = flip ? a1 : a0, u1 = flip ? a0 : a1;
             const float w0 = P.d * m0[c] + P.omd * u0, w1 = P.d * m1[c] + P.omd * u1;
             const float mx = fmaxf(w0, w1);
-            float *row = G.m + ft.m_off + c * 2 * kLanes + lane;
+            float *row = G.mo + ft.m_off + c * 2 * kLanes + lane;
             row[0] = w0 - mx;
             row[kLanes] = w1 - mx;
         }
@@ -493,7 +518,8 @@ __global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, con
     const GenClass gc = G.gcls[ft.a];
     const int A = gc.arity, C = gc.ncfg, R = gc.nrows;
     for (int i = lane; i < C * A; i += kLanes) rows[i] = G.grows[gc.rows_off + i];
-    float *mrow = G.m + ft.m_off + lane;
+    const float *mrow = G.m + ft.m_off + lane;
+    float *wrow = G.mo + ft.m_off + lane;
     for (int j = 0; j < A; ++j) {
         const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
         for (int s = 0; s < gc.slot_n[j]; ++s) {
@@ -536,10 +562,325 @@ __global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, con
         }
         for (int s = 0; s < n; ++s) {
             const int r = r0 + s;
-            mrow[r * kLanes] = sacc[r][lane] - mx;
+            wrow[r * kLanes] = sacc[r][lane] - mx;
         }
     }
     (void)R;
+}
+
+// --------------------------------------------------------------------------
+// adjoint of the unrolled damped sum-product iterations (T > 0)
+// --------------------------------------------------------------------------
+// Reverse mode of one iteration t (m_t -> m_{t+1}).  The adjoint of m_{t+1}
+// is held in two parts, A[e,s] + Bbar[var(e),s]: A is the direct part owned
+// by the factor of e, Bbar the adjoint of the next iterate's beliefs.  Per
+// factor, with u, m' = d m + (1-d) u recomputed from m_t:
+//   gm  = A + Bbar[var]                         adjoint of m_{t+1}
+//   gmp = gm - [s = argmax m'] sum_s gm         normalisation m_{t+1} = m' - max m'
+//   gu  = (1-d) gmp
+//   sbar(c) = sum_j gu[e_j,c_j] pi_j(c),  pi_j(c) = exp((score(c) - LSE_j,c_j)/T)
+//   phibar(c) += sbar(c)
+//   nbar[e_j,s] = sum_{c: c_j = s} sbar(c) - gu[e_j,s]
+//   A <- d gmp - nbar                           direct part of the adjoint of m_t
+// The variable side (Bbar_t = sum_e nbar, thetabar += Bbar_t) runs the belief
+// kernels on nbar.
+template <int NA, int NB, bool EXACT>
+__global__ __launch_bounds__(256) void k_pair_adj(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                                  int nitems, TParams P, AdjBufs J) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const int lane = lane_id();
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    const int na = EXACT ? NA : ft.a;
+    const int nb = EXACT ? NB : ft.b;
+    const int va = G.fvb[ft.vb_off + lane];
+    const int vb = G.fvb[ft.vb_off + kLanes + lane];
+    const int o0 = ft.m_off + lane, o1 = o0 + na * kLanes;
+    float m0[NA], m1[NB], x0[NA], x1[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+        if (i < na) {
+            m0[i] = G.m[o0 + i * kLanes];
+            x0[i] = G.B[va + i * kLanes] - m0[i];
+        }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (j < nb) {
+            m1[j] = G.m[o1 + j * kLanes];
+            x1[j] = G.B[vb + j * kLanes] - m1[j];
+        }
+    const float *ph = G.phi + ft.phi_off + lane;
+    float p[NA][NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (i < na && j < nb) p[i][j] = ph[(i * nb + j) * kLanes];
+    // forward: u (LSE per row / column), exactly as in the forward kernel
+    float u0[NA], u1[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+        if (i < na) {
+            float t[NB];
+            float M = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (j < nb) {
+                    t[j] = p[i][j] + x1[j];
+                    M = fmaxf(M, t[j]);
+                }
+            float sm = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (j < nb) sm += fexp2((t[j] - M) * P.c);
+            u0[i] = M + flog2(sm) * P.r;
+        }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (j < nb) {
+            float t[NA];
+            float M = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+                if (i < na) {
+                    t[i] = p[i][j] + x0[i];
+                    M = fmaxf(M, t[i]);
+                }
+            float sm = 0.0f;
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+                if (i < na) sm += fexp2((t[i] - M) * P.c);
+            u1[j] = M + flog2(sm) * P.r;
+        }
+    // adjoint of damping + normalisation
+    float gu0[NA], gu1[NB], dg0[NA], dg1[NB];
+    {
+        float mx = -INFINITY, tot = 0.0f, gm[NA];
+        int am = 0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            if (i < na) {
+                const float mp = P.d * m0[i] + P.omd * u0[i];
+                if (mp > mx) {
+                    mx = mp;
+                    am = i;
+                }
+                gm[i] = J.A[o0 + i * kLanes] + J.Bbar[va + i * kLanes];
+                tot += gm[i];
+            }
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            if (i < na) {
+                const float gmp = gm[i] - (i == am ? tot : 0.0f);
+                gu0[i] = P.omd * gmp;
+                dg0[i] = P.d * gmp;
+            }
+    }
+    {
+        float mx = -INFINITY, tot = 0.0f, gm[NB];
+        int am = 0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < nb) {
+                const float mp = P.d * m1[j] + P.omd * u1[j];
+                if (mp > mx) {
+                    mx = mp;
+                    am = j;
+                }
+                gm[j] = J.A[o1 + j * kLanes] + J.Bbar[vb + j * kLanes];
+                tot += gm[j];
+            }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < nb) {
+                const float gmp = gm[j] - (j == am ? tot : 0.0f);
+                gu1[j] = P.omd * gmp;
+                dg1[j] = P.d * gmp;
+            }
+    }
+    // configuration adjoints
+    float rs0[NA], rs1[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) rs0[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) rs1[j] = 0.0f;
+    float *pb = J.phibar + ft.phi_off + lane;
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (i < na && j < nb) {
+                const float pa = fexp2((p[i][j] + x1[j] - u0[i]) * P.c);
+                const float pbv = fexp2((p[i][j] + x0[i] - u1[j]) * P.c);
+                const float sb = gu0[i] * pa + gu1[j] * pbv;
+                pb[(i * nb + j) * kLanes] += sb;
+                rs0[i] += sb;
+                rs1[j] += sb;
+            }
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+        if (i < na) {
+            const float nbar = rs0[i] - gu0[i];
+            J.nbar[o0 + i * kLanes] = nbar;
+            J.A[o0 + i * kLanes] = dg0[i] - nbar;
+        }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (j < nb) {
+            const float nbar = rs1[j] - gu1[j];
+            J.nbar[o1 + j * kLanes] = nbar;
+            J.A[o1 + j * kLanes] = dg1[j] - nbar;
+        }
+}
+
+// generic enumeration factors (one wavefront per block, LDS as in k_gen)
+__global__ __launch_bounds__(64) void k_gen_adj(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                                int nitems, TParams P, AdjBufs J) {
+    __shared__ uint8_t rows[kGenCfgMax * kGenArityMax];
+    __shared__ float nv[kGenRowsMax][kLanes];
+    __shared__ float lse[kGenRowsMax][kLanes];
+    __shared__ float acc[kGenRowsMax][kLanes];
+    __shared__ float gu[kGenRowsMax][kLanes];
+    __shared__ float dg[kGenRowsMax][kLanes];
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+    if (w >= nitems) return;
+    const int lane = lane_id();
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    const GenClass gc = G.gcls[ft.a];
+    const int A = gc.arity, C = gc.ncfg;
+    for (int i = lane; i < C * A; i += kLanes) rows[i] = G.grows[gc.rows_off + i];
+    const int base = ft.m_off + lane;
+    for (int j = 0; j < A; ++j) {
+        const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
+        for (int s = 0; s < gc.slot_n[j]; ++s) {
+            const int r = gc.slot_row[j] + s;
+            nv[r][lane] = G.B[vb + s * kLanes] - G.m[base + r * kLanes];
+            lse[r][lane] = -INFINITY;
+            acc[r][lane] = 0.0f;
+        }
+    }
+    __syncthreads();
+    const float *ph = G.phi + ft.phi_off + lane;
+    for (int c = 0; c < C; ++c) {
+        float sc = ph[c * kLanes];
+        for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j]][lane];
+        for (int j = 0; j < A; ++j) {
+            const int r = rows[c * A + j];
+            lse[r][lane] = fmaxf(lse[r][lane], sc);
+        }
+    }
+    for (int c = 0; c < C; ++c) {
+        float sc = ph[c * kLanes];
+        for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j]][lane];
+        for (int j = 0; j < A; ++j) {
+            const int r = rows[c * A + j];
+            acc[r][lane] += fexp2((sc - lse[r][lane]) * P.c);
+        }
+    }
+    for (int j = 0; j < A; ++j) {
+        const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
+        const int r0 = gc.slot_row[j], n = gc.slot_n[j];
+        float mx = -INFINITY, tot = 0.0f;
+        int am = 0;
+        for (int s = 0; s < n; ++s) {
+            const int r = r0 + s;
+            lse[r][lane] = lse[r][lane] + flog2(acc[r][lane]) * P.r;
+            const float u = lse[r][lane] - nv[r][lane];
+            const float mp = P.d * G.m[base + r * kLanes] + P.omd * u;
+            if (mp > mx) {
+                mx = mp;
+                am = s;
+            }
+            const float gm = J.A[base + r * kLanes] + J.Bbar[vb + s * kLanes];
+            gu[r][lane] = gm;
+            tot += gm;
+        }
+        for (int s = 0; s < n; ++s) {
+            const int r = r0 + s;
+            const float gmp = gu[r][lane] - (s == am ? tot : 0.0f);
+            gu[r][lane] = P.omd * gmp;
+            dg[r][lane] = P.d * gmp;
+            acc[r][lane] = 0.0f;
+        }
+    }
+    float *pb = J.phibar + ft.phi_off + lane;
+    for (int c = 0; c < C; ++c) {
+        float sc = ph[c * kLanes];
+        for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j]][lane];
+        float sb = 0.0f;
+        for (int j = 0; j < A; ++j) {
+            const int r = rows[c * A + j];
+            sb += gu[r][lane] * fexp2((sc - lse[r][lane]) * P.c);
+        }
+        pb[c * kLanes] += sb;
+        for (int j = 0; j < A; ++j) acc[rows[c * A + j]][lane] += sb;
+    }
+    for (int r = 0; r < gc.nrows; ++r) {
+        const float nbar = acc[r][lane] - gu[r][lane];
+        J.nbar[base + r * kLanes] = nbar;
+        J.A[base + r * kLanes] = dg[r][lane] - nbar;
+    }
+}
+
+// Adjoint of the read-out q = B - LSE_T(B): Bbar = gq - softmax(B/T) sum gq;
+// it is also the first contribution to thetabar.
+__global__ __launch_bounds__(256) void k_readout_adj(const DevGraph *__restrict__ gs, int ntiles, TParams P,
+                                                     const float *__restrict__ gq, float *__restrict__ bbar,
+                                                     float *__restrict__ thetabar) {
+    const int w = wave_index(4);
+    if (w >= ntiles) return;
+    const int lane = lane_id();
+    const DevGraph &G = gs[0];
+    const int v = w * kLanes + lane;
+    if (v >= G.V) return;
+    const int n = G.vn[v];
+    const int b0 = G.vtile[w].b_off + lane;
+    const float *b = G.B + b0;
+    const float *g = gq + G.vs_off[v];
+    float M = -INFINITY, tot = 0.0f;
+    for (int s = 0; s < n; ++s) {
+        M = fmaxf(M, b[s * kLanes]);
+        tot += g[s];
+    }
+    float z = 0.0f;
+    for (int s = 0; s < n; ++s) z += fexp2((b[s * kLanes] - M) * P.c);
+    const float iz = 1.0f / z;
+    for (int s = 0; s < n; ++s) {
+        const float pr = fexp2((b[s * kLanes] - M) * P.c) * iz;
+        const float x = g[s] - pr * tot;
+        bbar[b0 + s * kLanes] = x;
+        thetabar[b0 + s * kLanes] = x;
+    }
+}
+
+__global__ void k_accumulate(float *__restrict__ y, const float *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += x[i];
+}
+
+__global__ void k_logpot_out(const DevGraph *__restrict__ gs, const float *__restrict__ panel, float *__restrict__ out) {
+    const DevGraph &G = gs[0];
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= G.F) return;
+    const int base = G.fac_phi[f];
+    if (base < 0) return;
+    const int64_t o = G.lp_off[f];
+    const int n = (int)(G.lp_off[f + 1] - o);
+    for (int c = 0; c < n; ++c) out[o + c] = panel[base + c * kLanes];
+}
+
+__global__ void k_evidence_out(const DevGraph *__restrict__ gs, const float *__restrict__ panel,
+                               float *__restrict__ out) {
+    const DevGraph &G = gs[0];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= G.V) return;
+    const float *row = panel + G.vtile[v / kLanes].b_off + (v % kLanes);
+    const int64_t o = G.vs_off[v];
+    for (int s = 0; s < G.vn[v]; ++s) out[o + s] = row[s * kLanes];
 }
 
 // --------------------------------------------------------------------------
@@ -647,7 +988,7 @@ hipError_t launch_belief_low(const DevGraph *gs, const WorkItem *items, int n, i
 
 hipError_t launch_belief_high(const DevGraph *gs, const WorkItem *items, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_belief_high, dim3(blocks_for(n, 4)), dim3(256), 0, st, gs, items, n);
+    hipLaunchKernelGGL(k_belief_high, dim3(n), dim3(kHighThreads), 0, st, gs, items, n);
     return hipGetLastError();
 }
 
@@ -743,6 +1084,59 @@ hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStr
 hipError_t launch_logpot_in(const DevGraph *gs, int F, const float *in, hipStream_t st) {
     if (F <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_logpot_in, dim3(blocks_for(F, 256)), dim3(256), 0, st, gs, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_adj(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, const TParams &P,
+                           const AdjBufs &J, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid(blocks_for(n, 4)), block(256);
+    if (na == nb && na >= 2 && na <= 8) {
+        switch (na) {
+        case 2: hipLaunchKernelGGL((k_pair_adj<2, 2, true>), grid, block, 0, st, gs, items, n, P, J); break;
+        case 3: hipLaunchKernelGGL((k_pair_adj<3, 3, true>), grid, block, 0, st, gs, items, n, P, J); break;
+        case 4: hipLaunchKernelGGL((k_pair_adj<4, 4, true>), grid, block, 0, st, gs, items, n, P, J); break;
+        case 5: hipLaunchKernelGGL((k_pair_adj<5, 5, true>), grid, block, 0, st, gs, items, n, P, J); break;
+        case 6: hipLaunchKernelGGL((k_pair_adj<6, 6, true>), grid, block, 0, st, gs, items, n, P, J); break;
+        case 7: hipLaunchKernelGGL((k_pair_adj<7, 7, true>), grid, block, 0, st, gs, items, n, P, J); break;
+        default: hipLaunchKernelGGL((k_pair_adj<8, 8, true>), grid, block, 0, st, gs, items, n, P, J); break;
+        }
+    } else {
+        hipLaunchKernelGGL((k_pair_adj<kPairStatesMax, kPairStatesMax, false>), grid, block, 0, st, gs, items, n, P, J);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_adj(const DevGraph *gs, const WorkItem *items, int n, const TParams &P, const AdjBufs &J,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gen_adj, dim3(n), dim3(64), 0, st, gs, items, n, P, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout_adj(const DevGraph *gs, int nvtiles, const TParams &P, const float *gq, float *bbar,
+                              float *thetabar, hipStream_t st) {
+    if (nvtiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_readout_adj, dim3(blocks_for(nvtiles, 4)), dim3(256), 0, st, gs, nvtiles, P, gq, bbar,
+                       thetabar);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(float *y, const float *x, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(n, 256)), dim3(256), 0, st, y, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_logpot_out(const DevGraph *gs, int F, const float *panel, float *out, hipStream_t st) {
+    if (F <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_logpot_out, dim3(blocks_for(F, 256)), dim3(256), 0, st, gs, panel, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_evidence_out(const DevGraph *gs, int V, const float *panel, float *out, hipStream_t st) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_evidence_out, dim3(blocks_for(V, 256)), dim3(256), 0, st, gs, panel, out);
     return hipGetLastError();
 }
 

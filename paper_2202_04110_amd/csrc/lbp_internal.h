@@ -71,6 +71,7 @@ struct GenClass {
 // Device pointers of one uploaded graph.
 struct DevGraph {
     float *m;             // messages (panels) + a zero panel at zero_addr
+    float *mo;            // where factor kernels write updated messages (== m: in place)
     float *B;             // beliefs (panels)
     float *theta;         // evidence (panels)
     float *phi;           // potentials (panels)

@@ -61,6 +61,7 @@ _sig("lbp_check_layout", C.c_int, [C.POINTER(GraphDesc), _P])
 _sig("lbp_ctx_create", C.c_int, [C.c_int, _P, C.POINTER(_P)])
 _sig("lbp_ctx_set_stream", C.c_int, [_P, _P])
 _sig("lbp_ctx_synchronize", C.c_int, [_P])
+_sig("lbp_ctx_use_graphs", C.c_int, [_P, C.c_int])
 _sig("lbp_ctx_destroy", None, [_P])
 _sig("lbp_graph_upload", C.c_int, [_P, C.POINTER(GraphDesc), C.POINTER(_P)])
 _sig("lbp_graph_free", None, [_P])
@@ -74,6 +75,8 @@ _sig("lbp_decode_map", C.c_int, [_P, _P, C.c_int])
 _sig("lbp_graph_status", C.c_int, [_P])
 _sig("lbp_get_messages", C.c_int, [_P, _P, C.c_int])
 _sig("lbp_set_messages", C.c_int, [_P, _P, C.c_int])
+_sig("lbp_run_bp_record", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_int32])
+_sig("lbp_run_bp_backward", C.c_int, [_P, _P, _P, _P])
 _sig("lbp_batch_create", C.c_int, [_P, _P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_batch_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
 _sig("lbp_batch_free", None, [_P])
@@ -177,6 +180,9 @@ class Context:
     def synchronize(self):
         check(_lib.lbp_ctx_synchronize(self.h))
 
+    def use_graphs(self, enable: bool):
+        check(_lib.lbp_ctx_use_graphs(self.h, int(bool(enable))))
+
     def close(self):
         if self.h:
             _lib.lbp_ctx_destroy(self.h)
@@ -254,6 +260,16 @@ class Graph:
         if not _is_dev(values):
             values = np.ascontiguousarray(values, np.float32)
         check(_lib.lbp_set_log_potentials(self.h, _ptr(values), int(_is_dev(values))))
+
+    def run_bp_record(self, iters: int, damping: float, temperature: float, ckpt_every: int = 10):
+        """Like run_bp, keeping checkpoints for backward (T > 0, enumeration factors)."""
+        check(_lib.lbp_run_bp_record(self.h, int(iters), float(damping), float(temperature), int(ckpt_every)))
+
+    def backward(self, grad_q, grad_logpot, grad_evidence=None):
+        """dL/dphi and dL/dtheta of L = sum(grad_q * q) for the recorded run
+        (all device tensors, float32, flat orders)."""
+        check(_lib.lbp_run_bp_backward(self.h, _ptr(grad_q), _ptr(grad_logpot),
+                                       _ptr(grad_evidence) if grad_evidence is not None else None))
 
     def time_phase(self, phase: int, reps: int, damping: float, temperature: float) -> float:
         ms = C.c_float()

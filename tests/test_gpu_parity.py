@@ -384,3 +384,32 @@ def test_argument_errors(lbp, ctx):
         assert ei.value.code == lbp.LBP_E_INVALID
     with pytest.raises(lbp.LBPError):
         g.set_evidence(np.full(g.VS, np.inf, np.float32))
+
+
+def test_graph_replay_matches_eager(lbp, ctx):
+    """Captured loops replayed several times, with eager work and
+    synchronisations between replays, give the eager result every time."""
+    import torch
+    spec = W.potts_grid(30, 4, 81)
+    eager_ctx = lbp.Context(0)
+    eager_ctx.use_graphs(False)
+    a = lbp.Graph(eager_ctx, spec)
+    b = lbp.Graph(ctx, spec)
+    for rep in range(4):
+        a.run_bp(7, 0.5, 1.0)
+        b.run_bp(7, 0.5, 1.0)  # captured on the first call, replayed afterwards
+        qb = b.get_beliefs()
+        x = torch.randn(1000, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(a.get_messages(), b.get_messages())
+        np.testing.assert_array_equal(a.get_beliefs(), qb)
+        del x
+    gs = [lbp.Graph(ctx, W.potts_grid(9, 3, 82)), lbp.Graph(ctx, W.ising_grid(7, 83))]
+    gs_e = [lbp.Graph(eager_ctx, W.potts_grid(9, 3, 82)), lbp.Graph(eager_ctx, W.ising_grid(7, 83))]
+    bt = lbp.Batch(ctx, gs)
+    for rep in range(3):
+        bt.run_bp(5, 0.5, 0.0)
+        for g in gs_e:
+            g.run_bp(5, 0.5, 0.0)
+        for g, h in zip(gs, gs_e):
+            np.testing.assert_array_equal(g.get_messages(), h.get_messages())
