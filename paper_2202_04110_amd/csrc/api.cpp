@@ -37,11 +37,48 @@ int hip_fail(hipError_t e, const char *what) {
 
 // A set of work items launched by one kernel.
 struct Launch {
-    int32_t kind;  // -1 belief-low, -2 belief-high, TK_* factor kernels
-    int32_t a, b;  // belief-low: bucket; PAIR: states; LOGW: chunk bucket
-    int32_t n;
+    int32_t kind;  // -1 variable phase, TK_* factor kernels
+    int32_t a, b;  // variable phase: state bucket; PAIR: slot state counts
+    int32_t n;     // items (variable phase: low tiles)
     WorkItem *items;  // device
+    int32_t n_mid = 0, n_high = 0;  // variable phase: wavefront- and block-per-variable items after the tiles
 };
+
+// Variable-phase launches: one per state bucket of the low tiles; the first
+// also carries every mid and high variable.
+struct VarWork {
+    std::vector<int32_t> buckets;
+    std::vector<std::vector<WorkItem>> items;  // per bucket: tiles, then (first only) mids, highs
+    int32_t n_mid = 0, n_high = 0;
+};
+
+void add_var_work(VarWork &vw, int32_t gi, const std::vector<VGroup> &vgroups, const std::vector<int32_t> &mids,
+                  const std::vector<int32_t> &highs, std::vector<WorkItem> *mid_out, std::vector<WorkItem> *high_out) {
+    for (const VGroup &vg : vgroups) {
+        size_t i = 0;
+        while (i < vw.buckets.size() && vw.buckets[i] != vg.bucket) ++i;
+        if (i == vw.buckets.size()) {
+            vw.buckets.push_back(vg.bucket);
+            vw.items.emplace_back();
+        }
+        for (int32_t t : vg.tiles) vw.items[i].push_back(WorkItem{gi, t});
+    }
+    for (int32_t h : mids) mid_out->push_back(WorkItem{gi, h});
+    for (int32_t h : highs) high_out->push_back(WorkItem{gi, h});
+}
+
+// Appends mids/highs to the first bucket's list (creating one if needed).
+void finish_var_work(VarWork &vw, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs) {
+    if (mids.empty() && highs.empty()) return;
+    if (vw.buckets.empty()) {
+        vw.buckets.push_back(2);
+        vw.items.emplace_back();
+    }
+    vw.n_mid = (int32_t)mids.size();
+    vw.n_high = (int32_t)highs.size();
+    vw.items[0].insert(vw.items[0].end(), mids.begin(), mids.end());
+    vw.items[0].insert(vw.items[0].end(), highs.begin(), highs.end());
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -68,15 +105,15 @@ hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, c
     hipError_t e = hipSuccess;
     if (phases & 1)
         for (const Launch &L : vl) {
-            e = L.kind == -1 ? launch_belief_low(gs, L.items, L.n, L.a, st) : launch_belief_high(gs, L.items, L.n, st);
+            e = launch_belief(gs, L.items, L.n, L.n_mid, L.n_high, L.a, st);
             if (e != hipSuccess) return e;
         }
     if (phases & 2)
         for (const Launch &L : fl) {
             switch (L.kind) {
             case TK_PAIR: e = launch_pair(gs, L.items, L.n, L.a, L.b, maxp, P, st); break;
-            case TK_LOGL: e = launch_logl(gs, L.items, L.n, maxp, P, st); break;
-            case TK_LOGW: e = launch_logw(gs, L.items, L.n, L.a, maxp, P, st); break;
+            case TK_LOGL: e = launch_logical(gs, L.items, L.n, false, maxp, P, st); break;
+            case TK_LOGW: e = launch_logical(gs, L.items, L.n, true, maxp, P, st); break;
             default: e = launch_gen(gs, L.items, L.n, maxp, P, st); break;
             }
             if (e != hipSuccess) return e;
@@ -168,7 +205,7 @@ struct lbp_graph {
     std::vector<Launch> vl, fl;   // variable-phase and factor-phase launches
     std::vector<FGroup> fgroups;  // shapes (batches merge by shape)
     std::vector<VGroup> vgroups;
-    int32_t nhvar = 0;
+    std::vector<int32_t> mids, highs;
     float last_T = 0.0f;
     std::vector<CachedLoop> loops;
     bool has_logical = false;
@@ -328,16 +365,13 @@ int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out) 
         // work items
         std::vector<std::vector<WorkItem>> items;
         std::vector<size_t> item_piece;
-        for (const VGroup &vg : L.vgroups) {
-            std::vector<WorkItem> w;
-            for (int32_t t : vg.tiles) w.push_back(WorkItem{0, t});
-            items.push_back(std::move(w));
-        }
+        VarWork vw;
         {
-            std::vector<WorkItem> w;
-            for (size_t i = 0; i < L.hvar.size(); ++i) w.push_back(WorkItem{0, (int32_t)i});
-            items.push_back(std::move(w));
+            std::vector<WorkItem> mids, highs;
+            add_var_work(vw, 0, L.vgroups, L.mids, L.highs, &mids, &highs);
+            finish_var_work(vw, mids, highs);
         }
+        for (auto &w : vw.items) items.push_back(w);
         for (const FGroup &fg : L.fgroups) {
             std::vector<WorkItem> w;
             for (int32_t t : fg.tiles) w.push_back(WorkItem{0, t});
@@ -402,12 +436,13 @@ int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out) 
             return hip_fail(e, "graph upload");
         }
         size_t ip = 0;
-        for (const VGroup &vg : L.vgroups) {
-            g->vl.push_back(Launch{-1, vg.bucket, 0, (int32_t)vg.tiles.size(), (WorkItem *)ptr(item_piece[ip])});
-            ++ip;
+        for (size_t i = 0; i < vw.buckets.size(); ++i, ++ip) {
+            Launch Lv{-1, vw.buckets[i], 0, 0, (WorkItem *)ptr(item_piece[ip])};
+            Lv.n_mid = i == 0 ? vw.n_mid : 0;
+            Lv.n_high = i == 0 ? vw.n_high : 0;
+            Lv.n = (int32_t)vw.items[i].size() - Lv.n_mid - Lv.n_high;
+            g->vl.push_back(Lv);
         }
-        if (!L.hvar.empty()) g->vl.push_back(Launch{-2, 0, 0, (int32_t)L.hvar.size(), (WorkItem *)ptr(item_piece[ip])});
-        ++ip;
         for (const FGroup &fg : L.fgroups) {
             g->fl.push_back(Launch{fg.kind, fg.a, fg.b, (int32_t)fg.tiles.size(), (WorkItem *)ptr(item_piece[ip])});
             ++ip;
@@ -416,7 +451,8 @@ int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out) 
         for (const FGroup &fg : L.fgroups)
             if (fg.kind == TK_LOGL || fg.kind == TK_LOGW) g->has_logical = true;
         g->vgroups = L.vgroups;
-        g->nhvar = (int32_t)L.hvar.size();
+        g->mids = L.mids;
+        g->highs = L.highs;
         g->V = L.V; g->VS = L.VS; g->F = L.F; g->E = L.E; g->ES = L.ES; g->Tn = L.Tn;
         g->M = L.M; g->VB = L.VB; g->P = L.P;
         g->nvt = (int32_t)L.vtile.size();
@@ -758,8 +794,10 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
             int32_t kind, a, b;
             bool operator==(const Key &o) const { return kind == o.kind && a == o.a && b == o.b; }
         };
-        std::vector<Key> vkeys, fkeys;
-        std::vector<std::vector<WorkItem>> vitems, fitems;
+        std::vector<Key> fkeys;
+        std::vector<std::vector<WorkItem>> fitems;
+        VarWork vw;
+        std::vector<WorkItem> mids, highs;
         auto slot = [](std::vector<Key> &keys, std::vector<std::vector<WorkItem>> &its, Key k) -> std::vector<WorkItem> & {
             for (size_t i = 0; i < keys.size(); ++i)
                 if (keys[i] == k) return its[i];
@@ -770,19 +808,14 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
         for (int32_t gi = 0; gi < num_graphs; ++gi) {
             const lbp_graph *g = graphs[gi];
             // the graph's item lists are on the device; rebuild them from its groups
-            for (const VGroup &vg : g->vgroups) {
-                auto &v = slot(vkeys, vitems, Key{-1, vg.bucket, 0});
-                for (int32_t t : vg.tiles) v.push_back(WorkItem{gi, t});
-            }
-            if (g->nhvar) {
-                auto &v = slot(vkeys, vitems, Key{-2, 0, 0});
-                for (int32_t t = 0; t < g->nhvar; ++t) v.push_back(WorkItem{gi, t});
-            }
+            add_var_work(vw, gi, g->vgroups, g->mids, g->highs, &mids, &highs);
             for (const FGroup &fg : g->fgroups) {
                 auto &v = slot(fkeys, fitems, Key{fg.kind, fg.a, fg.b});
                 for (int32_t t : fg.tiles) v.push_back(WorkItem{gi, t});
             }
         }
+        finish_var_work(vw, mids, highs);
+        std::vector<std::vector<WorkItem>> &vitems = vw.items;
         size_t total = align256(sizeof(DevGraph) * std::max(1, num_graphs));
         std::vector<size_t> voff, foff;
         for (auto &v : vitems) {
@@ -810,7 +843,11 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
         for (size_t i = 0; i < vitems.size() && e == hipSuccess; ++i) {
             e = hipMemcpyAsync(b->dmem + voff[i], vitems[i].data(), sizeof(WorkItem) * vitems[i].size(),
                                hipMemcpyHostToDevice, st);
-            b->vl.push_back(Launch{vkeys[i].kind, vkeys[i].a, 0, (int32_t)vitems[i].size(), (WorkItem *)(b->dmem + voff[i])});
+            Launch Lv{-1, vw.buckets[i], 0, 0, (WorkItem *)(b->dmem + voff[i])};
+            Lv.n_mid = i == 0 ? vw.n_mid : 0;
+            Lv.n_high = i == 0 ? vw.n_high : 0;
+            Lv.n = (int32_t)vitems[i].size() - Lv.n_mid - Lv.n_high;
+            b->vl.push_back(Lv);
         }
         for (size_t i = 0; i < fitems.size() && e == hipSuccess; ++i) {
             e = hipMemcpyAsync(b->dmem + foff[i], fitems[i].data(), sizeof(WorkItem) * fitems[i].size(),

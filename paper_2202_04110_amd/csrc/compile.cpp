@@ -251,7 +251,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
             int32_t flip = d->factor_kind[f] == LBP_FACTOR_AND;
             if (k <= kLogLaneArityMax)
                 key = Key(TK_LOGL, k, flip, -1, std::vector<int32_t>());
-            else  // one tile per factor; grouped by chunk bucket
+            else  // one tile per factor
                 key = Key(TK_LOGW, chunk_bucket((k + kLanes - 1) / kLanes), 0, -1, std::vector<int32_t>());
         }
         auto it = class_of.find(key);
@@ -417,11 +417,18 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                 L->ftile.push_back(ft);
             }
         }
-        // LOGW groups of the same bucket merge; others are one class each
+        // logical tiles of at most 4 chunks share one launch group; wider ones
+        // another; pairwise and generic classes are one group each
+        if (kind == TK_LOGL || (kind == TK_LOGW && grp.a <= 4)) {
+            grp.kind = TK_LOGL;
+            grp.a = 0;
+        } else if (kind == TK_LOGW) {
+            grp.a = 0;
+        }
         bool merged = false;
-        if (kind == TK_LOGW)
+        if (grp.kind == TK_LOGL || grp.kind == TK_LOGW)
             for (FGroup &g : L->fgroups)
-                if (g.kind == TK_LOGW && g.a == grp.a) {
+                if (g.kind == grp.kind) {
                     g.tiles.insert(g.tiles.end(), grp.tiles.begin(), grp.tiles.end());
                     merged = true;
                 }
@@ -440,7 +447,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
         const int64_t v0 = t * kLanes, v1 = std::min<int64_t>(V, v0 + kLanes);
         for (int64_t v = v0; v < v1; ++v) {
             int64_t deg = adj_off[v + 1] - adj_off[v];
-            bool low = deg <= kLowDegMax && L->vn[v] <= kLowStatesMax;
+            const bool low = deg <= kLowDegMax && L->vn[v] <= kLowStatesMax;
             if (low) {
                 kmax = std::max<int32_t>(kmax, (int32_t)deg);
                 nlow = std::max<int32_t>(nlow, L->vn[v]);
@@ -452,6 +459,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                 h.e_begin = (int32_t)L->hedge.size();
                 for (int64_t i = adj_off[v]; i < adj_off[v + 1]; ++i) L->hedge.push_back(L->edge_maddr[adj[i]]);
                 h.e_end = (int32_t)L->hedge.size();
+                (deg <= kMidDegMax ? L->mids : L->highs).push_back((int32_t)L->hvar.size());
                 L->hvar.push_back(h);
             }
         }
@@ -521,7 +529,13 @@ int check_layout(const HostLayout &L, std::string *err) {
                 }
             }
         }
-    // variable phase, high-degree variables
+    // variable phase, wavefront- and block-per-variable paths
+    for (int32_t i : L.mids)
+        if (!in(i, (int64_t)L.hvar.size()) || L.hvar[i].e_end - L.hvar[i].e_begin > kMidDegMax)
+            return oob("wavefront-per-variable entry");
+    for (int32_t i : L.highs)
+        if (!in(i, (int64_t)L.hvar.size())) return oob("block-per-variable entry");
+    if (L.mids.size() + L.highs.size() != L.hvar.size()) return oob("variable path lists");
     for (const HVar &h : L.hvar) {
         if (h.e_begin < 0 || h.e_end < h.e_begin || h.e_end > (int64_t)L.hedge.size()) return oob("hedge range");
         for (int32_t s = 0; s < h.n; ++s) {
@@ -545,7 +559,9 @@ int check_layout(const HostLayout &L, std::string *err) {
         for (int32_t t : fg.tiles) {
             if (!in(t, (int64_t)L.ftile.size())) return oob("factor tile index");
             const FTile &ft = L.ftile[t];
-            if (ft.kind != fg.kind) return oob("tile kind differs from its launch group");
+            const bool kind_ok = ft.kind == fg.kind ||
+                                 (fg.kind == TK_LOGL && ft.kind == TK_LOGW && ft.a <= 4 * kLanes);
+            if (!kind_ok) return oob("tile kind differs from its launch group");
             if (ft.kind == TK_PAIR) {
                 const int32_t ns[2] = {ft.a, ft.b};
                 if (ft.a > kPairStatesMax || ft.b > kPairStatesMax) return oob("pair states");
@@ -560,7 +576,8 @@ int check_layout(const HostLayout &L, std::string *err) {
                 if (!in(ft.m_off + (int64_t)2 * ft.a * kLanes - 1, M)) return oob("lane logical messages");
             } else if (ft.kind == TK_LOGW) {
                 const int32_t ch = (ft.a + kLanes - 1) / kLanes;
-                if (ft.a < 2 || ft.a > kLogWaveArityMax || ch > fg.a) return oob("wave logical arity/bucket");
+                if (ft.a < 2 || ft.a > kLogWaveArityMax || (fg.kind == TK_LOGL && ch > 4))
+                    return oob("wave logical arity/bucket");
                 for (int32_t j = 0; j < ft.a; ++j) {
                     const int64_t i = ft.vb_off + j;
                     if (!in(i, (int64_t)L.fvb.size()) || !in(L.fvb[i] + kLanes, VB)) return oob("wave logical beliefs");

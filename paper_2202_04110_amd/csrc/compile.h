@@ -10,10 +10,12 @@
 
 namespace lbp {
 
-// Factor tiles launched together: same kernel, same shape.
+// Factor tiles launched together: same kernel, same shape.  TK_LOGL groups
+// hold every logical tile of at most 256 edges (lane- and wavefront-per-factor
+// tiles share one kernel); TK_LOGW groups hold the wider ones.
 struct FGroup {
     int32_t kind;  // TK_*
-    int32_t a, b;  // PAIR: slot state counts; LOGW: chunk count bucket; otherwise 0
+    int32_t a, b;  // PAIR: slot state counts; otherwise 0
     std::vector<int32_t> tiles;
 };
 
@@ -33,6 +35,7 @@ struct HostLayout {
     std::vector<int32_t> vedge, vns;
     std::vector<HVar> hvar;
     std::vector<int32_t> hedge;
+    std::vector<int32_t> mids, highs;  // indices into hvar: wavefront- / block-per-variable paths
     std::vector<GenClass> gcls;
     std::vector<uint8_t> grows;
     std::vector<int32_t> edge_maddr;

@@ -26,14 +26,16 @@ struct AdjBufs {
     float *phibar;
 };
 
-hipError_t launch_belief_low(const DevGraph *gs, const WorkItem *items, int n, int bucket, hipStream_t st);
-hipError_t launch_belief_high(const DevGraph *gs, const WorkItem *items, int n, hipStream_t st);
+// Variable phase: items = n_low low tiles, then n_mid and n_high variables
+// (indices into the graph's hvar list); bucket >= states of every low lane.
+hipError_t launch_belief(const DevGraph *gs, const WorkItem *items, int n_low, int n_mid, int n_high, int bucket,
+                         hipStream_t st);
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
                        const TParams &P, hipStream_t st);
-hipError_t launch_logl(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
-                       hipStream_t st);
-hipError_t launch_logw(const DevGraph *gs, const WorkItem *items, int n, int chunk_bucket, bool maxp,
-                       const TParams &P, hipStream_t st);
+// Logical tiles: wide = false for lane tiles and factors of <= 256 edges,
+// true for factors of 257..1024 edges.
+hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool wide, bool maxp, const TParams &P,
+                          hipStream_t st);
 hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
                       hipStream_t st);
 // Read-out of a single graph (gs[0]).

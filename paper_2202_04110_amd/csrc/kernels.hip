@@ -73,21 +73,21 @@ __device__ __forceinline__ void damp_store(float *row, const float (&mo)[N], con
 // --------------------------------------------------------------------------
 // variable phase
 // --------------------------------------------------------------------------
+// Three paths, chosen per variable by its degree and state count only:
+//   low  (degree <= 16, <= 16 states): one lane per variable, tiles of 64
+//   mid  (degree <= 64): one wavefront per variable, one edge per lane
+//   high (larger degree): one 256-thread block per variable
+// One launch covers all three: blocks [0, ceil((n_low+n_mid)/4)) run four
+// wavefront items each (low tiles first, then mid variables), the remaining
+// blocks one high variable each.
 
-// One wavefront per variable tile, one lane per variable; NB >= states of
-// every low-degree lane of the tile.  Edge rows are fetched KU at a time (all
-// address loads, then all message loads in flight) and added in edge order.
+// low: NB >= states of every lane; edge rows fetched KU at a time (addresses,
+// then rows, all in flight) and added in edge order.
 template <int NB>
-__global__ __launch_bounds__(256) void k_belief_low(const DevGraph *__restrict__ gs,
-                                                    const WorkItem *__restrict__ items, int nitems) {
+__device__ __forceinline__ void belief_low_tile(const DevGraph &G, int t, int lane) {
     constexpr int KU = NB <= 4 ? 8 : 4;
-    const int w = wave_index(4);
-    if (w >= nitems) return;
-    const int lane = lane_id();
-    const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
-    const VTile vt = G.vtile[it.t];
-    const int n = G.vns[it.t * kLanes + lane];
+    const VTile vt = G.vtile[t];
+    const int n = G.vns[t * kLanes + lane];
     const int base = vt.b_off + lane;
     float acc[NB];
 #pragma unroll
@@ -113,22 +113,40 @@ __global__ __launch_bounds__(256) void k_belief_low(const DevGraph *__restrict__
         if (s < n) G.B[base + s * kLanes] = acc[s];
 }
 
-// One 256-thread block per high-degree variable.  Thread i sums edges
-// i, i+256, ... in order (their addresses, then their rows, fetched together
-// in chunks of 4), then a fixed LDS tree combines the 256 partial sums; the
-// result does not depend on anything but the variable's edge list.
+// mid: lane l holds edge l; a butterfly over the wavefront (every lane ends
+// with the same bits) sums each state.
+__device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int lane) {
+    constexpr int SC = 8;
+    const HVar h = G.hvar[hv];
+    const int k = h.e_begin + lane;
+    const int a = k < h.e_end ? G.hedge[k] : -1;
+    for (int s0 = 0; s0 < h.n; s0 += SC) {
+        float x[SC];
+#pragma unroll
+        for (int j = 0; j < SC; ++j) x[j] = (a >= 0 && s0 + j < h.n) ? G.m[a + (s0 + j) * kLanes] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < SC; ++j) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x[j] += __shfl_xor(x[j], off, 64);
+        }
+        if (lane < SC && s0 + lane < h.n) {
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < SC; ++j)
+                if (j == lane) v = x[j];
+            const int b = h.b_addr + (s0 + lane) * kLanes;
+            G.B[b] = G.theta[b] + v;
+        }
+    }
+}
+
+// high: thread i sums edges i, i+256, ... in order (fetched 4 at a time),
+// then a fixed LDS tree combines the 256 partial sums.
 constexpr int kHighThreads = 256;
-__global__ __launch_bounds__(kHighThreads) void k_belief_high(const DevGraph *__restrict__ gs,
-                                                              const WorkItem *__restrict__ items, int nitems) {
+__device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int tid, float (*red)[kHighThreads]) {
     constexpr int SC = 8;  // states per pass
     constexpr int KC = 4;  // edges per thread fetched together
-    __shared__ float red[SC][kHighThreads];
-    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
-    if (w >= nitems) return;
-    const int tid = threadIdx.x;
-    const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
-    const HVar h = G.hvar[it.t];
+    const HVar h = G.hvar[hv];
     for (int s0 = 0; s0 < h.n; s0 += SC) {
         float part[SC];
 #pragma unroll
@@ -164,11 +182,31 @@ __global__ __launch_bounds__(kHighThreads) void k_belief_high(const DevGraph *__
             __syncthreads();
         }
         if (tid < SC && s0 + tid < h.n) {
-            const int a = h.b_addr + (s0 + tid) * kLanes;
-            G.B[a] = G.theta[a] + red[tid][0];
+            const int b = h.b_addr + (s0 + tid) * kLanes;
+            G.B[b] = G.theta[b] + red[tid][0];
         }
         __syncthreads();
     }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                                int n_low, int n_mid, int n_high) {
+    __shared__ float red[8][kHighThreads];
+    const int nwave = n_low + n_mid;
+    const int wave_blocks = (nwave + 3) / 4;
+    if ((int)blockIdx.x < wave_blocks) {
+        const int w = wave_index(4);
+        if (w >= nwave) return;
+        const WorkItem it = items[w];
+        if (w < n_low) belief_low_tile<NB>(gs[it.g], it.t, lane_id());
+        else belief_mid_var(gs[it.g], it.t, lane_id());
+        return;
+    }
+    const int hb = __builtin_amdgcn_readfirstlane((int)blockIdx.x - wave_blocks);
+    if (hb >= n_high) return;
+    const WorkItem it = items[nwave + hb];
+    belief_high_var(gs[it.g], it.t, threadIdx.x, red);
 }
 
 // --------------------------------------------------------------------------
@@ -285,15 +323,8 @@ __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, c
 
 // one lane per factor, at most kLogLaneArityMax edges
 template <bool MAXP>
-__global__ __launch_bounds__(256) void k_logl(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
-                                              int nitems, TParams P) {
+__device__ __forceinline__ void logl_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
     constexpr int K = kLogLaneArityMax;
-    const int w = wave_index(4);
-    if (w >= nitems) return;
-    const int lane = lane_id();
-    const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
-    const FTile ft = G.ftile[it.t];
     const int k = ft.a, p = k - 1;
     const bool flip = ft.b != 0;
     const float *rows = G.m + ft.m_off + lane;
@@ -372,14 +403,7 @@ __global__ __launch_bounds__(256) void k_logl(const DevGraph *__restrict__ gs, c
 
 // one wavefront per factor; edge j sits in chunk j/64 at lane j%64
 template <int CH, bool MAXP>
-__global__ __launch_bounds__(256) void k_logw(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
-                                              int nitems, TParams P) {
-    const int w = wave_index(4);
-    if (w >= nitems) return;
-    const int lane = lane_id();
-    const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
-    const FTile ft = G.ftile[it.t];
+__device__ __forceinline__ void logw_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
     const int k = ft.a, p = k - 1;
     const int nch = (k + kLanes - 1) / kLanes;
     const bool flip = ft.b != 0;
@@ -493,6 +517,31 @@ __global__ __launch_bounds__(256) void k_logw(const DevGraph *__restrict__ gs, c
             row[kLanes] = w1 - mx;
         }
     }
+}
+
+// All logical tiles of at most 4 chunks (256 edges) in one launch: a
+// wavefront runs a lane-per-factor tile or one wide factor.
+template <bool MAXP>
+__global__ __launch_bounds__(256) void k_logical(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                                 int nitems, TParams P) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    if (ft.kind == TK_LOGL) logl_tile<MAXP>(G, ft, lane_id(), P);
+    else logw_tile<4, MAXP>(G, ft, lane_id(), P);
+}
+
+// logical factors of 257 .. 1024 edges
+template <bool MAXP>
+__global__ __launch_bounds__(256) void k_logical_wide(const DevGraph *__restrict__ gs,
+                                                      const WorkItem *__restrict__ items, int nitems, TParams P) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    logw_tile<kLogWaveChunks, MAXP>(G, G.ftile[it.t], lane_id(), P);
 }
 
 // --------------------------------------------------------------------------
@@ -974,21 +1023,16 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
-hipError_t launch_belief_low(const DevGraph *gs, const WorkItem *items, int n, int bucket, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    dim3 grid(blocks_for(n, 4)), block(256);
+hipError_t launch_belief(const DevGraph *gs, const WorkItem *items, int n_low, int n_mid, int n_high, int bucket,
+                         hipStream_t st) {
+    if (n_low + n_mid + n_high <= 0) return hipSuccess;
+    dim3 grid(blocks_for(n_low + n_mid, 4) + n_high), block(256);
     switch (bucket) {
-    case 2: hipLaunchKernelGGL((k_belief_low<2>), grid, block, 0, st, gs, items, n); break;
-    case 4: hipLaunchKernelGGL((k_belief_low<4>), grid, block, 0, st, gs, items, n); break;
-    case 8: hipLaunchKernelGGL((k_belief_low<8>), grid, block, 0, st, gs, items, n); break;
-    default: hipLaunchKernelGGL((k_belief_low<16>), grid, block, 0, st, gs, items, n); break;
+    case 2: hipLaunchKernelGGL((k_belief<2>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
+    case 4: hipLaunchKernelGGL((k_belief<4>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
+    case 8: hipLaunchKernelGGL((k_belief<8>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
+    default: hipLaunchKernelGGL((k_belief<16>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_belief_high(const DevGraph *gs, const WorkItem *items, int n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_belief_high, dim3(n), dim3(kHighThreads), 0, st, gs, items, n);
     return hipGetLastError();
 }
 
@@ -1019,30 +1063,17 @@ hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na,
     return hipGetLastError();
 }
 
-hipError_t launch_logl(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
-                       hipStream_t st) {
+hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool wide, bool maxp, const TParams &P,
+                          hipStream_t st) {
     if (n <= 0) return hipSuccess;
     dim3 grid(blocks_for(n, 4)), block(256);
-    if (maxp) hipLaunchKernelGGL((k_logl<true>), grid, block, 0, st, gs, items, n, P);
-    else hipLaunchKernelGGL((k_logl<false>), grid, block, 0, st, gs, items, n, P);
-    return hipGetLastError();
-}
-
-hipError_t launch_logw(const DevGraph *gs, const WorkItem *items, int n, int chunk_bucket, bool maxp,
-                       const TParams &P, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    dim3 grid(blocks_for(n, 4)), block(256);
-#define LOGW_CASE(CHV)                                                                          \
-    if (maxp) hipLaunchKernelGGL((k_logw<CHV, true>), grid, block, 0, st, gs, items, n, P);    \
-    else hipLaunchKernelGGL((k_logw<CHV, false>), grid, block, 0, st, gs, items, n, P);
-    if (chunk_bucket <= 1) {
-        LOGW_CASE(1)
-    } else if (chunk_bucket <= 4) {
-        LOGW_CASE(4)
+    if (wide) {
+        if (maxp) hipLaunchKernelGGL((k_logical_wide<true>), grid, block, 0, st, gs, items, n, P);
+        else hipLaunchKernelGGL((k_logical_wide<false>), grid, block, 0, st, gs, items, n, P);
     } else {
-        LOGW_CASE(16)
+        if (maxp) hipLaunchKernelGGL((k_logical<true>), grid, block, 0, st, gs, items, n, P);
+        else hipLaunchKernelGGL((k_logical<false>), grid, block, 0, st, gs, items, n, P);
     }
-#undef LOGW_CASE
     return hipGetLastError();
 }
 

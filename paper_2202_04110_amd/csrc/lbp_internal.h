@@ -17,8 +17,9 @@ namespace lbp {
 
 constexpr int kLanes = 64;
 constexpr int kMaxStates = 64;        // states per variable
-constexpr int kLowDegMax = 64;        // variables with more edges use the wave-per-variable path
-constexpr int kLowStatesMax = 16;     // and so do variables with more states
+constexpr int kLowDegMax = 16;        // lane-per-variable belief path: at most this many edges
+constexpr int kLowStatesMax = 16;     //   and at most this many states
+constexpr int kMidDegMax = 64;        // wavefront-per-variable path up to this degree, block-per-variable above
 constexpr int kPairStatesMax = 8;     // dense pairwise fast path, both slots
 constexpr int kLogLaneArityMax = 8;   // OR/AND with at most this many edges: one lane per factor
 constexpr int kLogWaveArityMax = 1024;  // larger OR/AND: one wavefront per factor
@@ -49,7 +50,7 @@ struct VTile {
     int32_t e_off;    // base of the edge-address rows [k][64]
 };
 
-// A variable handled by the wave-per-variable belief path.
+// A variable handled by the wavefront- or block-per-variable belief path.
 struct HVar {
     int32_t b_addr;   // belief address of state 0
     int32_t n;

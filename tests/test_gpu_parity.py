@@ -151,6 +151,8 @@ STEP_CASES = [
     ("biglogic", lambda: big_logical(5, parents=150), [0.0, 0.3, 1.0]),
     ("biglogic_wide", lambda: big_logical(6, parents=700, nfac=3), [0.0, 1.0]),
     ("star300", lambda: star(7, 300, 3), [0.0, 1.0]),
+    ("star40", lambda: star(11, 40, 4), [0.0, 1.0]),
+    ("star40x20", lambda: star(12, 40, 20), [1.0]),
     ("rect3x5", lambda: rect_pairs(8, 3, 5), [0.0, 1.0]),
     ("potts6x16", lambda: wide_states(9, 16, 6), [0.0, 1.0]),
     ("potts4x30", lambda: wide_states(10, 30, 4), [1.0]),
