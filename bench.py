@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -103,6 +105,36 @@ def cpu_baseline(spec, iters_full, damping, temperature, budget_s=12.0):
                       "%.2f s" % (iters, iters_full, dt)}
 
 
+def serving_leg(lbp, W, ctx, n, budget_mb, seed=5):
+    """Served stream: n Potts requests (side log-uniform 16..256, 2..8
+    states, sum-product T=1, damping 0.5, 50 iterations; 10% carry a backward
+    pass with checkpoints every 10).  Capacity R is measured with every
+    request arriving at once; then Poisson arrivals at 0.5R and 0.8R give
+    p50/p99 latency (completion minus scheduled arrival)."""
+    from paper_2202_04110_amd.serving import run_stream
+
+    reqs = W.served_requests(n, seed=seed, backward_count=max(1, n // 10))
+    specs = [W.request_graph(r) for r in reqs]
+    gqs = [W.request_loss_coeffs(r) if r["backward"] else None for r in reqs]
+    out = {"requests": n, "iters": 50, "budget_mb": budget_mb,
+           "edge_states_mean": float(np.mean([s.num_edge_states for s in specs]))}
+    runs = {}
+    for label, frac in (("burst", None), ("0.5R", 0.5), ("0.8R", 0.8)):
+        srv = lbp.Server(ctx, budget_bytes=budget_mb << 20, max_slots=64, steps_per_round=5)
+        if frac is None:
+            arr = np.zeros(n)
+        else:
+            arr = W.poisson_arrivals(n, qps=frac * runs["burst"]["requests_per_s"], seed=seed)
+        _, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10)
+        srv.close()
+        st = summ.pop("stats")
+        summ["max_resident"] = st["max_resident"]
+        summ["rounds"] = st["rounds"]
+        runs[label] = summ
+    out["runs"] = runs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +143,9 @@ def main():
     ap.add_argument("--workload", default="potts512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=200)
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="also run the served stream with N requests (0: skip)")
+    ap.add_argument("--serving-budget-mb", type=int, default=2048)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 5 times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -120,7 +155,6 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np  # noqa: F401
     import torch
 
     if args.copy_calibration:
@@ -199,6 +233,8 @@ def main():
         "kernel_src_sha": kernel_source_sha(),
         "device": torch.cuda.get_device_name(0),
     }
+    if args.serving:
+        out["serving"] = serving_leg(lbp, W, ctx, args.serving, args.serving_budget_mb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, iters, d, T)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

@@ -60,6 +60,7 @@ enum { LBP_FACTOR_ENUM = 0, LBP_FACTOR_OR = 1, LBP_FACTOR_AND = 2 };
 typedef struct lbp_ctx lbp_ctx;
 typedef struct lbp_graph lbp_graph;
 typedef struct lbp_batch lbp_batch;
+typedef struct lbp_server lbp_server;
 
 /*
  * Factor graph description (all host pointers).  The flat-array form of the
@@ -240,6 +241,65 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
                      lbp_batch **out);
 int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature);
 void lbp_batch_free(lbp_batch *b);
+
+/*
+ * Serving with continuous batching.  Requests arrive while others run: a
+ * worker thread admits queued requests first-in first-out whenever a slot
+ * is free and the server's memory arena (one device allocation of
+ * hbm_budget_bytes) has room for the graph, its messages and, for backward
+ * requests, the checkpoint workspace.  Admitted graphs are uploaded on a copy
+ * stream while the compute stream advances every resident graph by up to
+ * steps_per_round iterations per round in shared multi-graph launches (the
+ * batch form above); graphs join and leave at round boundaries, and their
+ * messages stay resident in between.  Results are bitwise equal to lone runs.
+ */
+typedef struct lbp_completion {
+    uint64_t req_id;
+    int32_t status;            /* LBP_OK, LBP_E_NONFINITE, LBP_E_STATE (cancelled), other errors */
+    int32_t reserved;
+    int64_t num_vars, num_var_states, num_logpots;
+    const float *beliefs;      /* VS normalised beliefs (host), NULL on failure */
+    const int32_t *map;        /* V MAP states (host), NULL on failure */
+    const float *grad_logpot;  /* Tn gradient (host) for backward requests, else NULL */
+    double t_arrival, t_admit, t_done;  /* seconds on the server clock */
+} lbp_completion;
+
+/* Server on ctx's device with an arena of hbm_budget_bytes, at most max_slots
+ * resident requests and at most steps_per_round iterations per round.  The
+ * server owns its streams and arena; ctx is only read for its device. */
+int lbp_server_create(lbp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, int32_t steps_per_round,
+                      lbp_server **out);
+/* The same scheduler with a bookkeeping-only executor: no GPU is touched,
+ * completions carry zero-filled outputs.  For tests of admission and
+ * queueing on hosts without a GPU. */
+int lbp_server_create_host_only(int64_t budget_bytes, int32_t max_slots, int32_t steps_per_round, lbp_server **out);
+/* Seconds since the server was created (the clock of every timestamp). */
+double lbp_server_clock(const lbp_server *s);
+/* Queues a request; the description (host arrays) is compiled and copied
+ * before return.  grad_q (host, VS floats) != NULL asks for the gradient of
+ * sum(grad_q * q) w.r.t. the log-potentials (T > 0, enumeration factors
+ * only), with checkpoints every ckpt_every iterations.  t_arrival: the
+ * request's arrival time on the server clock (its latency is measured from
+ * it), or < 0 for "now".  Returns LBP_E_BUDGET if the request alone exceeds
+ * the budget, LBP_E_INVALID / LBP_E_UNSUPPORTED as lbp_graph_upload and
+ * lbp_run_bp_record would. */
+int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, float damping, float temperature,
+                      const float *grad_q, int32_t ckpt_every, double t_arrival, uint64_t req_id);
+/* Marks a queued or resident request cancelled; it completes with
+ * LBP_E_STATE at the next round boundary. */
+int lbp_server_cancel(lbp_server *s, uint64_t req_id);
+/* Moves up to max finished requests into out[0 .. *n_out-1].  Their output
+ * pointers stay valid until the next poll or lbp_server_destroy. */
+int lbp_server_poll(lbp_server *s, lbp_completion *out, int32_t max, int32_t *n_out);
+/* Waits until every accepted request has finished (LBP_E_STATE on timeout). */
+int lbp_server_drain(lbp_server *s, double timeout_s);
+/* out[12] = {accepted, finished, completed, rejected at submit, failed,
+ * cancelled, rounds, resident now, queued now, max resident, arena peak bytes,
+ * worker busy microseconds}. */
+int lbp_server_stats(lbp_server *s, int64_t out[12]);
+/* Stops the worker (queued and resident requests are dropped) and frees
+ * everything. */
+void lbp_server_destroy(lbp_server *s);
 
 /* Diagnostic timing: runs `reps` launches of one phase of an iteration on the
  * current messages and returns the mean launch time in milliseconds measured

@@ -1,0 +1,502 @@
+// Internal runtime shared by the C-ABI and the serving loop (see runtime.h).
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace lbp {
+
+namespace {
+thread_local std::string t_err;
+}
+
+int set_error(int code, const std::string &msg) {
+    t_err = msg;
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what) {
+    return set_error(LBP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const char *last_error() { return t_err.c_str(); }
+
+bool valid_params(int32_t iters, float d, float T, std::string *why) {
+    if (iters < 0) {
+        *why = "iters < 0";
+        return false;
+    }
+    if (!(d >= 0.0f && d <= 1.0f)) {
+        *why = "damping outside [0, 1]";
+        return false;
+    }
+    if (!(T >= 0.0f) || !std::isfinite(T)) {
+        *why = "temperature must be finite and >= 0";
+        return false;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------ launch lists
+void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<WorkItem> *mids,
+                  std::vector<WorkItem> *highs) {
+    for (const VGroup &vg : s.vgroups) {
+        size_t i = 0;
+        while (i < ll.vbucket.size() && ll.vbucket[i] != vg.bucket) ++i;
+        if (i == ll.vbucket.size()) {
+            ll.vbucket.push_back(vg.bucket);
+            ll.vitems.emplace_back();
+        }
+        for (int32_t t : vg.tiles) ll.vitems[i].push_back(WorkItem{gi, t});
+    }
+    for (int32_t h : s.mids) mids->push_back(WorkItem{gi, h});
+    for (int32_t h : s.highs) highs->push_back(WorkItem{gi, h});
+    for (const FGroup &fg : s.fgroups) {
+        size_t i = 0;
+        while (i < ll.fshape.size() &&
+               !(ll.fshape[i].kind == fg.kind && ll.fshape[i].a == fg.a && ll.fshape[i].b == fg.b))
+            ++i;
+        if (i == ll.fshape.size()) {
+            FGroup sh;
+            sh.kind = fg.kind;
+            sh.a = fg.a;
+            sh.b = fg.b;
+            ll.fshape.push_back(sh);
+            ll.fitems.emplace_back();
+        }
+        for (int32_t t : fg.tiles) ll.fitems[i].push_back(WorkItem{gi, t});
+    }
+}
+
+void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs) {
+    if (mids.empty() && highs.empty()) return;
+    if (ll.vbucket.empty()) {
+        ll.vbucket.push_back(2);
+        ll.vitems.emplace_back();
+    }
+    ll.n_mid = (int32_t)mids.size();
+    ll.n_high = (int32_t)highs.size();
+    ll.vitems[0].insert(ll.vitems[0].end(), mids.begin(), mids.end());
+    ll.vitems[0].insert(ll.vitems[0].end(), highs.begin(), highs.end());
+}
+
+size_t lists_bytes(const LaunchLists &ll) {
+    size_t b = 0;
+    for (const auto &v : ll.vitems) b += align256(std::max<size_t>(1, v.size()) * sizeof(WorkItem));
+    for (const auto &v : ll.fitems) b += align256(std::max<size_t>(1, v.size()) * sizeof(WorkItem));
+    return b;
+}
+
+hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::vector<Launch> *vl,
+                        std::vector<Launch> *fl) {
+    vl->clear();
+    fl->clear();
+    size_t off = 0;
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ll.vitems.size() && e == hipSuccess; ++i) {
+        const auto &v = ll.vitems[i];
+        if (!v.empty()) e = hipMemcpyAsync(mem + off, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice, st);
+        Launch L{-1, ll.vbucket[i], 0, 0, (WorkItem *)(mem + off)};
+        L.n_mid = i == 0 ? ll.n_mid : 0;
+        L.n_high = i == 0 ? ll.n_high : 0;
+        L.n = (int32_t)v.size() - L.n_mid - L.n_high;
+        vl->push_back(L);
+        off += align256(std::max<size_t>(1, v.size()) * sizeof(WorkItem));
+    }
+    for (size_t i = 0; i < ll.fitems.size() && e == hipSuccess; ++i) {
+        const auto &v = ll.fitems[i];
+        if (!v.empty()) e = hipMemcpyAsync(mem + off, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice, st);
+        fl->push_back(Launch{ll.fshape[i].kind, ll.fshape[i].a, ll.fshape[i].b, (int32_t)v.size(),
+                             (WorkItem *)(mem + off)});
+        off += align256(std::max<size_t>(1, v.size()) * sizeof(WorkItem));
+    }
+    return e;
+}
+
+hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, const std::vector<Launch> &fl,
+                            const TParams &P, bool maxp, hipStream_t st, int phases) {
+    hipError_t e = hipSuccess;
+    if (phases & 1)
+        for (const Launch &L : vl) {
+            e = launch_belief(gs, L.items, L.n, L.n_mid, L.n_high, L.a, st);
+            if (e != hipSuccess) return e;
+        }
+    if (phases & 2)
+        for (const Launch &L : fl) {
+            switch (L.kind) {
+            case TK_PAIR: e = launch_pair(gs, L.items, L.n, L.a, L.b, maxp, P, st); break;
+            case TK_LOGL: e = launch_logical(gs, L.items, L.n, false, maxp, P, st); break;
+            case TK_LOGW: e = launch_logical(gs, L.items, L.n, true, maxp, P, st); break;
+            default: e = launch_gen(gs, L.items, L.n, maxp, P, st); break;
+            }
+            if (e != hipSuccess) return e;
+        }
+    return e;
+}
+
+// ------------------------------------------------------------ captured loops
+namespace {
+constexpr size_t kMaxCachedLoops = 4;
+}
+
+void destroy_loops(std::vector<CachedLoop> &v) {
+    for (CachedLoop &c : v) (void)hipGraphExecDestroy(c.exec);
+    v.clear();
+}
+
+hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const std::vector<Launch> &vl,
+                    const std::vector<Launch> &fl, int32_t iters, float d, float T) {
+    const TParams P = make_params(d, T);
+    const bool maxp = T == 0.0f;
+    const size_t per_iter = vl.size() + fl.size();
+    if (!ctx->use_graphs || iters < 2 || per_iter == 0) {
+        for (int32_t it = 0; it < iters; ++it) {
+            hipError_t e = launch_iteration(gs, vl, fl, P, maxp, ctx->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    for (const CachedLoop &c : cache)
+        if (c.iters == iters && c.d == d && c.T == T) return hipGraphLaunch(c.exec, ctx->stream);
+    if (!ctx->capture) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int32_t it = 0; it < iters && le == hipSuccess; ++it)
+        le = launch_iteration(gs, vl, fl, P, maxp, ctx->capture);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le != hipSuccess ? le : e;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (cache.size() >= kMaxCachedLoops) {
+        (void)hipGraphExecDestroy(cache.front().exec);
+        cache.erase(cache.begin());
+    }
+    cache.push_back(CachedLoop{iters, d, T, exec});
+    return hipGraphLaunch(exec, ctx->stream);
+}
+
+// ------------------------------------------------------------ graph memory
+namespace {
+
+struct Piece {
+    const void *src;
+    size_t bytes;
+    size_t off;
+};
+
+// The pieces of one graph's allocation in a fixed order (shared by the size
+// query and the upload).
+struct GraphPieces {
+    std::vector<Piece> p;
+    size_t total = 0;
+    size_t m, B, th, phi, ft, fvb, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
+    LaunchLists ll;
+
+    explicit GraphPieces(const HostLayout &L) {
+        auto add = [&](const void *src, size_t bytes) {
+            p.push_back(Piece{src, bytes, total});
+            total += align256(std::max<size_t>(bytes, 4));
+            return p.size() - 1;
+        };
+        m = add(nullptr, sizeof(float) * L.M);
+        B = add(nullptr, sizeof(float) * L.VB);
+        th = add(L.theta_panel.data(), sizeof(float) * L.VB);
+        phi = add(L.phi_panel.data(), sizeof(float) * L.P);
+        ft = add(L.ftile.data(), sizeof(FTile) * L.ftile.size());
+        fvb = add(L.fvb.data(), sizeof(int32_t) * L.fvb.size());
+        vt = add(L.vtile.data(), sizeof(VTile) * L.vtile.size());
+        ve = add(L.vedge.data(), sizeof(int32_t) * L.vedge.size());
+        vns = add(L.vns.data(), sizeof(int32_t) * L.vns.size());
+        hv = add(L.hvar.data(), sizeof(HVar) * L.hvar.size());
+        he = add(L.hedge.data(), sizeof(int32_t) * L.hedge.size());
+        gc = add(L.gcls.data(), sizeof(GenClass) * L.gcls.size());
+        gr = add(L.grows.data(), L.grows.size());
+        em = add(L.edge_maddr.data(), sizeof(int32_t) * L.edge_maddr.size());
+        es = add(L.es_off.data(), sizeof(int64_t) * L.es_off.size());
+        vs = add(L.vs_off.data(), sizeof(int64_t) * L.vs_off.size());
+        vn = add(L.vn.data(), sizeof(int32_t) * L.vn.size());
+        fp = add(L.fac_phi.data(), sizeof(int32_t) * L.fac_phi.size());
+        lp = add(L.lp_off.data(), sizeof(int64_t) * L.lp_off.size());
+        fl = add(nullptr, sizeof(int32_t) * 4);
+        dg = add(nullptr, sizeof(DevGraph));
+        q = add(nullptr, sizeof(float) * L.VS);
+        map = add(nullptr, sizeof(int32_t) * L.V);
+        GraphShape s{L.fgroups, L.vgroups, L.mids, L.highs};
+        std::vector<WorkItem> mids, highs;
+        add_to_lists(ll, 0, s, &mids, &highs);
+        finish_lists(ll, mids, highs);
+        items = add(nullptr, lists_bytes(ll));
+    }
+};
+
+}  // namespace
+
+size_t graph_device_bytes(const HostLayout &L) { return GraphPieces(L).total; }
+
+int graph_create(lbp_ctx *ctx, const HostLayout &L, char *mem, hipStream_t st, lbp_graph **out) {
+    lbp_graph *g = nullptr;
+    try {
+        GraphPieces gp(L);
+        g = new lbp_graph;
+        g->ctx = ctx;
+        if (mem) {
+            g->dmem = mem;
+            g->owns_memory = false;
+        } else {
+            hipError_t e = hipMalloc((void **)&g->dmem, gp.total);
+            if (e != hipSuccess) {
+                delete g;
+                (void)hipGetLastError();
+                return set_error(LBP_E_OOM, "device allocation of " + std::to_string(gp.total) + " bytes failed");
+            }
+        }
+        g->dbytes = gp.total;
+        auto ptr = [&](size_t i) { return (void *)(g->dmem + gp.p[i].off); };
+        hipError_t e = hipSuccess;
+        for (const Piece &p : gp.p)
+            if (p.src && p.bytes) {
+                e = hipMemcpyAsync(g->dmem + p.off, p.src, p.bytes, hipMemcpyHostToDevice, st);
+                if (e != hipSuccess) break;
+            }
+        if (e == hipSuccess) e = hipMemsetAsync(ptr(gp.m), 0, sizeof(float) * L.M, st);
+        if (e == hipSuccess) e = hipMemsetAsync(ptr(gp.B), 0, sizeof(float) * L.VB, st);
+        if (e == hipSuccess) e = hipMemsetAsync(ptr(gp.fl), 0, sizeof(int32_t) * 4, st);
+        DevGraph &h = g->host;
+        h.m = (float *)ptr(gp.m);
+        h.mo = h.m;
+        h.B = (float *)ptr(gp.B);
+        h.theta = (float *)ptr(gp.th);
+        h.phi = (float *)ptr(gp.phi);
+        h.ftile = (const FTile *)ptr(gp.ft);
+        h.fvb = (const int32_t *)ptr(gp.fvb);
+        h.vtile = (const VTile *)ptr(gp.vt);
+        h.vedge = (const int32_t *)ptr(gp.ve);
+        h.vns = (const int32_t *)ptr(gp.vns);
+        h.hvar = (const HVar *)ptr(gp.hv);
+        h.hedge = (const int32_t *)ptr(gp.he);
+        h.gcls = (const GenClass *)ptr(gp.gc);
+        h.grows = (const uint8_t *)ptr(gp.gr);
+        h.edge_maddr = (const int32_t *)ptr(gp.em);
+        h.es_off = (const int64_t *)ptr(gp.es);
+        h.vs_off = (const int64_t *)ptr(gp.vs);
+        h.vn = (const int32_t *)ptr(gp.vn);
+        h.fac_phi = (const int32_t *)ptr(gp.fp);
+        h.lp_off = (const int64_t *)ptr(gp.lp);
+        h.flag = (int32_t *)ptr(gp.fl);
+        h.V = (int32_t)L.V;
+        h.E = (int32_t)L.E;
+        h.F = (int32_t)L.F;
+        h.zero_addr = L.zero_addr;
+        g->dgraph = (DevGraph *)ptr(gp.dg);
+        g->q_tmp = (float *)ptr(gp.q);
+        g->map_tmp = (int32_t *)ptr(gp.map);
+        if (e == hipSuccess) e = hipMemcpyAsync(g->dgraph, &g->host, sizeof(DevGraph), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = upload_lists(gp.ll, (char *)ptr(gp.items), st, &g->vl, &g->fl);
+        // the host staging (L, gp) must outlive the copies
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            if (g->owns_memory) (void)hipFree(g->dmem);
+            delete g;
+            return hip_error(e, "graph upload");
+        }
+        g->shape = GraphShape{L.fgroups, L.vgroups, L.mids, L.highs};
+        for (const FGroup &fg : L.fgroups)
+            if (fg.kind == TK_LOGL || fg.kind == TK_LOGW) g->has_logical = true;
+        g->V = L.V; g->VS = L.VS; g->F = L.F; g->E = L.E; g->ES = L.ES; g->Tn = L.Tn;
+        g->M = L.M; g->VB = L.VB; g->P = L.P;
+        g->nvt = (int32_t)L.vtile.size();
+        *out = g;
+        return LBP_OK;
+    } catch (const std::bad_alloc &) {
+        if (g) {
+            if (g->dmem && g->owns_memory) (void)hipFree(g->dmem);
+            delete g;
+        }
+        return set_error(LBP_E_OOM, "host allocation failed");
+    }
+}
+
+void graph_destroy(lbp_graph *g) {
+    if (!g) return;
+    destroy_loops(g->loops);
+    if (g->adj.dmem && g->adj.owns_memory) (void)hipFree(g->adj.dmem);
+    if (g->owns_memory) (void)hipFree(g->dmem);
+    delete g;
+}
+
+int graph_readout(lbp_graph *g, float *q, int normalized, int32_t *map, bool on_device, hipStream_t st) {
+    const TParams P = make_params(0.5f, g->last_T);
+    const bool maxp = g->last_T == 0.0f;
+    hipError_t e = launch_iteration(g->dgraph, g->vl, g->fl, P, maxp, st, 1);
+    if (e != hipSuccess) return hip_error(e, "belief launch");
+    float *qd = q ? (on_device ? q : g->q_tmp) : nullptr;
+    int32_t *md = map ? (on_device ? map : g->map_tmp) : nullptr;
+    HIP_TRY(launch_readout(g->dgraph, g->nvt, maxp, P, qd, normalized, md, st));
+    if (on_device) return LBP_OK;
+    if (q) HIP_TRY(hipMemcpyAsync(q, g->q_tmp, sizeof(float) * g->VS, hipMemcpyDeviceToHost, st));
+    if (map) HIP_TRY(hipMemcpyAsync(map, g->map_tmp, sizeof(int32_t) * g->V, hipMemcpyDeviceToHost, st));
+    return LBP_OK;
+}
+
+// ------------------------------------------------------------ reverse sweep
+namespace {
+
+struct AdjLayout {
+    size_t ck, seg, A, nb, Bb, Bt, z, tb, pb, v, total;
+    AdjLayout(size_t M, size_t VB, size_t P, int32_t nseg, int32_t k) {
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off += align256(std::max<size_t>(bytes, 4));
+            return o;
+        };
+        ck = take(sizeof(float) * M * std::max(nseg, 1));
+        seg = take(sizeof(float) * M * k);
+        A = take(sizeof(float) * M);
+        nb = take(sizeof(float) * M);
+        Bb = take(sizeof(float) * VB);
+        Bt = take(sizeof(float) * VB);
+        z = take(sizeof(float) * VB);
+        tb = take(sizeof(float) * VB);
+        pb = take(sizeof(float) * P);
+        v = take(sizeof(DevGraph) * (k + 2));
+        total = off;
+    }
+};
+
+void record_shape(int32_t iters, int32_t ckpt_every, int32_t *k, int32_t *nseg) {
+    *k = std::min<int32_t>(ckpt_every, std::max<int32_t>(iters, 1));
+    *nseg = (iters + *k - 1) / *k;
+}
+
+}  // namespace
+
+size_t adjoint_bytes(int64_t M, int64_t VB, int64_t P, int32_t iters, int32_t ckpt_every) {
+    int32_t k, nseg;
+    record_shape(iters, ckpt_every, &k, &nseg);
+    return AdjLayout((size_t)M, (size_t)VB, (size_t)P, nseg, k).total;
+}
+
+int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_every, char *mem, hipStream_t st) {
+    auto &J = g->adj;
+    J.valid = false;
+    int32_t k, nseg;
+    record_shape(iters, ckpt_every, &k, &nseg);
+    const AdjLayout al((size_t)g->M, (size_t)g->VB, (size_t)g->P, nseg, k);
+    if (mem) {
+        if (J.dmem && J.owns_memory) {
+            HIP_TRY(hipStreamSynchronize(st));
+            (void)hipFree(J.dmem);
+        }
+        J.dmem = mem;
+        J.bytes = al.total;
+        J.owns_memory = false;
+    } else if (!J.owns_memory || al.total > J.bytes) {
+        if (J.dmem && J.owns_memory) {
+            HIP_TRY(hipStreamSynchronize(st));
+            (void)hipFree(J.dmem);
+        }
+        J.dmem = nullptr;
+        J.bytes = 0;
+        J.owns_memory = true;
+        hipError_t e = hipMalloc((void **)&J.dmem, al.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            J.dmem = nullptr;
+            return set_error(LBP_E_OOM, "adjoint workspace of " + std::to_string(al.total) + " bytes");
+        }
+        J.bytes = al.total;
+    }
+    const size_t M = (size_t)g->M, VB = (size_t)g->VB;
+    J.ckpt = (float *)(J.dmem + al.ck);
+    J.seg = (float *)(J.dmem + al.seg);
+    J.A = (float *)(J.dmem + al.A);
+    J.nbar = (float *)(J.dmem + al.nb);
+    J.Bbar = (float *)(J.dmem + al.Bb);
+    J.Bt = (float *)(J.dmem + al.Bt);
+    J.zeros = (float *)(J.dmem + al.z);
+    J.thetabar = (float *)(J.dmem + al.tb);
+    J.phibar = (float *)(J.dmem + al.pb);
+    J.views = (DevGraph *)(J.dmem + al.v);
+    // zero panels of the iterate buffers and of nbar must read as zero
+    HIP_TRY(hipMemsetAsync(J.seg, 0, sizeof(float) * M * k, st));
+    HIP_TRY(hipMemsetAsync(J.nbar, 0, sizeof(float) * M, st));
+    HIP_TRY(hipMemsetAsync(J.zeros, 0, sizeof(float) * VB, st));
+    std::vector<DevGraph> views(k + 2, g->host);
+    for (int32_t j = 0; j < k; ++j) {
+        views[j].m = J.seg + M * j;
+        views[j].mo = J.seg + M * std::min(j + 1, k - 1);
+        views[j].B = J.Bt;
+    }
+    views[k].B = J.Bt;
+    views[k + 1].m = J.nbar;
+    views[k + 1].mo = J.nbar;
+    views[k + 1].theta = J.zeros;
+    views[k + 1].B = J.Bbar;
+    HIP_TRY(hipMemcpyAsync(J.views, views.data(), sizeof(DevGraph) * (k + 2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // the host staging of the views must outlive its copy
+    J.iters = iters;
+    J.k = k;
+    J.nseg = nseg;
+    J.d = d;
+    J.T = T;
+    return LBP_OK;
+}
+
+int adjoint_checkpoint(lbp_graph *g, int32_t seg, hipStream_t st) {
+    auto &J = g->adj;
+    HIP_TRY(hipMemcpyAsync(J.ckpt + (size_t)g->M * seg, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st));
+    return LBP_OK;
+}
+
+void adjoint_finish_record(lbp_graph *g) {
+    g->adj.valid = true;
+    g->adj.version = g->version;
+}
+
+int adjoint_backward(lbp_graph *g, const float *grad_q, float *grad_logpot, float *grad_evidence, hipStream_t st) {
+    auto &J = g->adj;
+    const TParams P = make_params(J.d, J.T);
+    const int64_t M = g->M;
+    const int k = J.k;
+    AdjBufs B{J.A, J.nbar, J.Bbar, J.phibar};
+    HIP_TRY(hipMemsetAsync(J.A, 0, sizeof(float) * M, st));
+    HIP_TRY(hipMemsetAsync(J.phibar, 0, sizeof(float) * g->P, st));
+    // read-out adjoint at the recorded final iterate (the graph's messages)
+    hipError_t e = launch_iteration(J.views + k, g->vl, g->fl, P, false, st, 1);
+    if (e == hipSuccess) e = launch_readout_adj(J.views + k, g->nvt, P, grad_q, J.Bbar, J.thetabar, st);
+    for (int32_t sidx = J.nseg - 1; sidx >= 0 && e == hipSuccess; --sidx) {
+        const int32_t len = std::min(k, J.iters - sidx * k);
+        e = hipMemcpyAsync(J.seg, J.ckpt + M * sidx, sizeof(float) * M, hipMemcpyDeviceToDevice, st);
+        for (int32_t j = 0; j + 1 < len && e == hipSuccess; ++j)
+            e = launch_iteration(J.views + j, g->vl, g->fl, P, false, st, 3);
+        for (int32_t j = len - 1; j >= 0 && e == hipSuccess; --j) {
+            e = launch_iteration(J.views + j, g->vl, g->fl, P, false, st, 1);  // B_t
+            for (const Launch &L : g->fl) {
+                if (e != hipSuccess) break;
+                if (L.kind == TK_PAIR) e = launch_pair_adj(J.views + j, L.items, L.n, L.a, L.b, P, B, st);
+                else e = launch_gen_adj(J.views + j, L.items, L.n, P, B, st);
+            }
+            if (e == hipSuccess) e = launch_iteration(J.views + k + 1, g->vl, g->fl, P, false, st, 1);  // Bbar_t
+            if (e == hipSuccess) e = launch_accumulate(J.thetabar, J.Bbar, g->VB, st);
+        }
+    }
+    if (e == hipSuccess) e = launch_logpot_out(g->dgraph, (int)g->F, J.phibar, grad_logpot, st);
+    if (e == hipSuccess && grad_evidence) e = launch_evidence_out(g->dgraph, (int)g->V, J.thetabar, grad_evidence, st);
+    if (e != hipSuccess) return hip_error(e, "backward launch");
+    return LBP_OK;
+}
+
+}  // namespace lbp

@@ -1,0 +1,160 @@
+// Internal runtime of liblbp.so shared by the C-ABI (api.cpp) and the serving
+// loop (server.cpp): contexts, uploaded graphs, launch lists, the iteration
+// driver, read-out and the reverse sweep.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbp.h"
+#include "compile.h"
+#include "kernels.h"
+
+namespace lbp {
+
+// Thread-local last error: set_error returns `code` so callers can
+// `return set_error(...)`.
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+const char *last_error();
+
+#define HIP_TRY(expr)                                          \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return ::lbp::hip_error(e_, #expr); \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+bool valid_params(int32_t iters, float d, float T, std::string *why);
+
+// A set of work items launched by one kernel.
+struct Launch {
+    int32_t kind;     // -1 variable phase, TK_* factor kernels
+    int32_t a, b;     // variable phase: state bucket; PAIR: slot state counts
+    int32_t n;        // items (variable phase: low tiles)
+    WorkItem *items;  // device
+    int32_t n_mid = 0, n_high = 0;  // variable phase: wavefront- and block-per-variable items after the tiles
+};
+
+// Host-side launch lists of one graph or of a set of graphs (graph index gi
+// in each work item), before upload.
+struct LaunchLists {
+    std::vector<int32_t> vbucket;                 // variable launches: state bucket
+    std::vector<std::vector<WorkItem>> vitems;    // tiles, then (first launch only) mids, highs
+    int32_t n_mid = 0, n_high = 0;
+    std::vector<FGroup> fshape;                   // factor launches: kind, a, b
+    std::vector<std::vector<WorkItem>> fitems;
+};
+
+struct GraphShape;  // below
+void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<WorkItem> *mids,
+                  std::vector<WorkItem> *highs);
+void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs);
+// Device bytes of the lists' work items (one 256-aligned piece per launch).
+size_t lists_bytes(const LaunchLists &ll);
+// Copies the lists into `mem` on `st` and fills the launch descriptors.
+hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::vector<Launch> *vl,
+                        std::vector<Launch> *fl);
+
+hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, const std::vector<Launch> &fl,
+                            const TParams &P, bool maxp, hipStream_t st, int phases = 3);
+
+// A captured fixed-iteration loop, replayed with hipGraphLaunch.
+struct CachedLoop {
+    int32_t iters;
+    float d, T;
+    hipGraphExec_t exec;
+};
+void destroy_loops(std::vector<CachedLoop> &v);
+
+// The groups of a compiled graph needed to build launch lists.
+struct GraphShape {
+    std::vector<FGroup> fgroups;
+    std::vector<VGroup> vgroups;
+    std::vector<int32_t> mids, highs;
+};
+
+}  // namespace lbp
+
+struct lbp_ctx {
+    int device;
+    hipStream_t stream;             // the caller's stream (borrowed)
+    hipStream_t capture = nullptr;  // private stream used only to record launch graphs
+    bool use_graphs = true;
+};
+
+struct lbp_graph {
+    lbp_ctx *ctx = nullptr;
+    int64_t V = 0, VS = 0, F = 0, E = 0, ES = 0, Tn = 0, M = 0, VB = 0, P = 0;
+    int32_t nvt = 0;
+    char *dmem = nullptr;
+    size_t dbytes = 0;
+    bool owns_memory = true;
+    lbp::DevGraph host{};             // device pointers, host copy
+    lbp::DevGraph *dgraph = nullptr;  // device copy
+    float *q_tmp = nullptr;           // VS
+    int32_t *map_tmp = nullptr;       // V
+    std::vector<lbp::Launch> vl, fl;  // the graph's own launches
+    lbp::GraphShape shape;
+    float last_T = 0.0f;
+    std::vector<lbp::CachedLoop> loops;
+    bool has_logical = false;
+    uint64_t version = 0;  // bumped by every call that changes messages or inputs
+    // reverse-sweep workspace and the record it belongs to
+    struct Adjoint {
+        bool valid = false;
+        uint64_t version = 0;
+        int32_t iters = 0, k = 0, nseg = 0;
+        float d = 0.0f, T = 0.0f;
+        char *dmem = nullptr;
+        size_t bytes = 0;
+        bool owns_memory = true;
+        float *ckpt = nullptr, *seg = nullptr, *A = nullptr, *nbar = nullptr, *Bbar = nullptr, *Bt = nullptr,
+              *zeros = nullptr, *thetabar = nullptr, *phibar = nullptr;
+        lbp::DevGraph *views = nullptr;  // [0, k): iterates in seg; [k]: current messages; [k+1]: adjoint view
+    } adj;
+};
+
+struct lbp_batch {
+    lbp_ctx *ctx = nullptr;
+    std::vector<lbp_graph *> graphs;
+    char *dmem = nullptr;
+    lbp::DevGraph *dgraphs = nullptr;
+    std::vector<lbp::Launch> vl, fl;
+    std::vector<lbp::CachedLoop> loops;
+};
+
+namespace lbp {
+
+// Runs `iters` iterations on the context's stream: through a cached captured
+// graph when enabled (same kernels and arguments as eager launches), else by
+// launching each kernel.
+hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const std::vector<Launch> &vl,
+                    const std::vector<Launch> &fl, int32_t iters, float d, float T);
+
+// Device bytes an uploaded layout occupies.
+size_t graph_device_bytes(const HostLayout &L);
+// Creates a graph from a compiled (and checked) layout.  mem: a 256-aligned
+// region of graph_device_bytes(L) bytes the caller owns, or nullptr to
+// allocate.  Copies run on `st`, and the call waits for them.
+int graph_create(lbp_ctx *ctx, const HostLayout &L, char *mem, hipStream_t st, lbp_graph **out);
+void graph_destroy(lbp_graph *g);
+
+// Read-out (beliefs and/or MAP) on `st`; host outputs are copied with
+// hipMemcpyAsync and are complete once `st` is synchronised.
+int graph_readout(lbp_graph *g, float *q, int normalized, int32_t *map, bool out_on_device, hipStream_t st);
+
+// Reverse sweep.
+size_t adjoint_bytes(int64_t M, int64_t VB, int64_t P, int32_t iters, int32_t ckpt_every);
+// Sets up the workspace (mem: adjoint_bytes(...) bytes owned by the caller,
+// or nullptr to allocate) and the views for a record of (iters, d, T, k);
+// marks the record invalid until adjoint_finish_record.
+int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_every, char *mem, hipStream_t st);
+// Copies the current messages into checkpoint `seg` on `st`.
+int adjoint_checkpoint(lbp_graph *g, int32_t seg, hipStream_t st);
+void adjoint_finish_record(lbp_graph *g);
+int adjoint_backward(lbp_graph *g, const float *grad_q, float *grad_logpot, float *grad_evidence, hipStream_t st);
+
+}  // namespace lbp

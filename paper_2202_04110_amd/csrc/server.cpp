@@ -1,0 +1,642 @@
+// Serving loop: continuous batching of belief-propagation solves.
+//
+// Requests (a graph, iteration count, damping, temperature and optionally a
+// loss gradient for the reverse sweep) are compiled on the submitting thread
+// and queued.  A worker thread admits queued requests first-in first-out
+// while a slot is free and the memory arena (one device allocation of the
+// HBM budget) has room for the graph, its messages and, for backward
+// requests, the checkpoint workspace.  Admitted graphs are uploaded on a copy
+// stream and stay resident; every round advances all resident graphs by a
+// few iterations in shared multi-graph launches on the compute stream, so
+// uploads overlap compute and requests join and leave at round boundaries.
+// A finished graph is read out (normalised beliefs, MAP and, if asked, the
+// gradient w.r.t. its log-potentials) into pinned host buffers and its memory
+// returns to the arena.
+//
+// The same kernels and per-element arithmetic run whether a graph is alone or
+// in the mix, so served results are bitwise equal to lone runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "arena.h"
+#include "runtime.h"
+
+using namespace lbp;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t id = 0;
+    int32_t iters = 0, k = 10;
+    float d = 0.5f, T = 1.0f;
+    bool backward = false;
+    std::vector<float> grad_q;
+    HostLayout L;
+    size_t bytes = 0, graph_bytes = 0, adj_bytes = 0;
+    size_t off = Arena::kNone;
+    lbp_graph *g = nullptr;
+    int32_t done = 0;
+    int32_t status = LBP_OK;
+    bool cancel = false;
+    double t_arrival = 0, t_admit = -1, t_done = -1;
+    float *q = nullptr;
+    int32_t *map = nullptr;
+    float *gphi = nullptr;
+    float *gq_dev = nullptr, *gphi_dev = nullptr;
+};
+
+// What the scheduler asks of the machine.  The GPU executor runs the HIP
+// path; the host executor only keeps the books (scheduling tests on a host
+// without a GPU).
+class Executor {
+public:
+    virtual ~Executor() {}
+    virtual int admit(Request &r) = 0;
+    virtual int round(const std::vector<Request *> &active, int32_t steps) = 0;
+    virtual int wait() = 0;
+    virtual int finish(Request &r) = 0;
+    virtual void release(Request &r) = 0;
+    virtual int alloc_outputs(Request &r) = 0;
+    virtual void free_outputs(Request &r) = 0;
+};
+
+class HostExecutor : public Executor {
+public:
+    int admit(Request &) override { return LBP_OK; }
+    int round(const std::vector<Request *> &, int32_t) override { return LBP_OK; }
+    int wait() override { return LBP_OK; }
+    int finish(Request &) override { return LBP_OK; }
+    void release(Request &) override {}
+    int alloc_outputs(Request &r) override {
+        r.q = (float *)calloc((size_t)std::max<int64_t>(1, r.L.VS), sizeof(float));
+        r.map = (int32_t *)calloc((size_t)std::max<int64_t>(1, r.L.V), sizeof(int32_t));
+        if (r.backward) r.gphi = (float *)calloc((size_t)std::max<int64_t>(1, r.L.Tn), sizeof(float));
+        return (r.q && r.map && (!r.backward || r.gphi)) ? LBP_OK : LBP_E_OOM;
+    }
+    void free_outputs(Request &r) override {
+        free(r.q);
+        free(r.map);
+        free(r.gphi);
+        r.q = nullptr;
+        r.map = nullptr;
+        r.gphi = nullptr;
+    }
+};
+
+class GpuExecutor : public Executor {
+public:
+    ~GpuExecutor() override {
+        (void)hipSetDevice(ctx_.device);
+        if (compute_) (void)hipStreamSynchronize(compute_);
+        if (copy_) (void)hipStreamSynchronize(copy_);
+        if (stage_) (void)hipFree(stage_);
+        if (base_) (void)hipFree(base_);
+        if (ev_) (void)hipEventDestroy(ev_);
+        if (compute_) (void)hipStreamDestroy(compute_);
+        if (copy_) (void)hipStreamDestroy(copy_);
+    }
+
+    int init(int device, size_t budget) {
+        ctx_.device = device;
+        ctx_.use_graphs = false;
+        HIP_TRY(hipSetDevice(device));
+        HIP_TRY(hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+        ctx_.stream = compute_;
+        hipError_t e = hipMalloc((void **)&base_, std::max<size_t>(budget, 256));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            base_ = nullptr;
+            return set_error(LBP_E_OOM, "server arena of " + std::to_string(budget) + " bytes");
+        }
+        return LBP_OK;
+    }
+
+    // Called on the worker thread before any other call.
+    void bind() { (void)hipSetDevice(ctx_.device); }
+
+    int admit(Request &r) override {
+        char *mem = base_ + r.off;
+        int rc = graph_create(&ctx_, r.L, mem, copy_, &r.g);
+        if (rc != LBP_OK) return rc;
+        r.g->last_T = r.T;
+        if (r.backward) {
+            char *am = mem + Arena::round(r.graph_bytes);
+            rc = adjoint_prepare(r.g, r.iters, r.d, r.T, r.k, am, copy_);
+            if (rc != LBP_OK) return rc;
+            r.gq_dev = (float *)(am + Arena::round(r.adj_bytes));
+            r.gphi_dev = (float *)((char *)r.gq_dev + Arena::round(sizeof(float) * r.L.VS));
+            HIP_TRY(hipMemcpyAsync(r.gq_dev, r.grad_q.data(), sizeof(float) * r.L.VS, hipMemcpyHostToDevice, copy_));
+            HIP_TRY(hipStreamSynchronize(copy_));
+        }
+        return LBP_OK;
+    }
+
+    int round(const std::vector<Request *> &active, int32_t steps) override {
+        std::vector<uint64_t> ids;
+        for (Request *r : active) ids.push_back(r->id);
+        if (ids != ids_) {
+            int rc = rebuild(active);
+            if (rc != LBP_OK) return rc;
+            ids_ = ids;
+        }
+        for (Request *r : active)
+            if (r->backward && r->done % r->g->adj.k == 0 && r->done < r->iters) {
+                int rc = adjoint_checkpoint(r->g, r->done / r->g->adj.k, compute_);
+                if (rc != LBP_OK) return rc;
+            }
+        for (const Part &p : parts_) {
+            const TParams P = make_params(p.d, p.T);
+            for (int32_t it = 0; it < steps; ++it) {
+                hipError_t e = launch_iteration(p.dgs, p.vl, p.fl, P, p.T == 0.0f, compute_);
+                if (e != hipSuccess) return hip_error(e, "served iteration launch");
+            }
+        }
+        HIP_TRY(hipEventRecord(ev_, compute_));
+        return LBP_OK;
+    }
+
+    int wait() override {
+        HIP_TRY(hipEventSynchronize(ev_));
+        return LBP_OK;
+    }
+
+    int finish(Request &r) override {
+        int rc = graph_readout(r.g, r.q, 1, r.map, false, compute_);
+        if (rc != LBP_OK) return rc;
+        if (r.backward) {
+            adjoint_finish_record(r.g);
+            rc = adjoint_backward(r.g, r.gq_dev, r.gphi_dev, nullptr, compute_);
+            if (rc != LBP_OK) return rc;
+            HIP_TRY(hipMemcpyAsync(r.gphi, r.gphi_dev, sizeof(float) * r.L.Tn, hipMemcpyDeviceToHost, compute_));
+        }
+        int32_t flag = 0;
+        HIP_TRY(hipMemcpyAsync(&flag, r.g->host.flag, sizeof(int32_t), hipMemcpyDeviceToHost, compute_));
+        HIP_TRY(hipStreamSynchronize(compute_));
+        return flag ? set_error(LBP_E_NONFINITE, "beliefs contain NaN or infinity") : LBP_OK;
+    }
+
+    void release(Request &r) override {
+        graph_destroy(r.g);  // the arena owns the memory
+        r.g = nullptr;
+        ids_.clear();        // the resident set changes
+    }
+
+    int alloc_outputs(Request &r) override {
+        if (hipHostMalloc((void **)&r.q, sizeof(float) * std::max<int64_t>(1, r.L.VS)) != hipSuccess ||
+            hipHostMalloc((void **)&r.map, sizeof(int32_t) * std::max<int64_t>(1, r.L.V)) != hipSuccess ||
+            (r.backward && hipHostMalloc((void **)&r.gphi, sizeof(float) * std::max<int64_t>(1, r.L.Tn)) != hipSuccess)) {
+            (void)hipGetLastError();
+            free_outputs(r);
+            return set_error(LBP_E_OOM, "pinned output buffers");
+        }
+        return LBP_OK;
+    }
+
+    void free_outputs(Request &r) override {
+        if (r.q) (void)hipHostFree(r.q);
+        if (r.map) (void)hipHostFree(r.map);
+        if (r.gphi) (void)hipHostFree(r.gphi);
+        r.q = nullptr;
+        r.map = nullptr;
+        r.gphi = nullptr;
+    }
+
+private:
+    // Active graphs sharing (damping, temperature) launch together.
+    struct Part {
+        float d, T;
+        std::vector<DevGraph> hgs;
+        LaunchLists ll;
+        DevGraph *dgs = nullptr;
+        std::vector<Launch> vl, fl;
+    };
+
+    int rebuild(const std::vector<Request *> &active) {
+        parts_.clear();
+        for (Request *r : active) {
+            Part *p = nullptr;
+            for (Part &q : parts_)
+                if (q.d == r->d && q.T == r->T) p = &q;
+            if (!p) {
+                parts_.push_back(Part{});
+                p = &parts_.back();
+                p->d = r->d;
+                p->T = r->T;
+            }
+            p->hgs.push_back(r->g->host);
+        }
+        size_t total = 0;
+        std::vector<std::vector<WorkItem>> mids(parts_.size()), highs(parts_.size());
+        for (size_t i = 0; i < parts_.size(); ++i) {
+            int32_t gi = 0;
+            for (Request *r : active)
+                if (r->d == parts_[i].d && r->T == parts_[i].T)
+                    add_to_lists(parts_[i].ll, gi++, r->g->shape, &mids[i], &highs[i]);
+            finish_lists(parts_[i].ll, mids[i], highs[i]);
+            total += align256(sizeof(DevGraph) * parts_[i].hgs.size()) + lists_bytes(parts_[i].ll);
+        }
+        if (total > stage_bytes_) {
+            if (stage_) (void)hipFree(stage_);
+            stage_ = nullptr;
+            stage_bytes_ = 0;
+            hipError_t e = hipMalloc((void **)&stage_, total * 2);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return set_error(LBP_E_OOM, "launch staging buffer");
+            }
+            stage_bytes_ = total * 2;
+        }
+        size_t off = 0;
+        for (Part &p : parts_) {
+            p.dgs = (DevGraph *)(stage_ + off);
+            HIP_TRY(hipMemcpyAsync(p.dgs, p.hgs.data(), sizeof(DevGraph) * p.hgs.size(), hipMemcpyHostToDevice,
+                                   compute_));
+            off += align256(sizeof(DevGraph) * p.hgs.size());
+            HIP_TRY(upload_lists(p.ll, stage_ + off, compute_, &p.vl, &p.fl));
+            off += lists_bytes(p.ll);
+        }
+        // the host staging (parts_) lives until the next rebuild, which only
+        // happens after the round that used it has been waited for
+        return LBP_OK;
+    }
+
+    lbp_ctx ctx_{};
+    hipStream_t compute_ = nullptr, copy_ = nullptr;
+    hipEvent_t ev_ = nullptr;
+    char *base_ = nullptr;
+    char *stage_ = nullptr;
+    size_t stage_bytes_ = 0;
+    std::vector<uint64_t> ids_;
+    std::vector<Part> parts_;
+};
+
+}  // namespace
+
+struct lbp_server {
+    std::unique_ptr<Executor> exec;
+    GpuExecutor *gpu = nullptr;
+    Arena arena;
+    int32_t max_slots = 1, steps = 5;
+    std::mutex mu;
+    std::condition_variable cv;        // wakes the worker
+    std::condition_variable done_cv;   // wakes drain()
+    std::deque<Request *> incoming;    // mu
+    std::deque<Request *> completed;   // mu
+    std::vector<uint64_t> cancels;     // mu
+    std::vector<Request *> handed_out; // caller thread: freed at the next poll
+    std::deque<Request *> pending;     // worker only
+    std::vector<Request *> resident;   // worker only
+    bool stop = false;                 // mu
+    std::thread th;
+    Clock::time_point t0 = Clock::now();
+    // statistics (mu)
+    int64_t n_submitted = 0, n_finished = 0, n_completed = 0, n_rejected = 0, n_failed = 0, n_cancelled = 0;
+    int64_t n_rounds = 0, max_resident = 0;
+    int64_t now_resident = 0, now_pending = 0, arena_used = 0, arena_peak = 0;
+    double busy_s = 0.0;
+
+    double clock() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    void complete(Request *r, int status) {
+        r->status = status;
+        r->t_done = clock();
+        std::lock_guard<std::mutex> lk(mu);
+        ++n_finished;
+        if (status == LBP_OK || status == LBP_E_NONFINITE) ++n_completed;
+        else if (status == LBP_E_STATE) ++n_cancelled;
+        else ++n_failed;
+        completed.push_back(r);
+        done_cv.notify_all();
+    }
+
+    void drop_resident(Request *r) {
+        exec->release(*r);
+        arena.release(r->off, r->bytes);
+    }
+
+    void admit() {
+        while (!pending.empty() && (int32_t)resident.size() < max_slots) {
+            Request *r = pending.front();
+            if (r->cancel) {
+                pending.pop_front();
+                complete(r, LBP_E_STATE);
+                continue;
+            }
+            const size_t off = arena.alloc(r->bytes);
+            if (off == Arena::kNone) {
+                if (resident.empty() && arena.used() == 0) {
+                    // cannot fit even an empty arena (requests are checked
+                    // against the budget at submit, so this is a guard only)
+                    pending.pop_front();
+                    complete(r, LBP_E_BUDGET);
+                    continue;
+                }
+                break;  // first in, first out: wait for memory
+            }
+            pending.pop_front();
+            r->off = off;
+            int rc = exec->alloc_outputs(*r);
+            if (rc == LBP_OK) rc = exec->admit(*r);
+            if (rc != LBP_OK) {
+                if (r->g) exec->release(*r);
+                arena.release(off, r->bytes);
+                complete(r, rc);
+                continue;
+            }
+            r->t_admit = clock();
+            resident.push_back(r);
+        }
+    }
+
+    void update_stats() {
+        std::lock_guard<std::mutex> lk(mu);
+        now_resident = (int64_t)resident.size();
+        now_pending = (int64_t)pending.size();
+        max_resident = std::max(max_resident, now_resident);
+        arena_used = (int64_t)arena.used();
+        arena_peak = (int64_t)arena.peak();
+    }
+
+    void run() {
+        if (gpu) gpu->bind();
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop || !incoming.empty() || !resident.empty() || !pending.empty(); });
+                if (stop) break;
+                while (!incoming.empty()) {
+                    pending.push_back(incoming.front());
+                    incoming.pop_front();
+                }
+                for (uint64_t id : cancels) {
+                    for (Request *r : pending)
+                        if (r->id == id) r->cancel = true;
+                    for (Request *r : resident)
+                        if (r->id == id) r->cancel = true;
+                }
+                cancels.clear();
+            }
+            // cancelled resident requests leave at this round boundary
+            for (size_t i = 0; i < resident.size();) {
+                if (resident[i]->cancel) {
+                    Request *r = resident[i];
+                    drop_resident(r);
+                    resident.erase(resident.begin() + i);
+                    complete(r, LBP_E_STATE);
+                } else {
+                    ++i;
+                }
+            }
+            admit();
+            update_stats();
+            std::vector<Request *> active;
+            int32_t s = steps;
+            for (Request *r : resident)
+                if (r->done < r->iters) {
+                    active.push_back(r);
+                    s = std::min(s, r->iters - r->done);
+                    if (r->backward) s = std::min(s, r->k - r->done % r->k);
+                }
+            const double tr = clock();
+            if (!active.empty()) {
+                int rc = exec->round(active, s);
+                if (rc == LBP_OK) admit();  // uploads on the copy stream overlap the round
+                if (rc == LBP_OK) rc = exec->wait();
+                if (rc != LBP_OK) {
+                    for (Request *r : active) {
+                        drop_resident(r);
+                        resident.erase(std::find(resident.begin(), resident.end(), r));
+                        complete(r, rc);
+                    }
+                    continue;
+                }
+                for (Request *r : active) r->done += s;
+                std::lock_guard<std::mutex> lk(mu);
+                ++n_rounds;
+            }
+            for (size_t i = 0; i < resident.size();) {
+                Request *r = resident[i];
+                if (r->done >= r->iters) {
+                    int rc = exec->finish(*r);
+                    drop_resident(r);
+                    resident.erase(resident.begin() + i);
+                    complete(r, rc);
+                } else {
+                    ++i;
+                }
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                busy_s += clock() - tr;
+            }
+            update_stats();
+        }
+        // shutting down: everything left is cancelled
+        for (Request *r : resident) {
+            drop_resident(r);
+            complete(r, LBP_E_STATE);
+        }
+        resident.clear();
+        for (Request *r : pending) complete(r, LBP_E_STATE);
+        pending.clear();
+    }
+};
+
+namespace {
+
+int server_create(lbp_ctx *ctx, int64_t budget, int32_t max_slots, int32_t steps, bool on_gpu, lbp_server **out) {
+    if (!out) return set_error(LBP_E_INVALID, "out is NULL");
+    if (budget <= 0 || max_slots < 1 || steps < 1)
+        return set_error(LBP_E_INVALID, "budget, max_slots and steps_per_round must be positive");
+    try {
+        std::unique_ptr<lbp_server> s(new lbp_server);
+        s->arena = Arena((size_t)budget);
+        s->max_slots = max_slots;
+        s->steps = steps;
+        if (on_gpu) {
+            if (!ctx) return set_error(LBP_E_INVALID, "ctx is NULL");
+            std::unique_ptr<GpuExecutor> g(new GpuExecutor);
+            int rc = g->init(ctx->device, (size_t)budget);
+            if (rc != LBP_OK) return rc;
+            s->gpu = g.get();
+            s->exec = std::move(g);
+        } else {
+            s->exec.reset(new HostExecutor);
+        }
+        lbp_server *raw = s.get();
+        s->th = std::thread([raw] { raw->run(); });
+        *out = s.release();
+        return LBP_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(LBP_E_OOM, "host allocation failed");
+    } catch (const std::system_error &) {
+        return set_error(LBP_E_OOM, "could not start the server thread");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbp_server_create(lbp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots, int32_t steps_per_round,
+                      lbp_server **out) {
+    return server_create(ctx, hbm_budget_bytes, max_slots, steps_per_round, true, out);
+}
+
+int lbp_server_create_host_only(int64_t budget_bytes, int32_t max_slots, int32_t steps_per_round, lbp_server **out) {
+    return server_create(nullptr, budget_bytes, max_slots, steps_per_round, false, out);
+}
+
+double lbp_server_clock(const lbp_server *s) { return s ? s->clock() : 0.0; }
+
+int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, float damping, float temperature,
+                      const float *grad_q, int32_t ckpt_every, double t_arrival, uint64_t req_id) {
+    if (!s) return set_error(LBP_E_INVALID, "server is NULL");
+    std::string why;
+    if (!valid_params(iters, damping, temperature, &why)) return set_error(LBP_E_INVALID, why);
+    try {
+        std::unique_ptr<Request> r(new Request);
+        std::string err;
+        int rc = compile_desc(desc, &r->L, &err);
+        if (rc == LBP_OK) rc = check_layout(r->L, &err);
+        if (rc != LBP_OK) return set_error(rc, err);
+        r->id = req_id;
+        r->iters = iters;
+        r->d = damping;
+        r->T = temperature;
+        r->backward = grad_q != nullptr;
+        r->t_arrival = t_arrival >= 0.0 ? t_arrival : s->clock();
+        r->graph_bytes = graph_device_bytes(r->L);
+        r->bytes = Arena::round(r->graph_bytes);
+        if (r->backward) {
+            if (!(temperature > 0.0f)) return set_error(LBP_E_INVALID, "backward requests need temperature > 0");
+            if (ckpt_every < 1) return set_error(LBP_E_INVALID, "ckpt_every must be >= 1");
+            for (const FGroup &fg : r->L.fgroups)
+                if (fg.kind == TK_LOGL || fg.kind == TK_LOGW)
+                    return set_error(LBP_E_UNSUPPORTED, "the adjoint supports enumeration factors only");
+            r->k = ckpt_every;
+            r->grad_q.assign(grad_q, grad_q + r->L.VS);
+            r->adj_bytes = adjoint_bytes(r->L.M, r->L.VB, r->L.P, iters, ckpt_every);
+            r->bytes += Arena::round(r->adj_bytes) + Arena::round(sizeof(float) * r->L.VS) +
+                        Arena::round(sizeof(float) * r->L.Tn);
+        }
+        // the worker only needs what the upload and the read-out read
+        if (r->bytes > s->arena.capacity()) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            ++s->n_rejected;
+            return set_error(LBP_E_BUDGET, "request needs " + std::to_string(r->bytes) +
+                                               " bytes, more than the server budget");
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return set_error(LBP_E_STATE, "server is shutting down");
+        ++s->n_submitted;
+        s->incoming.push_back(r.release());
+        s->cv.notify_one();
+        return LBP_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(LBP_E_OOM, "host allocation failed");
+    }
+}
+
+int lbp_server_cancel(lbp_server *s, uint64_t req_id) {
+    if (!s) return set_error(LBP_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cancels.push_back(req_id);
+    s->cv.notify_one();
+    return LBP_OK;
+}
+
+int lbp_server_poll(lbp_server *s, lbp_completion *out, int32_t max, int32_t *n_out) {
+    if (!s || !n_out || (max > 0 && !out)) return set_error(LBP_E_INVALID, "bad poll arguments");
+    for (Request *r : s->handed_out) {
+        s->exec->free_outputs(*r);
+        delete r;
+    }
+    s->handed_out.clear();
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t n = 0;
+    while (n < max && !s->completed.empty()) {
+        Request *r = s->completed.front();
+        s->completed.pop_front();
+        lbp_completion &c = out[n++];
+        std::memset(&c, 0, sizeof(c));
+        c.req_id = r->id;
+        c.status = r->status;
+        c.num_vars = r->L.V;
+        c.num_var_states = r->L.VS;
+        c.num_logpots = r->L.Tn;
+        const bool ok = r->status == LBP_OK || r->status == LBP_E_NONFINITE;
+        c.beliefs = ok ? r->q : nullptr;
+        c.map = ok ? r->map : nullptr;
+        c.grad_logpot = ok && r->backward ? r->gphi : nullptr;
+        c.t_arrival = r->t_arrival;
+        c.t_admit = r->t_admit;
+        c.t_done = r->t_done;
+        s->handed_out.push_back(r);
+    }
+    *n_out = n;
+    return LBP_OK;
+}
+
+int lbp_server_drain(lbp_server *s, double timeout_s) {
+    if (!s) return set_error(LBP_E_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    const bool ok = s->done_cv.wait_for(lk, std::chrono::duration<double>(std::max(0.0, timeout_s)),
+                                        [&] { return s->n_finished >= s->n_submitted; });
+    return ok ? LBP_OK : set_error(LBP_E_STATE, "drain timed out");
+}
+
+int lbp_server_stats(lbp_server *s, int64_t out[12]) {
+    if (!s || !out) return set_error(LBP_E_INVALID, "server or out is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out[0] = s->n_submitted;
+    out[1] = s->n_finished;
+    out[2] = s->n_completed;
+    out[3] = s->n_rejected;
+    out[4] = s->n_failed;
+    out[5] = s->n_cancelled;
+    out[6] = s->n_rounds;
+    out[7] = s->now_resident;
+    out[8] = s->now_pending;
+    out[9] = s->max_resident;
+    out[10] = s->arena_peak;
+    out[11] = (int64_t)(s->busy_s * 1e6);
+    return LBP_OK;
+}
+
+void lbp_server_destroy(lbp_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    for (Request *r : s->handed_out) {
+        s->exec->free_outputs(*r);
+        delete r;
+    }
+    for (Request *r : s->completed) {
+        s->exec->free_outputs(*r);
+        delete r;
+    }
+    for (Request *r : s->incoming) delete r;
+    delete s;
+}
+
+}  // extern "C"

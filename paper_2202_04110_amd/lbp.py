@@ -80,6 +80,26 @@ _sig("lbp_run_bp_backward", C.c_int, [_P, _P, _P, _P])
 _sig("lbp_batch_create", C.c_int, [_P, _P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_batch_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
 _sig("lbp_batch_free", None, [_P])
+
+
+class Completion(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("num_vars", C.c_int64), ("num_var_states", C.c_int64), ("num_logpots", C.c_int64),
+                ("beliefs", C.POINTER(C.c_float)), ("map", C.POINTER(C.c_int32)),
+                ("grad_logpot", C.POINTER(C.c_float)),
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+_sig("lbp_server_create", C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)])
+_sig("lbp_server_create_host_only", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)])
+_sig("lbp_server_clock", C.c_double, [_P])
+_sig("lbp_server_submit", C.c_int, [_P, C.POINTER(GraphDesc), C.c_int32, C.c_float, C.c_float, _P, C.c_int32,
+                                    C.c_double, C.c_uint64])
+_sig("lbp_server_cancel", C.c_int, [_P, C.c_uint64])
+_sig("lbp_server_poll", C.c_int, [_P, C.POINTER(Completion), C.c_int32, C.POINTER(C.c_int32)])
+_sig("lbp_server_drain", C.c_int, [_P, C.c_double])
+_sig("lbp_server_stats", C.c_int, [_P, _P])
+_sig("lbp_server_destroy", None, [_P])
 _sig("lbp_time_phase", C.c_int, [_P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.POINTER(C.c_float)])
 
 EXPORTS = [n for n in dir(_lib) if n.startswith("lbp_")]
@@ -299,5 +319,74 @@ class Batch:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+SERVER_STATS = ("accepted", "finished", "completed", "rejected", "failed", "cancelled", "rounds",
+                "resident", "queued", "max_resident", "arena_peak_bytes", "busy_us")
+
+
+class Server:
+    """Continuous-batching server (see lbp_server_* in include/lbp.h)."""
+
+    def __init__(self, ctx=None, budget_bytes: int = 1 << 30, max_slots: int = 64, steps_per_round: int = 5,
+                 host_only: bool = False):
+        h = _P()
+        if host_only:
+            check(_lib.lbp_server_create_host_only(int(budget_bytes), int(max_slots), int(steps_per_round),
+                                                   C.byref(h)))
+        else:
+            check(_lib.lbp_server_create(ctx.h, int(budget_bytes), int(max_slots), int(steps_per_round),
+                                         C.byref(h)))
+        self.h = h
+
+    def clock(self) -> float:
+        return float(_lib.lbp_server_clock(self.h))
+
+    def submit(self, spec, iters: int, damping: float, temperature: float, grad_q=None, ckpt_every: int = 10,
+               t_arrival: float = -1.0, req_id: int = 0):
+        d, keep = make_desc(spec)
+        gq = None if grad_q is None else np.ascontiguousarray(grad_q, np.float32)
+        check(_lib.lbp_server_submit(self.h, C.byref(d), int(iters), float(damping), float(temperature),
+                                     _ptr(gq), int(ckpt_every), float(t_arrival), int(req_id)))
+
+    def cancel(self, req_id: int):
+        check(_lib.lbp_server_cancel(self.h, int(req_id)))
+
+    def poll(self, max_n: int = 256):
+        """Finished requests as dicts; outputs are copied into numpy arrays."""
+        buf = (Completion * max_n)()
+        n = C.c_int32()
+        check(_lib.lbp_server_poll(self.h, buf, max_n, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            rec = {"req_id": int(c.req_id), "status": int(c.status), "t_arrival": c.t_arrival,
+                   "t_admit": c.t_admit, "t_done": c.t_done, "beliefs": None, "map": None, "grad_logpot": None}
+            if c.beliefs:
+                rec["beliefs"] = np.ctypeslib.as_array(c.beliefs, (c.num_var_states,)).copy()
+                rec["map"] = np.ctypeslib.as_array(c.map, (c.num_vars,)).copy()
+            if c.grad_logpot:
+                rec["grad_logpot"] = np.ctypeslib.as_array(c.grad_logpot, (c.num_logpots,)).copy()
+            out.append(rec)
+        return out
+
+    def drain(self, timeout: float = 600.0):
+        check(_lib.lbp_server_drain(self.h, float(timeout)))
+
+    def stats(self) -> dict:
+        s = np.zeros(12, np.int64)
+        check(_lib.lbp_server_stats(self.h, _ptr(s)))
+        return dict(zip(SERVER_STATS, (int(x) for x in s)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.lbp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

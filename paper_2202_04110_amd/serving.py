@@ -1,0 +1,60 @@
+"""Serving driver: submits requests at scheduled arrival times and reports
+latency percentiles and throughput.  The scheduling itself (admission by
+memory budget, resident messages, shared multi-graph launches) is the
+library's worker thread; this module only plays the clients."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+
+def run_stream(server, specs, arrivals, iters: int, damping: float, temperature: float, grad_qs=None,
+               ckpt_every: int = 10, timeout: float = 900.0, start_delay: float = 0.05):
+    """Submits request i (graph specs[i]) at server-clock time
+    start + arrivals[i] seconds, with its latency measured from that scheduled
+    time.  grad_qs[i] (or None) asks for the log-potential gradient.  Returns
+    (results by request id, summary)."""
+    n = len(specs)
+    order = np.argsort(arrivals, kind="stable")
+    t_start = server.clock() + start_delay
+    results = {}
+
+    def collect():
+        for rec in server.poll(256):
+            results[rec["req_id"]] = rec
+
+    for i in order:
+        due = t_start + float(arrivals[i])
+        while True:
+            now = server.clock()
+            if now >= due:
+                break
+            collect()
+            time.sleep(min(0.002, due - now))
+        gq = None if grad_qs is None else grad_qs[i]
+        server.submit(specs[i], iters, damping, temperature, grad_q=gq, ckpt_every=ckpt_every, t_arrival=due,
+                      req_id=int(i))
+    server.drain(timeout)
+    collect()
+    while len(results) < n:
+        got = server.poll(256)
+        if not got:
+            break
+        for rec in got:
+            results[rec["req_id"]] = rec
+    ok = [r for r in results.values() if r["status"] == 0]
+    lat = np.array([r["t_done"] - r["t_arrival"] for r in ok]) if ok else np.zeros(0)
+    makespan = (max(r["t_done"] for r in ok) - t_start) if ok else 0.0
+    es_total = sum(int(specs[r["req_id"]].num_edge_states) for r in ok) * iters
+    summary = {
+        "requests": n, "ok": len(ok),
+        "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+        "mean_s": float(lat.mean()) if lat.size else None,
+        "makespan_s": makespan,
+        "requests_per_s": len(ok) / makespan if makespan > 0 else None,
+        "edge_state_updates_per_s": es_total / makespan if makespan > 0 else None,
+        "stats": server.stats(),
+    }
+    return results, summary

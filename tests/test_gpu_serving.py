@@ -1,0 +1,97 @@
+"""Serving loop on the GPU: requests arriving while others run are admitted
+as slots and memory free up, share multi-graph launches, and each result is
+bitwise equal to the same request run alone (beliefs, MAP and, for backward
+requests, the log-potential gradient); a few are also checked against the
+FP64 oracle (1e-4 on beliefs)."""
+import numpy as np
+import pytest
+
+from oracle import OracleGraph
+from paper_2202_04110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbp(gpu_lib):
+    return gpu_lib
+
+
+@pytest.fixture(scope="module")
+def ctx(lbp):
+    return lbp.Context(0)
+
+
+def lone(lbp, ctx, spec, iters, d, T, gq=None, k=10):
+    import torch
+    g = lbp.Graph(ctx, spec)
+    if gq is None:
+        g.run_bp(iters, d, T)
+    else:
+        g.run_bp_record(iters, d, T, k)
+    q, mp = g.get_beliefs(), g.decode_map()
+    gphi = None
+    if gq is not None:
+        gp = torch.empty(g.Tn, device="cuda", dtype=torch.float32)
+        g.backward(torch.from_numpy(np.asarray(gq, np.float32)).cuda(), gp)
+        torch.cuda.synchronize()
+        gphi = gp.cpu().numpy()
+    g.free()
+    return q, mp, gphi
+
+
+def test_served_mix_equals_lone_runs(lbp, ctx):
+    from paper_2202_04110_amd.serving import run_stream
+    reqs = W.served_requests(40, seed=5, max_side=96, backward_count=6)
+    specs = [W.request_graph(r) for r in reqs]
+    gqs = [W.request_loss_coeffs(r) if r["backward"] else None for r in reqs]
+    arrivals = W.poisson_arrivals(len(reqs), qps=300.0, seed=6)
+    srv = lbp.Server(ctx, budget_bytes=48 << 20, max_slots=8, steps_per_round=5)
+    res, summ = run_stream(srv, specs, arrivals, 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10, timeout=300)
+    st = srv.stats()
+    srv.close()
+    print("served:", {k: v for k, v in summ.items() if k != "stats"}, st)
+    assert summ["ok"] == len(reqs)
+    assert st["max_resident"] > 1  # graphs really shared launches
+    for i, spec in enumerate(specs):
+        q, mp, gphi = lone(lbp, ctx, spec, 50, 0.5, 1.0, gqs[i])
+        np.testing.assert_array_equal(res[i]["beliefs"], q)
+        np.testing.assert_array_equal(res[i]["map"], mp)
+        if gqs[i] is not None:
+            np.testing.assert_array_equal(res[i]["grad_logpot"], gphi)
+    for i in (0, 7):
+        og = OracleGraph(specs[i])
+        _, qo, _ = og.beliefs(og.run(50, 0.5, 1.0), 1.0)
+        assert np.abs(res[i]["beliefs"] - qo).max() < 1e-4
+
+
+def test_mixed_parameters_and_kinds(lbp, ctx):
+    """Requests with different temperatures and factor kinds in one server."""
+    specs = [W.potts_grid(20, 3, 1), W.ising_grid(16, 2), W.deconv(seed=4, K=2, tw=4, sd=10, img=12),
+             W.rbm(30, 20, 3), W.potts_grid(33, 5, 4)]
+    params = [(30, 0.5, 1.0), (30, 0.5, 0.0), (40, 0.5, 0.0), (25, 0.3, 0.05), (30, 0.5, 1.0)]
+    srv = lbp.Server(ctx, budget_bytes=256 << 20, max_slots=4, steps_per_round=7)
+    for i, (s, (it, d, T)) in enumerate(zip(specs, params)):
+        srv.submit(s, it, d, T, req_id=i)
+    srv.drain(120)
+    res = {r["req_id"]: r for r in srv.poll()}
+    srv.close()
+    for i, (s, (it, d, T)) in enumerate(zip(specs, params)):
+        q, mp, _ = lone(lbp, ctx, s, it, d, T)
+        np.testing.assert_array_equal(res[i]["beliefs"], q)
+        np.testing.assert_array_equal(res[i]["map"], mp)
+
+
+def test_cancel_resident_request(lbp, ctx):
+    srv = lbp.Server(ctx, budget_bytes=256 << 20, max_slots=2, steps_per_round=2)
+    spec = W.potts_grid(64, 4, 5)
+    srv.submit(spec, 100000, 0.5, 1.0, req_id=1)
+    srv.submit(W.potts_grid(10, 3, 6), 20, 0.5, 1.0, req_id=2)
+    import time
+    time.sleep(0.2)
+    srv.cancel(1)
+    srv.drain(60)
+    res = {r["req_id"]: r for r in srv.poll()}
+    srv.close()
+    assert res[1]["status"] == lbp.LBP_E_STATE
+    assert res[2]["status"] == 0

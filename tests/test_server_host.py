@@ -1,0 +1,141 @@
+"""Scheduler of the serving loop on the host (bookkeeping-only executor, no
+GPU): admission under the memory budget and slot limit, first-in first-out
+queueing, rejection of requests larger than the budget, cancellation, and
+malformed requests."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2202_04110_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def lbp():
+    from paper_2202_04110_amd import lbp as mod
+    return mod
+
+
+def _sizes(lbp, spec):
+    return lbp.check_layout(spec)
+
+
+def test_budget_and_slots_respected(lbp):
+    specs = [W.potts_grid(L, n, seed=i) for i, (L, n) in enumerate(
+        [(20, 3), (40, 5), (12, 8), (60, 2), (30, 4), (25, 6), (50, 3), (16, 2)] * 3)]
+    budget = 6 << 20
+    srv = lbp.Server(budget_bytes=budget, max_slots=3, steps_per_round=4, host_only=True)
+    for i, s in enumerate(specs):
+        srv.submit(s, 20, 0.5, 1.0, req_id=i)
+    srv.drain(30)
+    recs = {r["req_id"]: r for r in srv.poll(1000)}
+    st = srv.stats()
+    srv.close()
+    assert len(recs) == len(specs) and all(r["status"] == 0 for r in recs.values())
+    assert st["max_resident"] <= 3
+    assert 0 < st["arena_peak_bytes"] <= budget
+    assert st["completed"] == len(specs) and st["rounds"] > 0
+    # first in, first out: admission times follow submission order
+    adm = [recs[i]["t_admit"] for i in range(len(specs))]
+    assert all(a <= b for a, b in zip(adm, adm[1:]))
+    # zero-filled outputs of the right sizes from the bookkeeping executor
+    assert recs[3]["beliefs"].shape == (specs[3].num_var_states,)
+    assert recs[3]["map"].shape == (specs[3].num_vars,)
+
+
+def test_oversized_request_rejected(lbp):
+    srv = lbp.Server(budget_bytes=1 << 20, max_slots=4, host_only=True)
+    with pytest.raises(lbp.LBPError) as ei:
+        srv.submit(W.potts_grid(200, 8, seed=1), 10, 0.5, 1.0, req_id=1)
+    assert ei.value.code == lbp.LBP_E_BUDGET
+    srv.submit(W.potts_grid(10, 3, seed=2), 10, 0.5, 1.0, req_id=2)
+    srv.drain(10)
+    recs = srv.poll()
+    assert [r["req_id"] for r in recs] == [2]
+    assert srv.stats()["rejected"] == 1
+    srv.close()
+
+
+def test_malformed_and_invalid_requests(lbp):
+    srv = lbp.Server(budget_bytes=1 << 24, host_only=True)
+    bad = W.potts_grid(5, 3, seed=1)
+    bad.edge_var[0] = 10 ** 6
+    with pytest.raises(lbp.LBPError) as ei:
+        srv.submit(bad, 10, 0.5, 1.0)
+    assert ei.value.code == lbp.LBP_E_INVALID
+    with pytest.raises(lbp.LBPError) as ei:
+        srv.submit(W.potts_grid(5, 3, seed=1), 10, 1.5, 1.0)
+    assert ei.value.code == lbp.LBP_E_INVALID
+    # backward needs T > 0 and enumeration factors only
+    g = W.potts_grid(5, 3, seed=1)
+    with pytest.raises(lbp.LBPError) as ei:
+        srv.submit(g, 10, 0.5, 0.0, grad_q=np.zeros(g.num_var_states))
+    assert ei.value.code == lbp.LBP_E_INVALID
+    lg = W.single_logical(1, W.OR, 3)
+    with pytest.raises(lbp.LBPError) as ei:
+        srv.submit(lg, 10, 0.5, 1.0, grad_q=np.zeros(lg.num_var_states))
+    assert ei.value.code == lbp.LBP_E_UNSUPPORTED
+    assert srv.stats()["accepted"] == 0
+    srv.close()
+
+
+def test_queue_waits_for_memory_then_admits(lbp):
+    """A budget that holds one graph at a time: requests wait in the queue and
+    are admitted one by one as memory frees up."""
+    spec = W.potts_grid(40, 5, seed=3)
+    srv0 = lbp.Server(budget_bytes=1 << 30, host_only=True)
+    srv0.submit(spec, 1, 0.5, 1.0, req_id=0)
+    srv0.drain(10)
+    srv0.close()
+    one = 0
+    # size of one request: find the smallest budget that admits it
+    lo, hi = 1 << 10, 1 << 26
+    while lo < hi:
+        mid = (lo + hi) // 2
+        s = lbp.Server(budget_bytes=mid, host_only=True)
+        try:
+            s.submit(spec, 1, 0.5, 1.0)
+            hi = mid
+        except lbp.LBPError:
+            lo = mid + 1
+        s.close()
+    one = lo
+    srv = lbp.Server(budget_bytes=int(one * 1.5), max_slots=8, steps_per_round=3, host_only=True)
+    for i in range(5):
+        srv.submit(spec, 9, 0.5, 1.0, req_id=i)
+    srv.drain(10)
+    recs = {r["req_id"]: r for r in srv.poll()}
+    st = srv.stats()
+    srv.close()
+    assert st["max_resident"] == 1 and st["completed"] == 5
+    # each request is admitted only after the previous one finished
+    for i in range(4):
+        assert recs[i + 1]["t_admit"] >= recs[i]["t_done"]
+
+
+def test_cancel_queued_request(lbp):
+    spec = W.potts_grid(30, 4, seed=4)
+    srv = lbp.Server(budget_bytes=1 << 30, max_slots=1, steps_per_round=1, host_only=True)
+    for i in range(4):
+        srv.submit(spec, 5000, 0.5, 1.0, req_id=i)
+    srv.cancel(3)
+    srv.cancel(0)
+    srv.drain(60)
+    recs = {r["req_id"]: r for r in srv.poll()}
+    st = srv.stats()
+    srv.close()
+    assert recs[3]["status"] == lbp.LBP_E_STATE and recs[3]["beliefs"] is None
+    assert recs[0]["status"] in (0, lbp.LBP_E_STATE)
+    assert recs[1]["status"] == 0 and recs[2]["status"] == 0
+    assert st["cancelled"] >= 1
+
+
+def test_stream_driver_host_only(lbp):
+    from paper_2202_04110_amd.serving import run_stream
+    reqs = W.served_requests(24, seed=5, max_side=48)
+    specs = [W.request_graph(r) for r in reqs]
+    arr = W.poisson_arrivals(len(reqs), qps=400.0, seed=5)
+    srv = lbp.Server(budget_bytes=64 << 20, max_slots=8, steps_per_round=5, host_only=True)
+    res, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, timeout=30)
+    srv.close()
+    assert summ["ok"] == 24 and summ["p99_s"] >= summ["p50_s"] >= 0
