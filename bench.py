@@ -143,6 +143,7 @@ def main():
     ap.add_argument("--workload", default="potts512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=200)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="also run the served stream with N requests (0: skip)")
     ap.add_argument("--serving-budget-mb", type=int, default=2048)
@@ -177,6 +178,10 @@ def main():
     torch.cuda.set_device(0)
     ctx = lbp.Context(0)
     g = lbp.Graph(ctx, spec)
+    tuned = None
+    if not args.no_tune:
+        from paper_2202_04110_amd import tune
+        tuned = tune.apply_or_tune(g, d, T)
     q = torch.empty(g.VS, device="cuda", dtype=torch.float32)
     mp = torch.empty(g.V, device="cuda", dtype=torch.int32)
 
@@ -231,6 +236,8 @@ def main():
         "iteration_gbps": bm["iter_bytes"] / (t_it * 1e-3) / 1e9,
         "solve_gbps": bm["iter_bytes"] * iters / (ms_step * 1e-3) / 1e9,
         "kernel_src_sha": kernel_source_sha(),
+        "launch_shapes": [{k: l[k] for k in ("phase", "kind", "a", "b", "wpb", "swizzle")} for l in g.launches()],
+        "tune_source": tuned["source"] if tuned else "default",
         "device": torch.cuda.get_device_name(0),
     }
     if args.serving:

@@ -275,14 +275,19 @@ int lbp_server_create(lbp_ctx *ctx, int64_t hbm_budget_bytes, int32_t max_slots,
 int lbp_server_create_host_only(int64_t budget_bytes, int32_t max_slots, int32_t steps_per_round, lbp_server **out);
 /* Seconds since the server was created (the clock of every timestamp). */
 double lbp_server_clock(const lbp_server *s);
-/* Queues a request; the description (host arrays) is compiled and copied
- * before return.  grad_q (host, VS floats) != NULL asks for the gradient of
- * sum(grad_q * q) w.r.t. the log-potentials (T > 0, enumeration factors
- * only), with checkpoints every ckpt_every iterations.  t_arrival: the
- * request's arrival time on the server clock (its latency is measured from
- * it), or < 0 for "now".  Returns LBP_E_BUDGET if the request alone exceeds
- * the budget, LBP_E_INVALID / LBP_E_UNSUPPORTED as lbp_graph_upload and
- * lbp_run_bp_record would. */
+/* Queues a request.  Its host arrays are copied before return (their
+ * lengths are read from the offsets, so they must be as long as the
+ * description says); validation (lbp_validate's checks) and compilation run
+ * on the server's prep threads, a failing request completes with status
+ * LBP_E_INVALID or LBP_E_UNSUPPORTED, and admission stays first-in
+ * first-out.  Null arrays, negative counts and bad parameters are rejected
+ * at once with LBP_E_INVALID.  grad_q
+ * (host, VS floats) != NULL asks for the gradient of sum(grad_q * q) w.r.t.
+ * the log-potentials (T > 0, enumeration factors only), with checkpoints
+ * every ckpt_every iterations.  t_arrival: the request's arrival time on the
+ * server clock (its latency is measured from it), or < 0 for "now".  A
+ * request that alone needs more than the budget completes with status
+ * LBP_E_BUDGET. */
 int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, float damping, float temperature,
                       const float *grad_q, int32_t ckpt_every, double t_arrival, uint64_t req_id);
 /* Marks a queued or resident request cancelled; it completes with
@@ -293,13 +298,31 @@ int lbp_server_cancel(lbp_server *s, uint64_t req_id);
 int lbp_server_poll(lbp_server *s, lbp_completion *out, int32_t max, int32_t *n_out);
 /* Waits until every accepted request has finished (LBP_E_STATE on timeout). */
 int lbp_server_drain(lbp_server *s, double timeout_s);
-/* out[12] = {accepted, finished, completed, rejected at submit, failed,
+/* out[12] = {accepted, finished, completed, rejected for the budget, failed,
  * cancelled, rounds, resident now, queued now, max resident, arena peak bytes,
  * worker busy microseconds}. */
 int lbp_server_stats(lbp_server *s, int64_t out[12]);
 /* Stops the worker (queued and resident requests are dropped) and frees
  * everything. */
 void lbp_server_destroy(lbp_server *s);
+
+/*
+ * Launch shapes and the autotuner.  A graph's work runs as a few launch
+ * groups (the variable phase, then one group per factor shape class).  Each
+ * group has a shape: wavefronts per block (1, 2 or 4; the variable phase and
+ * generic enumeration groups are fixed at 4) and whether blocks are remapped
+ * so that each of the 8 XCDs takes a contiguous range of tiles.  Shapes never
+ * change any element's arithmetic, so results are identical whatever the
+ * shape.  lbp_autotune times every candidate shape of every group with HIP
+ * events (reps launches each, messages saved and restored) and keeps the
+ * fastest; best_ms_out (may be NULL) receives the chosen launch time per
+ * group.  lbp_graph_get_launch returns {phase (0 variable, 1 factor), kind,
+ * a, b, waves per block, swizzle, work items} for group i.
+ */
+int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out);
+int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[7]);
+int lbp_graph_set_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle);
+int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, float *best_ms_out);
 
 /* Diagnostic timing: runs `reps` launches of one phase of an iteration on the
  * current messages and returns the mean launch time in milliseconds measured

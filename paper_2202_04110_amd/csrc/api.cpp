@@ -283,6 +283,147 @@ int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, flo
     return LBP_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+namespace {
+
+std::vector<Launch *> all_launches(std::vector<Launch> &vl, std::vector<Launch> &fl) {
+    std::vector<Launch *> v;
+    for (Launch &L : vl) v.push_back(&L);
+    for (Launch &L : fl) v.push_back(&L);
+    return v;
+}
+
+// Times `reps` launches of one launch group (after one warm-up launch).
+hipError_t time_one(const DevGraph *gs, const Launch &L, bool variable, const TParams &P, bool maxp, hipStream_t st,
+                    int reps, hipEvent_t a, hipEvent_t b, float *ms) {
+    std::vector<Launch> one{L}, none;
+    const std::vector<Launch> &vl = variable ? one : none;
+    const std::vector<Launch> &fl = variable ? none : one;
+    const int ph = variable ? 1 : 2;
+    hipError_t e = launch_iteration(gs, vl, fl, P, maxp, st, ph);
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_iteration(gs, vl, fl, P, maxp, st, ph);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    *ms /= (float)reps;
+    return e;
+}
+
+// Picks, per launch group, the fastest shape: variable phase {swizzle off, on};
+// lane-per-item factor kernels {1, 2, 4 wavefronts per block} x {swizzle off,
+// on}; generic enumeration launches keep their fixed shape.
+int tune_launches(const DevGraph *gs, std::vector<Launch> &vl, std::vector<Launch> &fl, float d, float T, int reps,
+                  hipStream_t st, float *best_ms) {
+    const TParams P = make_params(d, T);
+    const bool maxp = T == 0.0f;
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_error(e, "hipEventCreate");
+    }
+    int idx = 0;
+    for (Launch *L : all_launches(vl, fl)) {
+        const bool variable = L->kind == -1;
+        std::vector<LaunchShape> cand;
+        if (variable) {
+            cand = {LaunchShape{4, 0}, LaunchShape{4, 1}};
+        } else if (L->kind == TK_GEN) {
+            cand = {L->shape};
+        } else {
+            for (int w : {1, 2, 4})
+                for (int z : {0, 1}) cand.push_back(LaunchShape{w, z});
+        }
+        LaunchShape best = L->shape;
+        float best_t = 1e30f;
+        for (const LaunchShape &c : cand) {
+            L->shape = c;
+            float ms = 0.0f;
+            e = time_one(gs, *L, variable, P, maxp, st, reps, a, b, &ms);
+            if (e != hipSuccess) break;
+            if (ms < best_t) {
+                best_t = ms;
+                best = c;
+            }
+        }
+        L->shape = best;
+        if (best_ms) best_ms[idx] = best_t;
+        ++idx;
+        if (e != hipSuccess) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_error(e, "autotune");
+    return LBP_OK;
+}
+
+}  // namespace
+
+int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out) {
+    if (!g || !n_out) return fail(LBP_E_INVALID, "graph or n_out is NULL");
+    *n_out = (int32_t)(g->vl.size() + g->fl.size());
+    return LBP_OK;
+}
+
+int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[7]) {
+    if (!g || !out) return fail(LBP_E_INVALID, "graph or out is NULL");
+    const int32_t nv = (int32_t)g->vl.size(), nf = (int32_t)g->fl.size();
+    if (i < 0 || i >= nv + nf) return fail(LBP_E_INVALID, "launch index out of range");
+    const Launch &L = i < nv ? g->vl[i] : g->fl[i - nv];
+    out[0] = i < nv ? 0 : 1;
+    out[1] = L.kind;
+    out[2] = L.a;
+    out[3] = L.b;
+    out[4] = L.shape.wpb;
+    out[5] = L.shape.swizzle;
+    out[6] = L.n + L.n_mid + L.n_high;
+    return LBP_OK;
+}
+
+int lbp_graph_set_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    const int32_t nv = (int32_t)g->vl.size(), nf = (int32_t)g->fl.size();
+    if (i < 0 || i >= nv + nf) return fail(LBP_E_INVALID, "launch index out of range");
+    if (swizzle != 0 && swizzle != 1) return fail(LBP_E_INVALID, "swizzle must be 0 or 1");
+    Launch &L = i < nv ? g->vl[i] : g->fl[i - nv];
+    const bool fixed = i < nv || L.kind == TK_GEN;
+    if (fixed ? waves_per_block != 4 : (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4))
+        return fail(LBP_E_INVALID, "waves_per_block must be 1, 2 or 4 (4 for this launch)");
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    destroy_loops(g->loops);
+    L.shape = LaunchShape{waves_per_block, swizzle};
+    return LBP_OK;
+}
+
+int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, float *best_ms_out) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    std::string why;
+    if (!valid_params(0, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
+    if (reps < 1) return fail(LBP_E_INVALID, "reps must be >= 1");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t st = g->ctx->stream;
+    // the factor kernels update the messages: keep and restore them
+    float *save = nullptr;
+    hipError_t e = hipMalloc((void **)&save, sizeof(float) * g->M);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBP_E_OOM, "autotune message backup");
+    }
+    e = hipMemcpyAsync(save, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
+    int rc = e == hipSuccess ? tune_launches(g->dgraph, g->vl, g->fl, damping, temperature, reps, st, best_ms_out)
+                             : hip_error(e, "autotune backup");
+    e = hipMemcpyAsync(g->host.m, save, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(save);
+    destroy_loops(g->loops);
+    if (rc != LBP_OK) return rc;
+    if (e != hipSuccess) return hip_error(e, "autotune restore");
+    return LBP_OK;
+}
+
 // ---------------------------------------------------------------- adjoint
 int lbp_run_bp_record(lbp_graph *g, int32_t iters, float damping, float temperature, int32_t ckpt_every) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");

@@ -106,23 +106,26 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
             if (d->cfg_table_arity[t] != k)
                 return bad(err, "factor " + std::to_string(f) + " has arity " + std::to_string(k) +
                                     " but its table has arity " + std::to_string(d->cfg_table_arity[t]));
-            std::vector<int32_t> ns(k);
             int64_t nsum = 0;
+            int32_t ns2[2] = {0, 0};
             for (int64_t j = 0; j < k; ++j) {
-                ns[j] = d->var_num_states[d->edge_var[e0 + j]];
-                nsum += ns[j];
+                const int32_t n = d->var_num_states[d->edge_var[e0 + j]];
+                if (j < 2) ns2[j] = n;
+                nsum += n;
             }
             const bool dense = d->cfg_table_num_cfgs[t] == 0;
             int64_t ncfg;
             if (dense) {
                 ncfg = 1;
                 for (int64_t j = 0; j < k; ++j) {
-                    ncfg *= ns[j];
+                    ncfg *= d->var_num_states[d->edge_var[e0 + j]];
                     if (ncfg > INT32_MAX) return bad(err, "dense table of factor " + std::to_string(f) +
                                                               " is too large", LBP_E_UNSUPPORTED);
                 }
             } else {
                 ncfg = d->cfg_table_num_cfgs[t];
+                std::vector<int32_t> ns(k);
+                for (int64_t j = 0; j < k; ++j) ns[j] = d->var_num_states[d->edge_var[e0 + j]];
                 std::vector<int32_t> key(ns);
                 key.push_back(t);
                 if (!checked.count(key)) {
@@ -149,7 +152,7 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
             if (nlp != ncfg)
                 return bad(err, "factor " + std::to_string(f) + " has " + std::to_string(nlp) +
                                     " log-potentials, its table " + std::to_string(ncfg) + " configurations");
-            if (!pair_fast(dense, (int32_t)k, ns.data()) &&
+            if (!pair_fast(dense, (int32_t)k, ns2) &&
                 (k > kGenArityMax || ncfg > kGenCfgMax || nsum > kGenRowsMax))
                 return bad(err, "enumeration factor " + std::to_string(f) +
                                     " exceeds the generic kernel limits (arity <= 8, <= 4096 configurations, "
@@ -234,35 +237,63 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
     std::vector<Key> class_key;
     std::vector<std::vector<int32_t>> class_facs;
     std::vector<int32_t> fclass(F);
+    // Small integer codes for the common shapes avoid building a key per
+    // factor: dense pairwise (na, nb), lane logical (arity, AND), wide logical
+    // (chunk bucket).  Generic classes use the full key.
+    std::vector<int32_t> fast_class(2 * 65 * 65 + 64, -1);
+    auto fast_code = [&](int32_t kind, int32_t a, int32_t b) -> int32_t {
+        if (kind == TK_PAIR) return a * 65 + b;
+        if (kind == TK_LOGL) return 65 * 65 + a * 2 + b;
+        return 65 * 65 + 2 * (kLogLaneArityMax + 1) + a;  // TK_LOGW: a = chunk bucket <= 16
+    };
     for (int64_t f = 0; f < F; ++f) {
         const int64_t e0 = d->factor_edge_off[f];
         const int32_t k = (int32_t)(d->factor_edge_off[f + 1] - e0);
-        std::vector<int32_t> ns(k);
-        for (int32_t j = 0; j < k; ++j) ns[j] = L->vn[d->edge_var[e0 + j]];
-        Key key;
+        int32_t kind, a = 0, b = 0;
+        bool fast = true;
         if (d->factor_kind[f] == LBP_FACTOR_ENUM) {
-            int32_t t = d->factor_cfg_table[f];
-            bool dense = d->cfg_table_num_cfgs[t] == 0;
-            if (pair_fast(dense, k, ns.data()))
-                key = Key(TK_PAIR, ns[0], ns[1], -1, std::vector<int32_t>());
-            else
-                key = Key(TK_GEN, k, 0, dense ? -1 : t, ns);
-        } else {
-            int32_t flip = d->factor_kind[f] == LBP_FACTOR_AND;
-            if (k <= kLogLaneArityMax)
-                key = Key(TK_LOGL, k, flip, -1, std::vector<int32_t>());
-            else  // one tile per factor
-                key = Key(TK_LOGW, chunk_bucket((k + kLanes - 1) / kLanes), 0, -1, std::vector<int32_t>());
+            const int32_t t = d->factor_cfg_table[f];
+            const bool dense = d->cfg_table_num_cfgs[t] == 0;
+            int32_t ns2[2] = {k > 0 ? L->vn[d->edge_var[e0]] : 0, k > 1 ? L->vn[d->edge_var[e0 + 1]] : 0};
+            if (pair_fast(dense, k, ns2)) {
+                kind = TK_PAIR;
+                a = ns2[0];
+                b = ns2[1];
+            } else {
+                kind = TK_GEN;
+                fast = false;
+            }
+        } else if (k <= kLogLaneArityMax) {
+            kind = TK_LOGL;
+            a = k;
+            b = d->factor_kind[f] == LBP_FACTOR_AND;
+        } else {  // one tile per factor
+            kind = TK_LOGW;
+            a = chunk_bucket((k + kLanes - 1) / kLanes);
         }
-        auto it = class_of.find(key);
         int32_t c;
-        if (it == class_of.end()) {
-            c = (int32_t)class_key.size();
-            class_of[key] = c;
-            class_key.push_back(key);
-            class_facs.emplace_back();
+        if (fast) {
+            int32_t &slot = fast_class[fast_code(kind, a, b)];
+            if (slot < 0) {
+                slot = (int32_t)class_key.size();
+                class_key.push_back(Key(kind, a, b, -1, std::vector<int32_t>()));
+                class_facs.emplace_back();
+            }
+            c = slot;
         } else {
-            c = it->second;
+            std::vector<int32_t> ns(k);
+            for (int32_t j = 0; j < k; ++j) ns[j] = L->vn[d->edge_var[e0 + j]];
+            const int32_t t = d->factor_cfg_table[f];
+            Key key(TK_GEN, k, 0, d->cfg_table_num_cfgs[t] == 0 ? -1 : t, ns);
+            auto it = class_of.find(key);
+            if (it == class_of.end()) {
+                c = (int32_t)class_key.size();
+                class_of[key] = c;
+                class_key.push_back(key);
+                class_facs.emplace_back();
+            } else {
+                c = it->second;
+            }
         }
         class_facs[c].push_back((int32_t)f);
         fclass[f] = c;

@@ -17,6 +17,14 @@ struct TParams {
 
 TParams make_params(float damping, float temperature);
 
+// Launch shape of a wavefront-per-item kernel: wavefronts per block (1, 2 or
+// 4) and whether blocks are remapped so each XCD takes a contiguous range.
+// Neither changes any element's arithmetic.
+struct LaunchShape {
+    int wpb = 4;
+    int swizzle = 0;
+};
+
 // Buffers of the reverse sweep (message panels A, nbar; belief panel Bbar;
 // potential panel phibar).
 struct AdjBufs {
@@ -29,13 +37,13 @@ struct AdjBufs {
 // Variable phase: items = n_low low tiles, then n_mid and n_high variables
 // (indices into the graph's hvar list); bucket >= states of every low lane.
 hipError_t launch_belief(const DevGraph *gs, const WorkItem *items, int n_low, int n_mid, int n_high, int bucket,
-                         hipStream_t st);
+                         const LaunchShape &S, hipStream_t st);
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
-                       const TParams &P, hipStream_t st);
+                       const TParams &P, const LaunchShape &S, hipStream_t st);
 // Logical tiles: wide = false for lane tiles and factors of <= 256 edges,
 // true for factors of 257..1024 edges.
 hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool wide, bool maxp, const TParams &P,
-                          hipStream_t st);
+                          const LaunchShape &S, hipStream_t st);
 hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
                       hipStream_t st);
 // Read-out of a single graph (gs[0]).

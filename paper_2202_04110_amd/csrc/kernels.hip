@@ -34,6 +34,24 @@ namespace {
 __device__ __forceinline__ int wave_index(int waves_per_block) {
     return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * waves_per_block + (threadIdx.x >> 6)));
 }
+
+// Workgroups are dealt to the 8 XCDs round-robin.  With swizzling, block b of
+// n maps to a logical block such that each XCD runs one contiguous range of
+// logical blocks (neighbouring tiles then share that XCD's L2).  A bijection
+// on [0, n): the last n mod 8 blocks keep their index.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int swizzle_block(int b, int n) {
+    const int per = n / kXcds;
+    if (b >= per * kXcds) return b;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+// Work item of this wavefront: blockDim.x / 64 wavefronts per block.
+__device__ __forceinline__ int wave_item(int swz) {
+    const int wpb = blockDim.x >> 6;
+    const int b = swz ? swizzle_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    return __builtin_amdgcn_readfirstlane(b * wpb + (int)(threadIdx.x >> 6));
+}
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -191,12 +209,13 @@ __device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int t
 
 template <int NB>
 __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
-                                                int n_low, int n_mid, int n_high) {
+                                                int n_low, int n_mid, int n_high, int swz) {
     __shared__ float red[8][kHighThreads];
     const int nwave = n_low + n_mid;
     const int wave_blocks = (nwave + 3) / 4;
     if ((int)blockIdx.x < wave_blocks) {
-        const int w = wave_index(4);
+        const int b = swz ? swizzle_block(blockIdx.x, wave_blocks) : (int)blockIdx.x;
+        const int w = __builtin_amdgcn_readfirstlane(b * 4 + (int)(threadIdx.x >> 6));
         if (w >= nwave) return;
         const WorkItem it = items[w];
         if (w < n_low) belief_low_tile<NB>(gs[it.g], it.t, lane_id());
@@ -297,8 +316,8 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
 
 template <int NA, int NB, bool EXACT, bool MAXP>
 __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
-                                              int nitems, TParams P) {
-    const int w = wave_index(4);
+                                              int nitems, TParams P, int swz) {
+    const int w = wave_item(swz);
     if (w >= nitems) return;
     const WorkItem it = items[w];
     const DevGraph &G = gs[it.g];
@@ -523,8 +542,8 @@ __device__ __forceinline__ void logw_tile(const DevGraph &G, const FTile &ft, in
 // wavefront runs a lane-per-factor tile or one wide factor.
 template <bool MAXP>
 __global__ __launch_bounds__(256) void k_logical(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
-                                                 int nitems, TParams P) {
-    const int w = wave_index(4);
+                                                 int nitems, TParams P, int swz) {
+    const int w = wave_item(swz);
     if (w >= nitems) return;
     const WorkItem it = items[w];
     const DevGraph &G = gs[it.g];
@@ -536,8 +555,9 @@ __global__ __launch_bounds__(256) void k_logical(const DevGraph *__restrict__ gs
 // logical factors of 257 .. 1024 edges
 template <bool MAXP>
 __global__ __launch_bounds__(256) void k_logical_wide(const DevGraph *__restrict__ gs,
-                                                      const WorkItem *__restrict__ items, int nitems, TParams P) {
-    const int w = wave_index(4);
+                                                      const WorkItem *__restrict__ items, int nitems, TParams P,
+                                                      int swz) {
+    const int w = wave_item(swz);
     if (w >= nitems) return;
     const WorkItem it = items[w];
     const DevGraph &G = gs[it.g];
@@ -1024,55 +1044,58 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 // ----------------------------------------------------------------- launchers
 hipError_t launch_belief(const DevGraph *gs, const WorkItem *items, int n_low, int n_mid, int n_high, int bucket,
-                         hipStream_t st) {
+                         const LaunchShape &S, hipStream_t st) {
     if (n_low + n_mid + n_high <= 0) return hipSuccess;
     dim3 grid(blocks_for(n_low + n_mid, 4) + n_high), block(256);
+    const int z = S.swizzle;
     switch (bucket) {
-    case 2: hipLaunchKernelGGL((k_belief<2>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
-    case 4: hipLaunchKernelGGL((k_belief<4>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
-    case 8: hipLaunchKernelGGL((k_belief<8>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
-    default: hipLaunchKernelGGL((k_belief<16>), grid, block, 0, st, gs, items, n_low, n_mid, n_high); break;
+    case 2: hipLaunchKernelGGL((k_belief<2>), grid, block, 0, st, gs, items, n_low, n_mid, n_high, z); break;
+    case 4: hipLaunchKernelGGL((k_belief<4>), grid, block, 0, st, gs, items, n_low, n_mid, n_high, z); break;
+    case 8: hipLaunchKernelGGL((k_belief<8>), grid, block, 0, st, gs, items, n_low, n_mid, n_high, z); break;
+    default: hipLaunchKernelGGL((k_belief<16>), grid, block, 0, st, gs, items, n_low, n_mid, n_high, z); break;
     }
     return hipGetLastError();
 }
 
 template <bool MAXP>
 static void pair_dispatch(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, const TParams &P,
-                          hipStream_t st) {
-    dim3 grid(blocks_for(n, 4)), block(256);
+                          const LaunchShape &S, hipStream_t st) {
+    dim3 grid(blocks_for(n, S.wpb)), block(64 * S.wpb);
+    const int z = S.swizzle;
     if (na == nb) {
         switch (na) {
-        case 2: hipLaunchKernelGGL((k_pair<2, 2, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
-        case 3: hipLaunchKernelGGL((k_pair<3, 3, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
-        case 4: hipLaunchKernelGGL((k_pair<4, 4, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
-        case 5: hipLaunchKernelGGL((k_pair<5, 5, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
-        case 6: hipLaunchKernelGGL((k_pair<6, 6, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
-        case 7: hipLaunchKernelGGL((k_pair<7, 7, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
-        case 8: hipLaunchKernelGGL((k_pair<8, 8, true, MAXP>), grid, block, 0, st, gs, items, n, P); return;
+        case 2: hipLaunchKernelGGL((k_pair<2, 2, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
+        case 3: hipLaunchKernelGGL((k_pair<3, 3, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
+        case 4: hipLaunchKernelGGL((k_pair<4, 4, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
+        case 5: hipLaunchKernelGGL((k_pair<5, 5, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
+        case 6: hipLaunchKernelGGL((k_pair<6, 6, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
+        case 7: hipLaunchKernelGGL((k_pair<7, 7, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
+        case 8: hipLaunchKernelGGL((k_pair<8, 8, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
         default: break;
         }
     }
-    hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP>), grid, block, 0, st, gs, items, n, P);
+    hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP>), grid, block, 0, st, gs, items, n, P, z);
 }
 
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
-                       const TParams &P, hipStream_t st) {
+                       const TParams &P, const LaunchShape &S, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    if (maxp) pair_dispatch<true>(gs, items, n, na, nb, P, st);
-    else pair_dispatch<false>(gs, items, n, na, nb, P, st);
+    if (maxp) pair_dispatch<true>(gs, items, n, na, nb, P, S, st);
+    else pair_dispatch<false>(gs, items, n, na, nb, P, S, st);
     return hipGetLastError();
 }
 
 hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool wide, bool maxp, const TParams &P,
-                          hipStream_t st) {
+                          const LaunchShape &S, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    dim3 grid(blocks_for(n, 4)), block(256);
+    dim3 grid(blocks_for(n, S.wpb)), block(64 * S.wpb);
+    const int z = S.swizzle;
     if (wide) {
-        if (maxp) hipLaunchKernelGGL((k_logical_wide<true>), grid, block, 0, st, gs, items, n, P);
-        else hipLaunchKernelGGL((k_logical_wide<false>), grid, block, 0, st, gs, items, n, P);
+        if (maxp) hipLaunchKernelGGL((k_logical_wide<true>), grid, block, 0, st, gs, items, n, P, z);
+        else hipLaunchKernelGGL((k_logical_wide<false>), grid, block, 0, st, gs, items, n, P, z);
     } else {
-        if (maxp) hipLaunchKernelGGL((k_logical<true>), grid, block, 0, st, gs, items, n, P);
-        else hipLaunchKernelGGL((k_logical<false>), grid, block, 0, st, gs, items, n, P);
+        if (maxp) hipLaunchKernelGGL((k_logical<true>), grid, block, 0, st, gs, items, n, P, z);
+        else hipLaunchKernelGGL((k_logical<false>), grid, block, 0, st, gs, items, n, P, z);
     }
     return hipGetLastError();
 }

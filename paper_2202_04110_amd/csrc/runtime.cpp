@@ -120,15 +120,15 @@ hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, c
     hipError_t e = hipSuccess;
     if (phases & 1)
         for (const Launch &L : vl) {
-            e = launch_belief(gs, L.items, L.n, L.n_mid, L.n_high, L.a, st);
+            e = launch_belief(gs, L.items, L.n, L.n_mid, L.n_high, L.a, L.shape, st);
             if (e != hipSuccess) return e;
         }
     if (phases & 2)
         for (const Launch &L : fl) {
             switch (L.kind) {
-            case TK_PAIR: e = launch_pair(gs, L.items, L.n, L.a, L.b, maxp, P, st); break;
-            case TK_LOGL: e = launch_logical(gs, L.items, L.n, false, maxp, P, st); break;
-            case TK_LOGW: e = launch_logical(gs, L.items, L.n, true, maxp, P, st); break;
+            case TK_PAIR: e = launch_pair(gs, L.items, L.n, L.a, L.b, maxp, P, L.shape, st); break;
+            case TK_LOGL: e = launch_logical(gs, L.items, L.n, false, maxp, P, L.shape, st); break;
+            case TK_LOGW: e = launch_logical(gs, L.items, L.n, true, maxp, P, L.shape, st); break;
             default: e = launch_gen(gs, L.items, L.n, maxp, P, st); break;
             }
             if (e != hipSuccess) return e;

@@ -36,6 +36,7 @@ struct Launch {
     int32_t n;        // items (variable phase: low tiles)
     WorkItem *items;  // device
     int32_t n_mid = 0, n_high = 0;  // variable phase: wavefront- and block-per-variable items after the tiles
+    LaunchShape shape;              // chosen by lbp_autotune (variable phase: swizzle only)
 };
 
 // Host-side launch lists of one graph or of a set of graphs (graph index gi

@@ -19,10 +19,12 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -38,8 +40,55 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Host copy of a graph description (the caller may free its arrays once
+// lbp_server_submit returns).
+struct DescCopy {
+    std::vector<int32_t> nst, kind, evar, ftab, tab_ncfg, tab_arity, tab_states;
+    std::vector<float> ev, lp;
+    std::vector<int64_t> fe_off, tab_off, lp_off;
+    lbp_graph_desc d{};
+
+    // `src` must have passed validate_desc with these sizes.
+    void take(const lbp_graph_desc *src, const int64_t sz[6]) {
+        const int64_t V = sz[0], VS = sz[1], F = sz[2], E = sz[3], Tn = sz[5], NT = src->num_cfg_tables;
+        nst.assign(src->var_num_states, src->var_num_states + V);
+        if (src->evidence) ev.assign(src->evidence, src->evidence + VS);
+        kind.assign(src->factor_kind, src->factor_kind + F);
+        fe_off.assign(src->factor_edge_off, src->factor_edge_off + F + 1);
+        evar.assign(src->edge_var, src->edge_var + E);
+        ftab.assign(src->factor_cfg_table, src->factor_cfg_table + F);
+        if (NT > 0) {
+            tab_ncfg.assign(src->cfg_table_num_cfgs, src->cfg_table_num_cfgs + NT);
+            tab_arity.assign(src->cfg_table_arity, src->cfg_table_arity + NT);
+            tab_off.assign(src->cfg_table_off, src->cfg_table_off + NT + 1);
+            if (tab_off[NT] > 0) tab_states.assign(src->cfg_table_states, src->cfg_table_states + tab_off[NT]);
+        }
+        lp_off.assign(src->logpot_off, src->logpot_off + F + 1);
+        lp.assign(src->log_potentials, src->log_potentials + Tn);
+        d.num_vars = (int32_t)V;
+        d.var_num_states = nst.data();
+        d.evidence = src->evidence ? ev.data() : nullptr;
+        d.num_factors = (int32_t)F;
+        d.factor_kind = kind.data();
+        d.factor_edge_off = fe_off.data();
+        d.edge_var = evar.data();
+        d.factor_cfg_table = ftab.data();
+        d.num_cfg_tables = (int32_t)NT;
+        d.cfg_table_num_cfgs = tab_ncfg.data();
+        d.cfg_table_arity = tab_arity.data();
+        d.cfg_table_off = NT > 0 ? tab_off.data() : nullptr;
+        d.cfg_table_states = tab_states.data();
+        d.logpot_off = lp_off.data();
+        d.log_potentials = lp.data();
+    }
+};
+
 struct Request {
     uint64_t id = 0;
+    uint64_t seq = 0;
+    int prep = 0;  // 0 compiling, 1 ready, 2 failed (guarded by the server mutex)
+    int prep_status = LBP_OK;
+    std::unique_ptr<DescCopy> desc;
     int32_t iters = 0, k = 10;
     float d = 0.5f, T = 1.0f;
     bool backward = false;
@@ -104,6 +153,8 @@ public:
         if (copy_) (void)hipStreamSynchronize(copy_);
         if (stage_) (void)hipFree(stage_);
         if (base_) (void)hipFree(base_);
+        for (auto &kv : pool_)
+            for (void *p : kv.second) (void)hipHostFree(p);
         if (ev_) (void)hipEventDestroy(ev_);
         if (compute_) (void)hipStreamDestroy(compute_);
         if (copy_) (void)hipStreamDestroy(copy_);
@@ -197,26 +248,57 @@ public:
     }
 
     int alloc_outputs(Request &r) override {
-        if (hipHostMalloc((void **)&r.q, sizeof(float) * std::max<int64_t>(1, r.L.VS)) != hipSuccess ||
-            hipHostMalloc((void **)&r.map, sizeof(int32_t) * std::max<int64_t>(1, r.L.V)) != hipSuccess ||
-            (r.backward && hipHostMalloc((void **)&r.gphi, sizeof(float) * std::max<int64_t>(1, r.L.Tn)) != hipSuccess)) {
-            (void)hipGetLastError();
+        r.q = (float *)pinned_get(sizeof(float) * std::max<int64_t>(1, r.L.VS));
+        r.map = (int32_t *)pinned_get(sizeof(int32_t) * std::max<int64_t>(1, r.L.V));
+        if (r.backward) r.gphi = (float *)pinned_get(sizeof(float) * std::max<int64_t>(1, r.L.Tn));
+        if (!r.q || !r.map || (r.backward && !r.gphi)) {
             free_outputs(r);
             return set_error(LBP_E_OOM, "pinned output buffers");
         }
         return LBP_OK;
     }
 
+    // Called from the polling thread: buffers go back to the pool.
     void free_outputs(Request &r) override {
-        if (r.q) (void)hipHostFree(r.q);
-        if (r.map) (void)hipHostFree(r.map);
-        if (r.gphi) (void)hipHostFree(r.gphi);
+        pinned_put(r.q, sizeof(float) * std::max<int64_t>(1, r.L.VS));
+        pinned_put(r.map, sizeof(int32_t) * std::max<int64_t>(1, r.L.V));
+        if (r.gphi) pinned_put(r.gphi, sizeof(float) * std::max<int64_t>(1, r.L.Tn));
         r.q = nullptr;
         r.map = nullptr;
         r.gphi = nullptr;
     }
 
 private:
+    // Pinned host buffers, kept per power-of-two size class and reused.
+    static size_t size_class(size_t bytes) {
+        size_t c = 4096;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    void *pinned_get(size_t bytes) {
+        const size_t c = size_class(bytes);
+        {
+            std::lock_guard<std::mutex> lk(pool_mu_);
+            auto &v = pool_[c];
+            if (!v.empty()) {
+                void *p = v.back();
+                v.pop_back();
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, c) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void pinned_put(void *p, size_t bytes) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(pool_mu_);
+        pool_[size_class(bytes)].push_back(p);
+    }
+
     // Active graphs sharing (damping, temperature) launch together.
     struct Part {
         float d, T;
@@ -283,6 +365,8 @@ private:
     size_t stage_bytes_ = 0;
     std::vector<uint64_t> ids_;
     std::vector<Part> parts_;
+    std::mutex pool_mu_;
+    std::map<size_t, std::vector<void *>> pool_;
 };
 
 }  // namespace
@@ -295,7 +379,11 @@ struct lbp_server {
     std::mutex mu;
     std::condition_variable cv;        // wakes the worker
     std::condition_variable done_cv;   // wakes drain()
-    std::deque<Request *> incoming;    // mu
+    std::deque<Request *> incoming;    // mu: accepted, in submission order (compiled or not)
+    std::deque<Request *> to_prep;     // mu: waiting for a prep thread
+    std::condition_variable prep_cv;
+    std::vector<std::thread> preps;
+    uint64_t next_seq = 0;             // mu
     std::deque<Request *> completed;   // mu
     std::vector<uint64_t> cancels;     // mu
     std::vector<Request *> handed_out; // caller thread: freed at the next poll
@@ -319,10 +407,49 @@ struct lbp_server {
         ++n_finished;
         if (status == LBP_OK || status == LBP_E_NONFINITE) ++n_completed;
         else if (status == LBP_E_STATE) ++n_cancelled;
-        else ++n_failed;
+        else if (status != LBP_E_BUDGET) ++n_failed;
         completed.push_back(r);
         done_cv.notify_all();
     }
+
+    // Prep threads: compile and check queued descriptions, size the request.
+    void prep_loop() {
+        for (;;) {
+            Request *r = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                prep_cv.wait(lk, [&] { return stop || !to_prep.empty(); });
+                if (stop) return;
+                r = to_prep.front();
+                to_prep.pop_front();
+            }
+            int rc = LBP_OK;
+            try {
+                std::string err;
+                rc = compile_desc(&r->desc->d, &r->L, &err);  // validates first
+                if (rc == LBP_OK) rc = check_layout(r->L, &err);
+                if (rc == LBP_OK) {
+                    r->graph_bytes = graph_device_bytes(r->L);
+                    r->bytes = Arena::round(r->graph_bytes);
+                    if (r->backward) {
+                        r->adj_bytes = adjoint_bytes(r->L.M, r->L.VB, r->L.P, r->iters, r->k);
+                        r->bytes += Arena::round(r->adj_bytes) + Arena::round(sizeof(float) * r->L.VS) +
+                                    Arena::round(sizeof(float) * r->L.Tn);
+                    }
+                    if (r->bytes > arena.capacity()) rc = LBP_E_BUDGET;
+                }
+            } catch (const std::bad_alloc &) {
+                rc = LBP_E_OOM;
+            }
+            r->desc.reset();
+            std::lock_guard<std::mutex> lk(mu);
+            r->prep = rc == LBP_OK ? 1 : 2;
+            r->prep_status = rc;
+            cv.notify_one();
+        }
+    }
+
+    bool head_ready() const { return !pending.empty() && pending.front()->prep != 0; }
 
     void drop_resident(Request *r) {
         exec->release(*r);
@@ -332,9 +459,24 @@ struct lbp_server {
     void admit() {
         while (!pending.empty() && (int32_t)resident.size() < max_slots) {
             Request *r = pending.front();
+            int prep;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                prep = r->prep;
+            }
+            if (prep == 0) break;  // first in, first out: wait for its compile
             if (r->cancel) {
                 pending.pop_front();
                 complete(r, LBP_E_STATE);
+                continue;
+            }
+            if (prep == 2) {
+                pending.pop_front();
+                if (r->prep_status == LBP_E_BUDGET) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    ++n_rejected;
+                }
+                complete(r, r->prep_status);
                 continue;
             }
             const size_t off = arena.alloc(r->bytes);
@@ -377,7 +519,10 @@ struct lbp_server {
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv.wait(lk, [&] { return stop || !incoming.empty() || !resident.empty() || !pending.empty(); });
+                cv.wait(lk, [&] {
+                    return stop || !incoming.empty() || !resident.empty() || !cancels.empty() ||
+                           (!pending.empty() && pending.front()->prep != 0);
+                });
                 if (stop) break;
                 while (!incoming.empty()) {
                     pending.push_back(incoming.front());
@@ -480,6 +625,9 @@ int server_create(lbp_ctx *ctx, int64_t budget, int32_t max_slots, int32_t steps
         }
         lbp_server *raw = s.get();
         s->th = std::thread([raw] { raw->run(); });
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const unsigned np = std::min(8u, std::max(1u, hw / 2));
+        for (unsigned i = 0; i < np; ++i) s->preps.emplace_back([raw] { raw->prep_loop(); });
         *out = s.release();
         return LBP_OK;
     } catch (const std::bad_alloc &) {
@@ -510,42 +658,53 @@ int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, 
     std::string why;
     if (!valid_params(iters, damping, temperature, &why)) return set_error(LBP_E_INVALID, why);
     try {
+        // sizes only (full validation runs on the prep threads)
+        if (!desc) return set_error(LBP_E_INVALID, "graph description is NULL");
+        int64_t sz[6] = {desc->num_vars, 0, desc->num_factors, 0, 0, 0};
+        if (sz[0] < 0 || sz[2] < 0 || desc->num_cfg_tables < 0)
+            return set_error(LBP_E_INVALID, "negative num_vars, num_factors or num_cfg_tables");
+        if ((sz[0] > 0 && !desc->var_num_states) || !desc->factor_edge_off || !desc->logpot_off ||
+            (sz[2] > 0 && (!desc->factor_kind || !desc->factor_cfg_table)) ||
+            (desc->num_cfg_tables > 0 && (!desc->cfg_table_num_cfgs || !desc->cfg_table_arity || !desc->cfg_table_off)))
+            return set_error(LBP_E_INVALID, "a required array is NULL");
+        for (int64_t v = 0; v < sz[0]; ++v) {
+            const int32_t n = desc->var_num_states[v];
+            if (n < 2 || n > kMaxStates) return set_error(LBP_E_INVALID, "var_num_states outside [2, 64]");
+            sz[1] += n;
+        }
+        sz[3] = desc->factor_edge_off[sz[2]];
+        sz[5] = desc->logpot_off[sz[2]];
+        const int64_t nts = desc->num_cfg_tables > 0 ? desc->cfg_table_off[desc->num_cfg_tables] : 0;
+        if (desc->factor_edge_off[0] != 0 || sz[3] < 0 || sz[3] > INT32_MAX || desc->logpot_off[0] != 0 ||
+            sz[5] < 0 || nts < 0 || (sz[3] > 0 && !desc->edge_var) || (sz[5] > 0 && !desc->log_potentials) ||
+            (nts > 0 && !desc->cfg_table_states))
+            return set_error(LBP_E_INVALID, "malformed offsets");
         std::unique_ptr<Request> r(new Request);
-        std::string err;
-        int rc = compile_desc(desc, &r->L, &err);
-        if (rc == LBP_OK) rc = check_layout(r->L, &err);
-        if (rc != LBP_OK) return set_error(rc, err);
         r->id = req_id;
         r->iters = iters;
         r->d = damping;
         r->T = temperature;
         r->backward = grad_q != nullptr;
         r->t_arrival = t_arrival >= 0.0 ? t_arrival : s->clock();
-        r->graph_bytes = graph_device_bytes(r->L);
-        r->bytes = Arena::round(r->graph_bytes);
         if (r->backward) {
             if (!(temperature > 0.0f)) return set_error(LBP_E_INVALID, "backward requests need temperature > 0");
             if (ckpt_every < 1) return set_error(LBP_E_INVALID, "ckpt_every must be >= 1");
-            for (const FGroup &fg : r->L.fgroups)
-                if (fg.kind == TK_LOGL || fg.kind == TK_LOGW)
+            for (int64_t f = 0; f < sz[2]; ++f)
+                if (desc->factor_kind[f] != LBP_FACTOR_ENUM)
                     return set_error(LBP_E_UNSUPPORTED, "the adjoint supports enumeration factors only");
             r->k = ckpt_every;
-            r->grad_q.assign(grad_q, grad_q + r->L.VS);
-            r->adj_bytes = adjoint_bytes(r->L.M, r->L.VB, r->L.P, iters, ckpt_every);
-            r->bytes += Arena::round(r->adj_bytes) + Arena::round(sizeof(float) * r->L.VS) +
-                        Arena::round(sizeof(float) * r->L.Tn);
+            r->grad_q.assign(grad_q, grad_q + sz[1]);
         }
-        // the worker only needs what the upload and the read-out read
-        if (r->bytes > s->arena.capacity()) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            ++s->n_rejected;
-            return set_error(LBP_E_BUDGET, "request needs " + std::to_string(r->bytes) +
-                                               " bytes, more than the server budget");
-        }
+        r->desc.reset(new DescCopy);
+        r->desc->take(desc, sz);
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return set_error(LBP_E_STATE, "server is shutting down");
         ++s->n_submitted;
-        s->incoming.push_back(r.release());
+        r->seq = s->next_seq++;
+        Request *raw = r.release();
+        s->incoming.push_back(raw);
+        s->to_prep.push_back(raw);
+        s->prep_cv.notify_one();
         s->cv.notify_one();
         return LBP_OK;
     } catch (const std::bad_alloc &) {
@@ -626,7 +785,10 @@ void lbp_server_destroy(lbp_server *s) {
         s->stop = true;
         s->cv.notify_all();
     }
+    s->prep_cv.notify_all();
     if (s->th.joinable()) s->th.join();
+    for (std::thread &t : s->preps)
+        if (t.joinable()) t.join();
     for (Request *r : s->handed_out) {
         s->exec->free_outputs(*r);
         delete r;

@@ -100,6 +100,10 @@ _sig("lbp_server_poll", C.c_int, [_P, C.POINTER(Completion), C.c_int32, C.POINTE
 _sig("lbp_server_drain", C.c_int, [_P, C.c_double])
 _sig("lbp_server_stats", C.c_int, [_P, _P])
 _sig("lbp_server_destroy", None, [_P])
+_sig("lbp_graph_num_launches", C.c_int, [_P, C.POINTER(C.c_int32)])
+_sig("lbp_graph_get_launch", C.c_int, [_P, C.c_int32, _P])
+_sig("lbp_graph_set_launch", C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32])
+_sig("lbp_autotune", C.c_int, [_P, C.c_float, C.c_float, C.c_int32, _P])
 _sig("lbp_time_phase", C.c_int, [_P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.POINTER(C.c_float)])
 
 EXPORTS = [n for n in dir(_lib) if n.startswith("lbp_")]
@@ -290,6 +294,27 @@ class Graph:
         (all device tensors, float32, flat orders)."""
         check(_lib.lbp_run_bp_backward(self.h, _ptr(grad_q), _ptr(grad_logpot),
                                        _ptr(grad_evidence) if grad_evidence is not None else None))
+
+    def launches(self):
+        """Launch groups: dicts with phase, kind, a, b, wpb, swizzle, items."""
+        n = C.c_int32()
+        check(_lib.lbp_graph_num_launches(self.h, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            v = np.zeros(7, np.int32)
+            check(_lib.lbp_graph_get_launch(self.h, i, _ptr(v)))
+            out.append(dict(zip(("phase", "kind", "a", "b", "wpb", "swizzle", "items"), (int(x) for x in v))))
+        return out
+
+    def set_launch(self, i: int, wpb: int, swizzle: int):
+        check(_lib.lbp_graph_set_launch(self.h, int(i), int(wpb), int(swizzle)))
+
+    def autotune(self, damping: float, temperature: float, reps: int = 20):
+        """Times every candidate launch shape; returns the chosen ms per group."""
+        n = len(self.launches())
+        ms = np.zeros(max(1, n), np.float32)
+        check(_lib.lbp_autotune(self.h, float(damping), float(temperature), int(reps), _ptr(ms)))
+        return ms[:n]
 
     def time_phase(self, phase: int, reps: int, damping: float, temperature: float) -> float:
         ms = C.c_float()

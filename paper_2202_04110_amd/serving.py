@@ -5,16 +5,18 @@ library's worker thread; this module only plays the clients."""
 from __future__ import annotations
 
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 
 def run_stream(server, specs, arrivals, iters: int, damping: float, temperature: float, grad_qs=None,
-               ckpt_every: int = 10, timeout: float = 900.0, start_delay: float = 0.05):
+               ckpt_every: int = 10, timeout: float = 900.0, start_delay: float = 0.05, clients: int = 4):
     """Submits request i (graph specs[i]) at server-clock time
     start + arrivals[i] seconds, with its latency measured from that scheduled
-    time.  grad_qs[i] (or None) asks for the log-potential gradient.  Returns
-    (results by request id, summary)."""
+    time; ``clients`` threads perform the submissions (each copies its
+    request's arrays into the server).  grad_qs[i] (or None) asks for the
+    log-potential gradient.  Returns (results by request id, summary)."""
     n = len(specs)
     order = np.argsort(arrivals, kind="stable")
     t_start = server.clock() + start_delay
@@ -24,6 +26,8 @@ def run_stream(server, specs, arrivals, iters: int, damping: float, temperature:
         for rec in server.poll(256):
             results[rec["req_id"]] = rec
 
+    pool = ThreadPoolExecutor(max_workers=max(1, clients))
+    futures = []
     for i in order:
         due = t_start + float(arrivals[i])
         while True:
@@ -33,8 +37,11 @@ def run_stream(server, specs, arrivals, iters: int, damping: float, temperature:
             collect()
             time.sleep(min(0.002, due - now))
         gq = None if grad_qs is None else grad_qs[i]
-        server.submit(specs[i], iters, damping, temperature, grad_q=gq, ckpt_every=ckpt_every, t_arrival=due,
-                      req_id=int(i))
+        futures.append(pool.submit(server.submit, specs[i], iters, damping, temperature, gq, ckpt_every, due,
+                                   int(i)))
+    for f in futures:
+        f.result()
+    pool.shutdown()
     server.drain(timeout)
     collect()
     while len(results) < n:

@@ -1,0 +1,60 @@
+"""Autotuner front: chooses launch shapes per launch group and caches them in
+JSON, keyed by device, launch kind, shape class and a size bucket.
+
+The measurement is the library's (lbp_autotune: HIP-event timing of every
+candidate shape); this module only reuses earlier choices.  Shapes never
+change results, only speed.  Cache file: $LBP_TUNE_CACHE, else
+~/.cache/lbp_tune.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+
+def cache_path():
+    return os.environ.get("LBP_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "lbp_tune.json")
+
+
+def _key(device, d, T, ln):
+    bucket = int(math.log2(max(1, ln["items"])))
+    mode = "maxprod" if T == 0 else "lse"
+    return "%s|%s|p%d|k%d|a%d|b%d|n2^%d" % (device, mode, ln["phase"], ln["kind"], ln["a"], ln["b"], bucket)
+
+
+def _load(path):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def apply_or_tune(graph, damping: float, temperature: float, reps: int = 20, path=None, device=None):
+    """Applies cached shapes to every launch group of ``graph``; runs the
+    autotuner (and records its choices) when any group is missing."""
+    import torch
+
+    path = path or cache_path()
+    device = device or torch.cuda.get_device_name(graph.ctx.device)
+    cache = _load(path)
+    lns = graph.launches()
+    keys = [_key(device, damping, temperature, ln) for ln in lns]
+    if all(k in cache for k in keys):
+        for i, k in enumerate(keys):
+            graph.set_launch(i, cache[k]["wpb"], cache[k]["swizzle"])
+        return {"source": "cache", "shapes": [cache[k] for k in keys]}
+    ms = graph.autotune(damping, temperature, reps)
+    lns = graph.launches()
+    for k, ln, t in zip(keys, lns, ms):
+        cache[k] = {"wpb": ln["wpb"], "swizzle": ln["swizzle"], "ms": float(t)}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return {"source": "tuned", "shapes": [cache[k] for k in keys]}

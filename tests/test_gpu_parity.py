@@ -415,3 +415,40 @@ def test_graph_replay_matches_eager(lbp, ctx):
             g.run_bp(5, 0.5, 0.0)
         for g, h in zip(gs, gs_e):
             np.testing.assert_array_equal(g.get_messages(), h.get_messages())
+
+
+def test_launch_shapes_do_not_change_bits(lbp, ctx, tmp_path):
+    """Every launch shape the autotuner may pick gives bitwise the same
+    messages; the tuned graph matches the untuned one."""
+    specs = [W.potts_grid(45, 5, 91), W.deconv(seed=4, K=2, tw=4, sd=10, img=12), mixed_graph(92)]
+    for spec in specs:
+        ref = lbp.Graph(ctx, spec)
+        ref.run_bp(12, 0.5, 1.0)
+        m_ref = ref.get_messages()
+        g = lbp.Graph(ctx, spec)
+        for i, ln in enumerate(g.launches()):
+            shapes = [(4, 0), (4, 1)] if (ln["phase"] == 0 or ln["kind"] == 3) else \
+                [(w, z) for w in (1, 2, 4) for z in (0, 1)]
+            for w, z in shapes:
+                g.set_launch(i, w, z)
+                g.reset_messages()
+                g.run_bp(12, 0.5, 1.0)
+                np.testing.assert_array_equal(g.get_messages(), m_ref)
+        g.reset_messages()
+        g.run_bp(5, 0.5, 1.0)
+        before = g.get_messages()
+        ms = g.autotune(0.5, 1.0, reps=3)
+        assert len(ms) == len(g.launches()) and np.all(ms > 0)
+        np.testing.assert_array_equal(g.get_messages(), before)  # tuning restores the messages
+        g.reset_messages()
+        g.run_bp(12, 0.5, 1.0)
+        np.testing.assert_array_equal(g.get_messages(), m_ref)
+    # JSON cache round trip
+    from paper_2202_04110_amd import tune
+    path = str(tmp_path / "tune.json")
+    g = lbp.Graph(ctx, specs[0])
+    r1 = tune.apply_or_tune(g, 0.5, 1.0, reps=3, path=path)
+    g2 = lbp.Graph(ctx, specs[0])
+    r2 = tune.apply_or_tune(g2, 0.5, 1.0, reps=3, path=path)
+    assert r1["source"] == "tuned" and r2["source"] == "cache"
+    assert [(l["wpb"], l["swizzle"]) for l in g.launches()] == [(l["wpb"], l["swizzle"]) for l in g2.launches()]
