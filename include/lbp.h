@@ -323,12 +323,25 @@ int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out);
 int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[7]);
 int lbp_graph_set_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle);
 int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, float *best_ms_out);
+/* Fused iterations: for a graph whose variables all have at most 16 edges and
+ * 16 states and whose factors are all dense pairwise with equal slot sizes,
+ * a whole iteration can run in the factor launch (each factor recomputes its
+ * variables' beliefs from the previous messages, with the variable phase's
+ * exact arithmetic; messages alternate between two buffers and always end in
+ * the graph's own).  Results are bitwise identical either way; speed depends
+ * on the graph and cache sizes, so lbp_autotune switches it on only when it
+ * measures faster.  Off by default.  out = {available, in use}. */
+int lbp_graph_use_fused(lbp_graph *g, int enable);
+int lbp_graph_fused_state(const lbp_graph *g, int32_t out[2]);
 
 /* Diagnostic timing: runs `reps` launches of one phase of an iteration on the
- * current messages and returns the mean launch time in milliseconds measured
- * with HIP events on the context's stream.  phase 0 = variable (belief)
- * kernels, 1 = factor kernels, 2 = one whole iteration.  The factor phase
- * updates the messages, like an iteration does. */
+ * current messages and returns the mean time per launch (per iteration for
+ * phases 2 and 3) in milliseconds, measured with HIP events on the context's
+ * stream.  phase 0 = variable (belief) kernels, 1 = factor kernels (in
+ * place), 2 = two-phase iterations, 3 = fused iterations (graphs whose
+ * variables all have at most 16 edges and 16 states and whose factors are
+ * all dense pairwise with equal slot sizes; lbp_run_bp uses them for such
+ * graphs, with bitwise the same results).  Phases 1-3 update the messages. */
 int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, float temperature,
                    float *ms_out);
 

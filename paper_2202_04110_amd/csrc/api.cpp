@@ -137,7 +137,7 @@ int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out) 
         if (rc == LBP_OK) rc = check_layout(L, &err);
         if (rc != LBP_OK) return fail(rc, err);
         HIP_TRY(hipSetDevice(ctx->device));
-        return graph_create(ctx, L, nullptr, ctx->stream, out);
+        return graph_create(ctx, L, true, nullptr, ctx->stream, out);
     } catch (const std::bad_alloc &) {
         return fail(LBP_E_OOM, "host allocation failed");
     }
@@ -213,7 +213,8 @@ int lbp_run_bp(lbp_graph *g, int32_t iters, float damping, float temperature) {
     if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
     HIP_TRY(hipSetDevice(g->ctx->device));
     ++g->version;
-    hipError_t e = run_loop(g->ctx, g->loops, g->dgraph, g->vl, g->fl, iters, damping, temperature);
+    hipError_t e = run_loop(g->ctx, g->loops, g->dgraph, g->use_fused ? g->fused : nullptr, g->vl, g->fl, iters,
+                            damping, temperature);
     if (e != hipSuccess) return hip_error(e, "iteration launch");
     g->last_T = temperature;
     return LBP_OK;
@@ -254,7 +255,8 @@ int lbp_decode_map(lbp_graph *g, int32_t *out, int out_on_device) {
 
 int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, float temperature, float *ms_out) {
     if (!g || !ms_out) return fail(LBP_E_INVALID, "graph or ms_out is NULL");
-    if (phase < 0 || phase > 2 || reps < 1) return fail(LBP_E_INVALID, "phase must be 0..2 and reps >= 1");
+    if (phase < 0 || phase > 3 || reps < 1) return fail(LBP_E_INVALID, "phase must be 0..3 and reps >= 1");
+    if (phase == 3 && !g->fused) return fail(LBP_E_INVALID, "the graph has no fused iteration");
     std::string why;
     if (!valid_params(0, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
     HIP_TRY(hipSetDevice(g->ctx->device));
@@ -271,7 +273,15 @@ int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, flo
     }
     e = hipEventRecord(a, st);
     if (phases & 2) ++g->version;
-    for (int32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_iteration(g->dgraph, g->vl, g->fl, P, maxp, st, phases);
+    if (phase == 2 || phase == 3) {
+        // iterations as lbp_run_bp runs them (phase 3: fused, in pairs)
+        if (e == hipSuccess)
+            e = launch_loop(g->dgraph, phase == 3 ? g->fused : nullptr, g->vl, g->fl, 2 * reps, P, maxp, st);
+        reps *= 2;
+    } else {
+        for (int32_t r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_iteration(g->dgraph, g->vl, g->fl, P, maxp, st, phases);
+    }
     if (e == hipSuccess) e = hipEventRecord(b, st);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float ms = 0.0f;
@@ -398,6 +408,23 @@ int lbp_graph_set_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32
     return LBP_OK;
 }
 
+int lbp_graph_use_fused(lbp_graph *g, int enable) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    if (enable && !g->fused) return fail(LBP_E_INVALID, "the graph has no fused iteration");
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    destroy_loops(g->loops);
+    g->use_fused = enable != 0;
+    return LBP_OK;
+}
+
+int lbp_graph_fused_state(const lbp_graph *g, int32_t out[2]) {
+    if (!g || !out) return fail(LBP_E_INVALID, "graph or out is NULL");
+    out[0] = g->fused != nullptr;
+    out[1] = g->use_fused;
+    return LBP_OK;
+}
+
 int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, float *best_ms_out) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");
     std::string why;
@@ -415,6 +442,28 @@ int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, f
     e = hipMemcpyAsync(save, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
     int rc = e == hipSuccess ? tune_launches(g->dgraph, g->vl, g->fl, damping, temperature, reps, st, best_ms_out)
                              : hip_error(e, "autotune backup");
+    if (rc == LBP_OK && g->fused) {
+        // fused or two-phase iterations, whichever is faster on this graph
+        const TParams P = make_params(damping, temperature);
+        const bool maxp = temperature == 0.0f;
+        float t2 = 0.0f, tf = 0.0f;
+        hipEvent_t a = nullptr, b = nullptr;
+        e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+            const DevGraph *fz = pass ? g->fused : nullptr;
+            e = launch_loop(g->dgraph, fz, g->vl, g->fl, 2, P, maxp, st);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(a, st);
+            if (e == hipSuccess) e = launch_loop(g->dgraph, fz, g->vl, g->fl, 2 * reps, P, maxp, st);
+            if (e == hipSuccess) e = hipEventRecord(b, st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            if (e == hipSuccess) e = hipEventElapsedTime(pass ? &tf : &t2, a, b);
+        }
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        if (e != hipSuccess) rc = hip_error(e, "autotune fused");
+        else g->use_fused = tf < t2;
+    }
     e = hipMemcpyAsync(g->host.m, save, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(save);
@@ -443,7 +492,8 @@ int lbp_run_bp_record(lbp_graph *g, int32_t iters, float damping, float temperat
             rc = adjoint_checkpoint(g, sidx, st);
             if (rc != LBP_OK) return rc;
             const int32_t len = std::min(k, iters - sidx * k);
-            hipError_t e = run_loop(g->ctx, g->loops, g->dgraph, g->vl, g->fl, len, damping, temperature);
+            hipError_t e = run_loop(g->ctx, g->loops, g->dgraph, g->use_fused ? g->fused : nullptr, g->vl, g->fl, len,
+                                    damping, temperature);
             if (e != hipSuccess) return hip_error(e, "recorded iteration launch");
         }
         g->last_T = temperature;
@@ -518,7 +568,7 @@ int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature)
     std::string why;
     if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
     HIP_TRY(hipSetDevice(b->ctx->device));
-    hipError_t e = run_loop(b->ctx, b->loops, b->dgraphs, b->vl, b->fl, iters, damping, temperature);
+    hipError_t e = run_loop(b->ctx, b->loops, b->dgraphs, nullptr, b->vl, b->fl, iters, damping, temperature);
     if (e != hipSuccess) return hip_error(e, "batch iteration launch");
     for (lbp_graph *g : b->graphs) {
         g->last_T = temperature;

@@ -7,6 +7,7 @@
 // classes and the tile tables are this library's own.
 #include "compile.h"
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <map>
@@ -217,6 +218,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
     auto add_vb_rows = [&](int32_t rows) {
         const size_t base = L->fvb.size();
         L->fvb.resize(base + (size_t)rows * kLanes);
+        L->fvar.resize(base + (size_t)rows * kLanes, -1);
         for (int32_t r = 0; r < rows; ++r)
             for (int32_t l = 0; l < kLanes; ++l) L->fvb[base + (size_t)r * kLanes + l] = b_zero + l;
     };
@@ -306,6 +308,17 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
         return x < INT32_MAX - 4096 ? LBP_OK : bad(err, std::string(what) + " exceeds 2^31 floats", LBP_E_UNSUPPORTED);
     };
     std::vector<std::pair<int64_t, float>> phi_fill;  // filled after sizing
+    // Within a lane-per-factor class, order factors by the 64-variable block
+    // of their first variable (then by index): a tile's factors then touch
+    // few variable tiles, which keeps belief reads local.  Tile membership
+    // does not change any factor's arithmetic.
+    for (size_t c = 0; c < class_key.size(); ++c) {
+        if (std::get<0>(class_key[c]) == TK_LOGW) continue;
+        std::vector<int32_t> &fl = class_facs[c];
+        std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) {
+            return d->edge_var[d->factor_edge_off[x]] / kLanes < d->edge_var[d->factor_edge_off[y]] / kLanes;
+        });
+    }
     for (size_t c = 0; c < class_key.size(); ++c) {
         const int32_t kind = std::get<0>(class_key[c]);
         const std::vector<int32_t> &facs = class_facs[c];
@@ -333,6 +346,8 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                     L->edge_maddr[e0 + 1] = (int32_t)(M + (int64_t)na * kLanes + l);
                     L->fvb[ft.vb_off + l] = vaddr[d->edge_var[e0]];
                     L->fvb[ft.vb_off + kLanes + l] = vaddr[d->edge_var[e0 + 1]];
+                    L->fvar[ft.vb_off + l] = d->edge_var[e0];
+                    L->fvar[ft.vb_off + kLanes + l] = d->edge_var[e0 + 1];
                     L->fac_phi[f] = (int32_t)(P + l);
                 }
                 M += (int64_t)kLanes * (na + nb);
@@ -357,6 +372,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                     for (int32_t j = 0; j < k; ++j) {
                         L->edge_maddr[e0 + j] = (int32_t)(M + (int64_t)2 * j * kLanes + l);
                         L->fvb[ft.vb_off + j * kLanes + l] = vaddr[d->edge_var[e0 + j]];
+                        L->fvar[ft.vb_off + j * kLanes + l] = d->edge_var[e0 + j];
                     }
                 }
                 M += (int64_t)kLanes * 2 * k;
@@ -382,6 +398,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                     const int32_t ch = j / kLanes, l = j % kLanes;
                     L->edge_maddr[e0 + j] = (int32_t)(M + (int64_t)ch * 2 * kLanes + l);
                     L->fvb[ft.vb_off + j] = vaddr[d->edge_var[e0 + j]];
+                    L->fvar[ft.vb_off + j] = d->edge_var[e0 + j];
                 }
                 M += (int64_t)chunks * 2 * kLanes;
                 if ((rc = check(M, "message array"))) return rc;
@@ -438,6 +455,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                     for (int32_t j = 0; j < k; ++j) {
                         L->edge_maddr[e0 + j] = (int32_t)(M + (int64_t)gc.slot_row[j] * kLanes + l);
                         L->fvb[ft.vb_off + j * kLanes + l] = vaddr[d->edge_var[e0 + j]];
+                        L->fvar[ft.vb_off + j * kLanes + l] = d->edge_var[e0 + j];
                     }
                     L->fac_phi[f] = (int32_t)(P + l);
                 }
@@ -520,6 +538,10 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
     if (L->vedge.size() >= (size_t)INT32_MAX || L->hedge.size() >= (size_t)INT32_MAX ||
         L->fvb.size() >= (size_t)INT32_MAX)
         return bad(err, "index tables exceed 2^31 entries", LBP_E_UNSUPPORTED);
+
+    L->fusable = L->hvar.empty() && !L->fgroups.empty();
+    for (const FGroup &fg : L->fgroups)
+        if (fg.kind != TK_PAIR || fg.a != fg.b) L->fusable = false;
 
     // -------------------------------------------------------------- values
     L->theta_panel.assign(L->VB, 0.0f);
@@ -642,6 +664,29 @@ int check_layout(const HostLayout &L, std::string *err) {
         if (L.fac_phi[f] >= 0 && !in(L.fac_phi[f] + (L.lp_off[f + 1] - L.lp_off[f] - 1) * kLanes, P))
             return oob("factor potential address");
     if (!in(L.zero_addr + (int64_t)kLowStatesMax * kLanes - 1, M)) return oob("zero panel");
+    if (L.fvar.size() != L.fvb.size()) return oob("fvar size");
+    if (L.fusable) {
+        // the fused pairwise kernel recomputes each slot variable's belief from
+        // its edge rows: the variable's tile, lane states and edge addresses
+        for (const FGroup &fg : L.fgroups)
+            for (int32_t t : fg.tiles) {
+                const FTile &ft = L.ftile[t];
+                for (int32_t r = 0; r < 2; ++r)
+                    for (int32_t l = 0; l < ft.nact; ++l) {
+                        const int32_t v = L.fvar[ft.vb_off + (int64_t)r * kLanes + l];
+                        if (!in(v, L.V)) return oob("fused slot variable");
+                        const VTile &vt = L.vtile[v / kLanes];
+                        const int32_t n = L.vns[v];
+                        if (n != (r == 0 ? ft.a : ft.b)) return oob("fused slot states");
+                        for (int32_t k = 0; k < vt.kmax; ++k) {
+                            const int64_t ei = vt.e_off + (int64_t)k * kLanes + v % kLanes;
+                            if (!in(ei, (int64_t)L.vedge.size()) || !in(L.vedge[ei] + (int64_t)(n - 1) * kLanes, M))
+                                return oob("fused edge rows");
+                        }
+                        if (!in(vt.b_off + v % kLanes + (int64_t)(n - 1) * kLanes, VB)) return oob("fused evidence");
+                    }
+            }
+    }
     return LBP_OK;
 }
 

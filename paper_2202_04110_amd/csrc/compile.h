@@ -31,6 +31,8 @@ struct HostLayout {
     int32_t zero_addr = 0;
     std::vector<FTile> ftile;
     std::vector<int32_t> fvb;
+    std::vector<int32_t> fvar;  // variable of each (tile, slot, lane), same indexing as fvb (-1 idle)
+    bool fusable = false;       // every variable on the lane path, every factor dense pairwise
     std::vector<VTile> vtile;
     std::vector<int32_t> vedge, vns;
     std::vector<HVar> hvar;

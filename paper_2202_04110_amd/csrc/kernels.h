@@ -38,8 +38,10 @@ struct AdjBufs {
 // (indices into the graph's hvar list); bucket >= states of every low lane.
 hipError_t launch_belief(const DevGraph *gs, const WorkItem *items, int n_low, int n_mid, int n_high, int bucket,
                          const LaunchShape &S, hipStream_t st);
+// fused: one whole iteration in the factor launch (square classes only; see
+// pair_tile), reading G.m and writing G.mo.
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
-                       const TParams &P, const LaunchShape &S, hipStream_t st);
+                       const TParams &P, const LaunchShape &S, hipStream_t st, bool fused = false);
 // Logical tiles: wide = false for lane tiles and factors of <= 256 edges,
 // true for factors of 257..1024 edges.
 hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool wide, bool maxp, const TParams &P,

@@ -131,6 +131,38 @@ __device__ __forceinline__ void belief_low_tile(const DevGraph &G, int t, int la
         if (s < n) G.B[base + s * kLanes] = acc[s];
 }
 
+// The belief of variable v (a lane-path variable with n states) in
+// registers: the same additions in the same order as belief_low_tile.
+template <int N>
+__device__ __forceinline__ void belief_regs(const DevGraph &G, int v, int n, float (&b)[N]) {
+    constexpr int KU = N <= 4 ? 8 : 4;
+#pragma unroll
+    for (int s = 0; s < N; ++s) b[s] = 0.0f;
+    if (v < 0) return;
+    const VTile vt = G.vtile[v >> 6];
+    const int l = v & (kLanes - 1);
+    const int base = vt.b_off + l;
+#pragma unroll
+    for (int s = 0; s < N; ++s)
+        if (s < n) b[s] = G.theta[base + s * kLanes];
+    const int32_t *ea = G.vedge + vt.e_off + l;
+    for (int k0 = 0; k0 < vt.kmax; k0 += KU) {
+        int a[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) a[u] = (k0 + u < vt.kmax) ? ea[(k0 + u) * kLanes] : -1;
+        float x[KU][N];
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+            for (int s = 0; s < N; ++s) x[u][s] = (a[u] >= 0 && s < n) ? G.m[a[u] + s * kLanes] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+            for (int s = 0; s < N; ++s)
+                if (a[u] >= 0 && s < n) b[s] += x[u][s];
+    }
+}
+
 // mid: lane l holds edge l; a butterfly over the wavefront (every lane ends
 // with the same bits) sums each state.
 __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int lane) {
@@ -235,29 +267,51 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
 // equal to LSE over the configurations with that slot fixed, minus the slot's
 // own incoming term.  EXACT: NA x NB known at compile time; otherwise the
 // tile's (a, b) <= (NA, NB) are read at run time with the same arithmetic.
-template <int NA, int NB, bool EXACT, bool MAXP>
+// FUSED: the two slot beliefs are recomputed here from the messages being
+// read (belief_regs, the variable phase's exact arithmetic) instead of being
+// read from B, so one launch does a whole iteration; messages are then read
+// from G.m and written to G.mo, a different buffer.
+template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED>
 __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
     const int na = EXACT ? NA : ft.a;
     const int nb = EXACT ? NB : ft.b;
-    const int va = G.fvb[ft.vb_off + lane];
-    const int vb = G.fvb[ft.vb_off + kLanes + lane];
     const float *r0 = G.m + ft.m_off + lane;
     const float *r1 = r0 + na * kLanes;
     float *w0 = G.mo + ft.m_off + lane;
     float *w1 = w0 + na * kLanes;
     float m0[NA], m1[NB], x0[NA], x1[NB];
+    if (FUSED) {
+        float b0[NA], b1[NB];
+        belief_regs<NA>(G, G.fvar[ft.vb_off + lane], na, b0);
+        belief_regs<NB>(G, G.fvar[ft.vb_off + kLanes + lane], nb, b1);
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
-        if (i < na) {
-            m0[i] = r0[i * kLanes];
-            x0[i] = G.B[va + i * kLanes] - m0[i];
-        }
+        for (int i = 0; i < NA; ++i)
+            if (i < na) {
+                m0[i] = r0[i * kLanes];
+                x0[i] = b0[i] - m0[i];
+            }
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-        if (j < nb) {
-            m1[j] = r1[j * kLanes];
-            x1[j] = G.B[vb + j * kLanes] - m1[j];
-        }
+        for (int j = 0; j < NB; ++j)
+            if (j < nb) {
+                m1[j] = r1[j * kLanes];
+                x1[j] = b1[j] - m1[j];
+            }
+    } else {
+        const int va = G.fvb[ft.vb_off + lane];
+        const int vb = G.fvb[ft.vb_off + kLanes + lane];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            if (i < na) {
+                m0[i] = r0[i * kLanes];
+                x0[i] = G.B[va + i * kLanes] - m0[i];
+            }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < nb) {
+                m1[j] = r1[j * kLanes];
+                x1[j] = G.B[vb + j * kLanes] - m1[j];
+            }
+    }
     const float *ph = G.phi + ft.phi_off + lane;
     float p[NA][NB];
 #pragma unroll
@@ -314,7 +368,7 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
     damp_store<NB>(w1, m1, u1, nb, P);
 }
 
-template <int NA, int NB, bool EXACT, bool MAXP>
+template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED>
 __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
                                               int nitems, TParams P, int swz) {
     const int w = wave_item(swz);
@@ -322,7 +376,7 @@ __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, c
     const WorkItem it = items[w];
     const DevGraph &G = gs[it.g];
     const FTile ft = G.ftile[it.t];
-    pair_tile<NA, NB, EXACT, MAXP>(G, ft, lane_id(), P);
+    pair_tile<NA, NB, EXACT, MAXP, FUSED>(G, ft, lane_id(), P);
 }
 
 // --------------------------------------------------------------------------
@@ -1057,31 +1111,44 @@ hipError_t launch_belief(const DevGraph *gs, const WorkItem *items, int n_low, i
     return hipGetLastError();
 }
 
-template <bool MAXP>
+template <bool MAXP, bool FUSED>
 static void pair_dispatch(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, const TParams &P,
                           const LaunchShape &S, hipStream_t st) {
     dim3 grid(blocks_for(n, S.wpb)), block(64 * S.wpb);
     const int z = S.swizzle;
+#define PAIR_CASE(N)                                                                                   \
+    case N:                                                                                            \
+        hipLaunchKernelGGL((k_pair<N, N, true, MAXP, FUSED>), grid, block, 0, st, gs, items, n, P, z); \
+        return;
     if (na == nb) {
         switch (na) {
-        case 2: hipLaunchKernelGGL((k_pair<2, 2, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
-        case 3: hipLaunchKernelGGL((k_pair<3, 3, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
-        case 4: hipLaunchKernelGGL((k_pair<4, 4, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
-        case 5: hipLaunchKernelGGL((k_pair<5, 5, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
-        case 6: hipLaunchKernelGGL((k_pair<6, 6, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
-        case 7: hipLaunchKernelGGL((k_pair<7, 7, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
-        case 8: hipLaunchKernelGGL((k_pair<8, 8, true, MAXP>), grid, block, 0, st, gs, items, n, P, z); return;
+            PAIR_CASE(2)
+            PAIR_CASE(3)
+            PAIR_CASE(4)
+            PAIR_CASE(5)
+            PAIR_CASE(6)
+            PAIR_CASE(7)
+            PAIR_CASE(8)
         default: break;
         }
     }
-    hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP>), grid, block, 0, st, gs, items, n, P, z);
+#undef PAIR_CASE
+    if (!FUSED)
+        hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP, false>), grid, block, 0, st, gs,
+                           items, n, P, z);
 }
 
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
-                       const TParams &P, const LaunchShape &S, hipStream_t st) {
+                       const TParams &P, const LaunchShape &S, hipStream_t st, bool fused) {
     if (n <= 0) return hipSuccess;
-    if (maxp) pair_dispatch<true>(gs, items, n, na, nb, P, S, st);
-    else pair_dispatch<false>(gs, items, n, na, nb, P, S, st);
+    if (fused && (na != nb || na < 2 || na > kPairStatesMax)) return hipErrorInvalidValue;
+    if (fused) {
+        if (maxp) pair_dispatch<true, true>(gs, items, n, na, nb, P, S, st);
+        else pair_dispatch<false, true>(gs, items, n, na, nb, P, S, st);
+    } else {
+        if (maxp) pair_dispatch<true, false>(gs, items, n, na, nb, P, S, st);
+        else pair_dispatch<false, false>(gs, items, n, na, nb, P, S, st);
+    }
     return hipGetLastError();
 }
 

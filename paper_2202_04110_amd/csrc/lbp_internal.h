@@ -78,6 +78,7 @@ struct DevGraph {
     float *phi;           // potentials (panels)
     const FTile *ftile;
     const int32_t *fvb;   // belief address of each (tile, slot, lane)
+    const int32_t *fvar;  // variable of each (tile, slot, lane), -1 for idle lanes
     const VTile *vtile;
     const int32_t *vedge; // message address of each (var tile, k, lane)
     const int32_t *vns;   // states of each low-degree lane, 0 for others

@@ -136,6 +136,21 @@ hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, c
     return e;
 }
 
+hipError_t launch_loop(const DevGraph *gs, const DevGraph *fused, const std::vector<Launch> &vl,
+                       const std::vector<Launch> &fl, int32_t iters, const TParams &P, bool maxp, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    int32_t it = 0;
+    if (fused)
+        for (; it + 1 < iters && e == hipSuccess; it += 2)
+            for (int h = 0; h < 2 && e == hipSuccess; ++h)
+                for (const Launch &L : fl) {
+                    e = launch_pair(fused + h, L.items, L.n, L.a, L.b, maxp, P, L.shape, st, true);
+                    if (e != hipSuccess) break;
+                }
+    for (; it < iters && e == hipSuccess; ++it) e = launch_iteration(gs, vl, fl, P, maxp, st);
+    return e;
+}
+
 // ------------------------------------------------------------ captured loops
 namespace {
 constexpr size_t kMaxCachedLoops = 4;
@@ -146,18 +161,13 @@ void destroy_loops(std::vector<CachedLoop> &v) {
     v.clear();
 }
 
-hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const std::vector<Launch> &vl,
-                    const std::vector<Launch> &fl, int32_t iters, float d, float T) {
+hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const DevGraph *fused,
+                    const std::vector<Launch> &vl, const std::vector<Launch> &fl, int32_t iters, float d, float T) {
     const TParams P = make_params(d, T);
     const bool maxp = T == 0.0f;
     const size_t per_iter = vl.size() + fl.size();
-    if (!ctx->use_graphs || iters < 2 || per_iter == 0) {
-        for (int32_t it = 0; it < iters; ++it) {
-            hipError_t e = launch_iteration(gs, vl, fl, P, maxp, ctx->stream);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    }
+    if (!ctx->use_graphs || iters < 2 || per_iter == 0)
+        return launch_loop(gs, fused, vl, fl, iters, P, maxp, ctx->stream);
     for (const CachedLoop &c : cache)
         if (c.iters == iters && c.d == d && c.T == T) return hipGraphLaunch(c.exec, ctx->stream);
     if (!ctx->capture) {
@@ -166,9 +176,7 @@ hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph
     }
     hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = hipSuccess;
-    for (int32_t it = 0; it < iters && le == hipSuccess; ++it)
-        le = launch_iteration(gs, vl, fl, P, maxp, ctx->capture);
+    hipError_t le = launch_loop(gs, fused, vl, fl, iters, P, maxp, ctx->capture);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -201,10 +209,12 @@ struct Piece {
 struct GraphPieces {
     std::vector<Piece> p;
     size_t total = 0;
-    size_t m, B, th, phi, ft, fvb, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
+    size_t m, B, th, phi, ft, fvb, fvar, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
+    size_t m2 = 0, fdg = 0;
+    bool fused;
     LaunchLists ll;
 
-    explicit GraphPieces(const HostLayout &L) {
+    GraphPieces(const HostLayout &L, bool with_fused) : fused(with_fused && L.fusable) {
         auto add = [&](const void *src, size_t bytes) {
             p.push_back(Piece{src, bytes, total});
             total += align256(std::max<size_t>(bytes, 4));
@@ -216,6 +226,7 @@ struct GraphPieces {
         phi = add(L.phi_panel.data(), sizeof(float) * L.P);
         ft = add(L.ftile.data(), sizeof(FTile) * L.ftile.size());
         fvb = add(L.fvb.data(), sizeof(int32_t) * L.fvb.size());
+        fvar = add(L.fvar.data(), sizeof(int32_t) * L.fvar.size());
         vt = add(L.vtile.data(), sizeof(VTile) * L.vtile.size());
         ve = add(L.vedge.data(), sizeof(int32_t) * L.vedge.size());
         vns = add(L.vns.data(), sizeof(int32_t) * L.vns.size());
@@ -238,17 +249,21 @@ struct GraphPieces {
         add_to_lists(ll, 0, s, &mids, &highs);
         finish_lists(ll, mids, highs);
         items = add(nullptr, lists_bytes(ll));
+        if (fused) {
+            m2 = add(nullptr, sizeof(float) * L.M);
+            fdg = add(nullptr, sizeof(DevGraph) * 2);
+        }
     }
 };
 
 }  // namespace
 
-size_t graph_device_bytes(const HostLayout &L) { return GraphPieces(L).total; }
+size_t graph_device_bytes(const HostLayout &L, bool with_fused) { return GraphPieces(L, with_fused).total; }
 
-int graph_create(lbp_ctx *ctx, const HostLayout &L, char *mem, hipStream_t st, lbp_graph **out) {
+int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out) {
     lbp_graph *g = nullptr;
     try {
-        GraphPieces gp(L);
+        GraphPieces gp(L, with_fused);
         g = new lbp_graph;
         g->ctx = ctx;
         if (mem) {
@@ -281,6 +296,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, char *mem, hipStream_t st, l
         h.phi = (float *)ptr(gp.phi);
         h.ftile = (const FTile *)ptr(gp.ft);
         h.fvb = (const int32_t *)ptr(gp.fvb);
+        h.fvar = (const int32_t *)ptr(gp.fvar);
         h.vtile = (const VTile *)ptr(gp.vt);
         h.vedge = (const int32_t *)ptr(gp.ve);
         h.vns = (const int32_t *)ptr(gp.vns);
@@ -303,6 +319,18 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, char *mem, hipStream_t st, l
         g->q_tmp = (float *)ptr(gp.q);
         g->map_tmp = (int32_t *)ptr(gp.map);
         if (e == hipSuccess) e = hipMemcpyAsync(g->dgraph, &g->host, sizeof(DevGraph), hipMemcpyHostToDevice, st);
+        DevGraph fv[2];
+        if (gp.fused) {
+            float *m2 = (float *)ptr(gp.m2);
+            fv[0] = g->host;
+            fv[0].mo = m2;
+            fv[1] = g->host;
+            fv[1].m = m2;
+            fv[1].mo = g->host.m;
+            g->fused = (DevGraph *)ptr(gp.fdg);
+            if (e == hipSuccess) e = hipMemsetAsync(m2, 0, sizeof(float) * L.M, st);  // its zero panel
+            if (e == hipSuccess) e = hipMemcpyAsync(g->fused, fv, sizeof(fv), hipMemcpyHostToDevice, st);
+        }
         if (e == hipSuccess) e = upload_lists(gp.ll, (char *)ptr(gp.items), st, &g->vl, &g->fl);
         // the host staging (L, gp) must outlive the copies
         if (e == hipSuccess) e = hipStreamSynchronize(st);

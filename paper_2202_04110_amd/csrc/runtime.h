@@ -61,6 +61,12 @@ hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::v
 
 hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, const std::vector<Launch> &fl,
                             const TParams &P, bool maxp, hipStream_t st, int phases = 3);
+// `iters` iterations of a fusable graph: pairs of fused iterations through
+// the second message buffer (fused[0]: m -> m2, fused[1]: m2 -> m), then one
+// two-phase in-place iteration on gs if iters is odd, so the messages end in
+// the graph's own buffer.  Bitwise the same as two-phase iterations.
+hipError_t launch_loop(const DevGraph *gs, const DevGraph *fused, const std::vector<Launch> &vl,
+                       const std::vector<Launch> &fl, int32_t iters, const TParams &P, bool maxp, hipStream_t st);
 
 // A captured fixed-iteration loop, replayed with hipGraphLaunch.
 struct CachedLoop {
@@ -95,6 +101,8 @@ struct lbp_graph {
     bool owns_memory = true;
     lbp::DevGraph host{};             // device pointers, host copy
     lbp::DevGraph *dgraph = nullptr;  // device copy
+    lbp::DevGraph *fused = nullptr;   // device [2]: fused views over the two message buffers, or null
+    bool use_fused = false;           // lbp_run_bp runs fused iterations (chosen by the autotuner)
     float *q_tmp = nullptr;           // VS
     int32_t *map_tmp = nullptr;       // V
     std::vector<lbp::Launch> vl, fl;  // the graph's own launches
@@ -132,15 +140,17 @@ namespace lbp {
 // Runs `iters` iterations on the context's stream: through a cached captured
 // graph when enabled (same kernels and arguments as eager launches), else by
 // launching each kernel.
-hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const std::vector<Launch> &vl,
-                    const std::vector<Launch> &fl, int32_t iters, float d, float T);
+// fused: the graph's fused views (nullptr for two-phase iterations).
+hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const DevGraph *fused,
+                    const std::vector<Launch> &vl, const std::vector<Launch> &fl, int32_t iters, float d, float T);
 
-// Device bytes an uploaded layout occupies.
-size_t graph_device_bytes(const HostLayout &L);
+// Device bytes an uploaded layout occupies (with_fused: plus the second
+// message buffer and views of the fused iteration, if the layout allows it).
+size_t graph_device_bytes(const HostLayout &L, bool with_fused);
 // Creates a graph from a compiled (and checked) layout.  mem: a 256-aligned
-// region of graph_device_bytes(L) bytes the caller owns, or nullptr to
-// allocate.  Copies run on `st`, and the call waits for them.
-int graph_create(lbp_ctx *ctx, const HostLayout &L, char *mem, hipStream_t st, lbp_graph **out);
+// region of graph_device_bytes(L, with_fused) bytes the caller owns, or
+// nullptr to allocate.  Copies run on `st`, and the call waits for them.
+int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out);
 void graph_destroy(lbp_graph *g);
 
 // Read-out (beliefs and/or MAP) on `st`; host outputs are copied with

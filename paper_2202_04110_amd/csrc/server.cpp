@@ -182,7 +182,7 @@ public:
 
     int admit(Request &r) override {
         char *mem = base_ + r.off;
-        int rc = graph_create(&ctx_, r.L, mem, copy_, &r.g);
+        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g);
         if (rc != LBP_OK) return rc;
         r.g->last_T = r.T;
         if (r.backward) {
@@ -429,7 +429,7 @@ struct lbp_server {
                 rc = compile_desc(&r->desc->d, &r->L, &err);  // validates first
                 if (rc == LBP_OK) rc = check_layout(r->L, &err);
                 if (rc == LBP_OK) {
-                    r->graph_bytes = graph_device_bytes(r->L);
+                    r->graph_bytes = graph_device_bytes(r->L, false);
                     r->bytes = Arena::round(r->graph_bytes);
                     if (r->backward) {
                         r->adj_bytes = adjoint_bytes(r->L.M, r->L.VB, r->L.P, r->iters, r->k);

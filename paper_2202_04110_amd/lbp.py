@@ -104,6 +104,8 @@ _sig("lbp_graph_num_launches", C.c_int, [_P, C.POINTER(C.c_int32)])
 _sig("lbp_graph_get_launch", C.c_int, [_P, C.c_int32, _P])
 _sig("lbp_graph_set_launch", C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32])
 _sig("lbp_autotune", C.c_int, [_P, C.c_float, C.c_float, C.c_int32, _P])
+_sig("lbp_graph_use_fused", C.c_int, [_P, C.c_int])
+_sig("lbp_graph_fused_state", C.c_int, [_P, _P])
 _sig("lbp_time_phase", C.c_int, [_P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.POINTER(C.c_float)])
 
 EXPORTS = [n for n in dir(_lib) if n.startswith("lbp_")]
@@ -230,6 +232,9 @@ class Graph:
         check(_lib.lbp_graph_sizes(h, _ptr(s)))
         (self.V, self.VS, self.F, self.E, self.ES, self.Tn, self.device_bytes,
          self.padded_edge_states) = (int(x) for x in s)
+        st = np.zeros(2, np.int32)
+        check(_lib.lbp_graph_fused_state(h, _ptr(st)))
+        self.fused = bool(st[0])
 
     def free(self):
         if getattr(self, "h", None):
@@ -305,6 +310,15 @@ class Graph:
             check(_lib.lbp_graph_get_launch(self.h, i, _ptr(v)))
             out.append(dict(zip(("phase", "kind", "a", "b", "wpb", "swizzle", "items"), (int(x) for x in v))))
         return out
+
+    def use_fused(self, enable: bool):
+        check(_lib.lbp_graph_use_fused(self.h, int(bool(enable))))
+
+    @property
+    def fused_in_use(self) -> bool:
+        st = np.zeros(2, np.int32)
+        check(_lib.lbp_graph_fused_state(self.h, _ptr(st)))
+        return bool(st[1])
 
     def set_launch(self, i: int, wpb: int, swizzle: int):
         check(_lib.lbp_graph_set_launch(self.h, int(i), int(wpb), int(swizzle)))

@@ -41,14 +41,23 @@ def apply_or_tune(graph, damping: float, temperature: float, reps: int = 20, pat
     cache = _load(path)
     lns = graph.launches()
     keys = [_key(device, damping, temperature, ln) for ln in lns]
-    if all(k in cache for k in keys):
+    fkey = None
+    if graph.fused:
+        es = max(1, graph.ES)
+        fkey = "%s|%s|fused|es2^%d" % (device, "maxprod" if temperature == 0 else "lse", int(math.log2(es)))
+    if all(k in cache for k in keys) and (fkey is None or fkey in cache):
         for i, k in enumerate(keys):
             graph.set_launch(i, cache[k]["wpb"], cache[k]["swizzle"])
-        return {"source": "cache", "shapes": [cache[k] for k in keys]}
+        if fkey is not None:
+            graph.use_fused(cache[fkey]["use"])
+        return {"source": "cache", "shapes": [cache[k] for k in keys],
+                "fused": graph.fused_in_use}
     ms = graph.autotune(damping, temperature, reps)
     lns = graph.launches()
     for k, ln, t in zip(keys, lns, ms):
         cache[k] = {"wpb": ln["wpb"], "swizzle": ln["swizzle"], "ms": float(t)}
+    if fkey is not None:
+        cache[fkey] = {"use": graph.fused_in_use}
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         tmp = path + ".tmp%d" % os.getpid()
@@ -57,4 +66,4 @@ def apply_or_tune(graph, damping: float, temperature: float, reps: int = 20, pat
         os.replace(tmp, path)
     except OSError:
         pass
-    return {"source": "tuned", "shapes": [cache[k] for k in keys]}
+    return {"source": "tuned", "shapes": [cache[k] for k in keys], "fused": graph.fused_in_use}

@@ -452,3 +452,26 @@ def test_launch_shapes_do_not_change_bits(lbp, ctx, tmp_path):
     r2 = tune.apply_or_tune(g2, 0.5, 1.0, reps=3, path=path)
     assert r1["source"] == "tuned" and r2["source"] == "cache"
     assert [(l["wpb"], l["swizzle"]) for l in g.launches()] == [(l["wpb"], l["swizzle"]) for l in g2.launches()]
+
+
+def test_fused_iterations_match_two_phase(lbp, ctx):
+    """Grids run fused iterations (beliefs recomputed inside the factor
+    launch, double-buffered messages); odd counts end with one two-phase
+    iteration.  Bitwise equal to two-phase iterations (a batch of one graph
+    runs the two-phase path)."""
+    for spec, T in ((W.potts_grid(41, 5, 101), 1.0), (W.ising_grid(33, 102), 0.0), (W.potts_grid(20, 8, 103), 0.5)):
+        g = lbp.Graph(ctx, spec)
+        assert g.fused and not g.fused_in_use
+        g.use_fused(True)
+        ref = lbp.Graph(ctx, spec)
+        b = lbp.Batch(ctx, [ref])
+        for iters in (1, 2, 7, 10):
+            g.run_bp(iters, 0.5, T)
+            b.run_bp(iters, 0.5, T)
+            np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
+        np.testing.assert_array_equal(g.get_beliefs(), ref.get_beliefs())
+        b.free()
+    mg = lbp.Graph(ctx, mixed_graph(104))
+    assert not mg.fused
+    with pytest.raises(lbp.LBPError):
+        mg.use_fused(True)
