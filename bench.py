@@ -69,17 +69,22 @@ def byte_model(spec, iters):
             "floor_bytes": 8 * ES + 4 * Tn + 4 * VS}
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources; else None."""
+def measured_traffic(workload, kernel, shape):
+    """Bytes per launch that L2 exchanged with the memory side for `kernel`
+    ("fused", "factor" or "variable"), from the committed rocprofv3 counter
+    summary, scaled by the copy calibration; None unless the summary was taken
+    on the current kernel sources with the same launch shape."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_src_sha") != kernel_source_sha():
+    k = t.get("kernels", {}).get(kernel)
+    if t.get("kernel_src_sha") != kernel_source_sha() or not k:
         return None
-    return t.get("bytes_per_launch")
+    if [k.get("wpb"), k.get("swizzle")] != list(shape):
+        return None
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(spec, iters_full, damping, temperature, budget_s=12.0):
@@ -135,6 +140,47 @@ def serving_leg(lbp, W, ctx, n, budget_mb, seed=5):
     return out
 
 
+def gradient_leg(lbp, W, ctx, reps=10, side=64, states=6, iters=50, every=10):
+    """Cost of a gradient: a Potts side x side grid with `states` states
+    (sum-product T=1, damping 0.5, `iters` iterations) solved forward only,
+    then recorded with checkpoints every `every` iterations and swept back
+    for dL/dphi and dL/dtheta of a fixed linear loss on the beliefs."""
+    import torch
+
+    spec = W.potts_grid(side, states, seed=7)
+    g = lbp.Graph(ctx, spec)
+    gq = torch.from_numpy(np.random.default_rng(7).standard_normal(g.VS).astype(np.float32)).cuda()
+    gphi = torch.empty(len(spec.log_potentials), device="cuda", dtype=torch.float32)
+    gth = torch.empty(g.VS, device="cuda", dtype=torch.float32)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    def fwd():
+        g.reset_messages()
+        g.run_bp(iters, 0.5, 1.0)
+
+    def rec():
+        g.reset_messages()
+        g.run_bp_record(iters, 0.5, 1.0, every)
+
+    def both():
+        rec()
+        g.backward(gq, gphi, gth)
+
+    t_f, t_r, t_b = timed(fwd), timed(rec), timed(both)
+    g.free()
+    return {"graph": "Potts %dx%d, %d states, %d iterations, checkpoints every %d" % (side, side, states, iters, every),
+            "edge_states": spec.num_edge_states, "forward_ms": t_f, "record_ms": t_r,
+            "record_plus_backward_ms": t_b, "backward_over_forward": (t_b - t_r) / t_f}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +193,8 @@ def main():
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="also run the served stream with N requests (0: skip)")
     ap.add_argument("--serving-budget-mb", type=int, default=2048)
+    ap.add_argument("--gradient", action="store_true",
+                    help="also time a recorded solve plus its reverse sweep against the forward solve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 5 times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -170,7 +218,7 @@ def main():
                           "launches": 5}))
         return
 
-    from paper_2202_04110_amd import lbp
+    from paper_2202_04110_amd import lbp, tune
     from paper_2202_04110_amd import workloads as W
 
     build, iters, d, T, desc = WORKLOADS[args.workload]
@@ -180,7 +228,6 @@ def main():
     g = lbp.Graph(ctx, spec)
     tuned = None
     if not args.no_tune:
-        from paper_2202_04110_amd import tune
         tuned = tune.apply_or_tune(g, d, T)
     q = torch.empty(g.VS, device="cuda", dtype=torch.float32)
     mp = torch.empty(g.V, device="cuda", dtype=torch.int32)
@@ -210,15 +257,18 @@ def main():
     t_fac = g.time_phase(1, reps, d, T)
     t_it = g.time_phase(2, reps, d, T)
     t_fused = g.time_phase(3, reps, d, T) if g.fused else None
+    fl = [l for l in g.launches() if l["phase"] == 1]
     if g.fused and g.fused_in_use:
         # the fused iteration is the dominant (and only) kernel of a solve;
         # it moves the floor bytes: phi, messages in and out, evidence
         kernel, kbytes, kms = "fused iteration (dense pairwise factors, beliefs recomputed)", \
             bm["floor_bytes"], t_fused
+        tkey, shape = "fused", (fl[0]["fused_wpb"], fl[0]["fused_swizzle"])
     else:
-        kernel, kbytes, kms = "factor phase (dense pairwise enumeration factors)", bm["factor_bytes"], t_fac
+        kernel, kbytes, kms = "factor phase (every factor launch of one iteration)", bm["factor_bytes"], t_fac
+        tkey, shape = "factor", (fl[0]["wpb"], fl[0]["swizzle"]) if len(fl) == 1 else (None, None)
     achieved = kbytes / (kms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(args.workload, tkey, shape)
     out = {
         "metric": "edge-state message updates/sec",
         "value": value,
@@ -242,13 +292,16 @@ def main():
         "iteration_gbps": bm["iter_bytes"] / (t_it * 1e-3) / 1e9,
         "solve_gbps": bm["iter_bytes"] * iters / (ms_step * 1e-3) / 1e9,
         "kernel_src_sha": kernel_source_sha(),
-        "launch_shapes": [{k: l[k] for k in ("phase", "kind", "a", "b", "wpb", "swizzle")} for l in g.launches()],
+        "launch_shapes": [{k: l[k] for k in ("phase", "kind", "a", "b", "wpb", "swizzle", "fused_wpb",
+                                              "fused_swizzle")} for l in g.launches()],
         "tune_source": tuned["source"] if tuned else "default",
         "fused_iterations": g.fused_in_use,
-        "device": torch.cuda.get_device_name(0),
+        "device": tune.device_key(0),
     }
     if args.serving:
         out["serving"] = serving_leg(lbp, W, ctx, args.serving, args.serving_budget_mb)
+    if args.gradient:
+        out["gradient"] = gradient_leg(lbp, W, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, iters, d, T)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

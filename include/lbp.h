@@ -317,11 +317,15 @@ void lbp_server_destroy(lbp_server *s);
  * events (reps launches each, messages saved and restored) and keeps the
  * fastest; best_ms_out (may be NULL) receives the chosen launch time per
  * group.  lbp_graph_get_launch returns {phase (0 variable, 1 factor), kind,
- * a, b, waves per block, swizzle, work items} for group i.
+ * a, b, waves per block, swizzle, work items, fused waves per block, fused
+ * swizzle} for group i.
  */
 int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out);
-int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[7]);
+int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[9]);
 int lbp_graph_set_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle);
+/* Shape of the fused variant of factor launch i (see lbp_graph_use_fused);
+ * lbp_graph_get_launch returns it in out[7], out[8]. */
+int lbp_graph_set_fused_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle);
 int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, float *best_ms_out);
 /* Fused iterations: for a graph whose variables all have at most 16 edges and
  * 16 states and whose factors are all dense pairwise with equal slot sizes,

@@ -377,7 +377,7 @@ int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out) {
     return LBP_OK;
 }
 
-int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[7]) {
+int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[9]) {
     if (!g || !out) return fail(LBP_E_INVALID, "graph or out is NULL");
     const int32_t nv = (int32_t)g->vl.size(), nf = (int32_t)g->fl.size();
     if (i < 0 || i >= nv + nf) return fail(LBP_E_INVALID, "launch index out of range");
@@ -389,6 +389,21 @@ int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[7]) {
     out[4] = L.shape.wpb;
     out[5] = L.shape.swizzle;
     out[6] = L.n + L.n_mid + L.n_high;
+    out[7] = L.fshape.wpb;
+    out[8] = L.fshape.swizzle;
+    return LBP_OK;
+}
+
+int lbp_graph_set_fused_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    const int32_t nv = (int32_t)g->vl.size(), nf = (int32_t)g->fl.size();
+    if (i < nv || i >= nv + nf || !g->fused) return fail(LBP_E_INVALID, "not a launch with a fused variant");
+    if ((swizzle != 0 && swizzle != 1) || (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4))
+        return fail(LBP_E_INVALID, "waves_per_block must be 1, 2 or 4 and swizzle 0 or 1");
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    destroy_loops(g->loops);
+    g->fl[i - nv].fshape = LaunchShape{waves_per_block, swizzle};
     return LBP_OK;
 }
 
@@ -443,22 +458,41 @@ int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, f
     int rc = e == hipSuccess ? tune_launches(g->dgraph, g->vl, g->fl, damping, temperature, reps, st, best_ms_out)
                              : hip_error(e, "autotune backup");
     if (rc == LBP_OK && g->fused) {
-        // fused or two-phase iterations, whichever is faster on this graph
+        // the fused variant's own shapes, then fused or two-phase iterations,
+        // whichever is faster on this graph
         const TParams P = make_params(damping, temperature);
         const bool maxp = temperature == 0.0f;
-        float t2 = 0.0f, tf = 0.0f;
         hipEvent_t a = nullptr, b = nullptr;
         e = hipEventCreate(&a);
         if (e == hipSuccess) e = hipEventCreate(&b);
-        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-            const DevGraph *fz = pass ? g->fused : nullptr;
-            e = launch_loop(g->dgraph, fz, g->vl, g->fl, 2, P, maxp, st);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(a, st);
-            if (e == hipSuccess) e = launch_loop(g->dgraph, fz, g->vl, g->fl, 2 * reps, P, maxp, st);
-            if (e == hipSuccess) e = hipEventRecord(b, st);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            if (e == hipSuccess) e = hipEventElapsedTime(pass ? &tf : &t2, a, b);
+        auto time_loop = [&](const DevGraph *fz, float *ms) {
+            hipError_t x = launch_loop(g->dgraph, fz, g->vl, g->fl, 2, P, maxp, st);  // warm-up
+            if (x == hipSuccess) x = hipEventRecord(a, st);
+            if (x == hipSuccess) x = launch_loop(g->dgraph, fz, g->vl, g->fl, 2 * reps, P, maxp, st);
+            if (x == hipSuccess) x = hipEventRecord(b, st);
+            if (x == hipSuccess) x = hipEventSynchronize(b);
+            if (x == hipSuccess) x = hipEventElapsedTime(ms, a, b);
+            return x;
+        };
+        for (Launch &L : g->fl) {
+            LaunchShape best = L.fshape;
+            float best_t = 1e30f;
+            for (int w : {1, 2, 4})
+                for (int z : {0, 1}) {
+                    if (e != hipSuccess) break;
+                    L.fshape = LaunchShape{w, z};
+                    float ms = 0.0f;
+                    e = time_loop(g->fused, &ms);
+                    if (e == hipSuccess && ms < best_t) {
+                        best_t = ms;
+                        best = L.fshape;
+                    }
+                }
+            L.fshape = best;
         }
+        float t2 = 0.0f, tf = 0.0f;
+        if (e == hipSuccess) e = time_loop(nullptr, &t2);
+        if (e == hipSuccess) e = time_loop(g->fused, &tf);
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
         if (e != hipSuccess) rc = hip_error(e, "autotune fused");

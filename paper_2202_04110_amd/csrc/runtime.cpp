@@ -144,7 +144,7 @@ hipError_t launch_loop(const DevGraph *gs, const DevGraph *fused, const std::vec
         for (; it + 1 < iters && e == hipSuccess; it += 2)
             for (int h = 0; h < 2 && e == hipSuccess; ++h)
                 for (const Launch &L : fl) {
-                    e = launch_pair(fused + h, L.items, L.n, L.a, L.b, maxp, P, L.shape, st, true);
+                    e = launch_pair(fused + h, L.items, L.n, L.a, L.b, maxp, P, L.fshape, st, true);
                     if (e != hipSuccess) break;
                 }
     for (; it < iters && e == hipSuccess; ++it) e = launch_iteration(gs, vl, fl, P, maxp, st);

@@ -37,6 +37,7 @@ struct Launch {
     WorkItem *items;  // device
     int32_t n_mid = 0, n_high = 0;  // variable phase: wavefront- and block-per-variable items after the tiles
     LaunchShape shape;              // chosen by lbp_autotune (variable phase: swizzle only)
+    LaunchShape fshape;             // shape of the fused variant of a pairwise launch
 };
 
 // Host-side launch lists of one graph or of a set of graphs (graph index gi

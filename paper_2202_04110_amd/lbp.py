@@ -103,6 +103,7 @@ _sig("lbp_server_destroy", None, [_P])
 _sig("lbp_graph_num_launches", C.c_int, [_P, C.POINTER(C.c_int32)])
 _sig("lbp_graph_get_launch", C.c_int, [_P, C.c_int32, _P])
 _sig("lbp_graph_set_launch", C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32])
+_sig("lbp_graph_set_fused_launch", C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32])
 _sig("lbp_autotune", C.c_int, [_P, C.c_float, C.c_float, C.c_int32, _P])
 _sig("lbp_graph_use_fused", C.c_int, [_P, C.c_int])
 _sig("lbp_graph_fused_state", C.c_int, [_P, _P])
@@ -306,10 +307,14 @@ class Graph:
         check(_lib.lbp_graph_num_launches(self.h, C.byref(n)))
         out = []
         for i in range(n.value):
-            v = np.zeros(7, np.int32)
+            v = np.zeros(9, np.int32)
             check(_lib.lbp_graph_get_launch(self.h, i, _ptr(v)))
-            out.append(dict(zip(("phase", "kind", "a", "b", "wpb", "swizzle", "items"), (int(x) for x in v))))
+            out.append(dict(zip(("phase", "kind", "a", "b", "wpb", "swizzle", "items", "fused_wpb",
+                                 "fused_swizzle"), (int(x) for x in v))))
         return out
+
+    def set_fused_launch(self, i: int, wpb: int, swizzle: int):
+        check(_lib.lbp_graph_set_fused_launch(self.h, int(i), int(wpb), int(swizzle)))
 
     def use_fused(self, enable: bool):
         check(_lib.lbp_graph_use_fused(self.h, int(bool(enable))))

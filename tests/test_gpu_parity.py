@@ -447,9 +447,9 @@ def test_launch_shapes_do_not_change_bits(lbp, ctx, tmp_path):
     from paper_2202_04110_amd import tune
     path = str(tmp_path / "tune.json")
     g = lbp.Graph(ctx, specs[0])
-    r1 = tune.apply_or_tune(g, 0.5, 1.0, reps=3, path=path)
+    r1 = tune.apply_or_tune(g, 0.5, 1.0, reps=3, path=path, packaged=False)
     g2 = lbp.Graph(ctx, specs[0])
-    r2 = tune.apply_or_tune(g2, 0.5, 1.0, reps=3, path=path)
+    r2 = tune.apply_or_tune(g2, 0.5, 1.0, reps=3, path=path, packaged=False)
     assert r1["source"] == "tuned" and r2["source"] == "cache"
     assert [(l["wpb"], l["swizzle"]) for l in g.launches()] == [(l["wpb"], l["swizzle"]) for l in g2.launches()]
 
@@ -470,6 +470,17 @@ def test_fused_iterations_match_two_phase(lbp, ctx):
             b.run_bp(iters, 0.5, T)
             np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
         np.testing.assert_array_equal(g.get_beliefs(), ref.get_beliefs())
+        # every fused launch shape gives the same bits
+        m_ref = ref.get_messages()
+        last = len(g.launches()) - 1
+        for w in (1, 2, 4):
+            for z in (0, 1):
+                g.set_fused_launch(last, w, z)
+                g.reset_messages()
+                ref.reset_messages()
+                g.run_bp(4, 0.5, T)
+                b.run_bp(4, 0.5, T)
+                np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
         b.free()
     mg = lbp.Graph(ctx, mixed_graph(104))
     assert not mg.fused
