@@ -110,33 +110,37 @@ def cpu_baseline(spec, iters_full, damping, temperature, budget_s=12.0):
                       "%.2f s" % (iters, iters_full, dt)}
 
 
-def serving_leg(lbp, W, ctx, n, budget_mb, seed=5):
+def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
     """Served stream: n Potts requests (side log-uniform 16..256, 2..8
     states, sum-product T=1, damping 0.5, 50 iterations; 10% carry a backward
-    pass with checkpoints every 10).  Capacity R is measured with every
-    request arriving at once; then Poisson arrivals at 0.5R and 0.8R give
-    p50/p99 latency (completion minus scheduled arrival)."""
+    pass with checkpoints every 10), per HBM budget.  Capacity R is measured
+    with every request arriving at once; then Poisson arrivals at 0.5R, 0.8R
+    and 1.0R give p50/p99 latency (completion minus scheduled arrival)."""
     from paper_2202_04110_amd.serving import run_stream
 
     reqs = W.served_requests(n, seed=seed, backward_count=max(1, n // 10))
     specs = [W.request_graph(r) for r in reqs]
     gqs = [W.request_loss_coeffs(r) if r["backward"] else None for r in reqs]
-    out = {"requests": n, "iters": 50, "budget_mb": budget_mb,
-           "edge_states_mean": float(np.mean([s.num_edge_states for s in specs]))}
-    runs = {}
-    for label, frac in (("burst", None), ("0.5R", 0.5), ("0.8R", 0.8)):
-        srv = lbp.Server(ctx, budget_bytes=budget_mb << 20, max_slots=64, steps_per_round=5)
-        if frac is None:
-            arr = np.zeros(n)
-        else:
-            arr = W.poisson_arrivals(n, qps=frac * runs["burst"]["requests_per_s"], seed=seed)
-        _, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10)
-        srv.close()
-        st = summ.pop("stats")
-        summ["max_resident"] = st["max_resident"]
-        summ["rounds"] = st["rounds"]
-        runs[label] = summ
-    out["runs"] = runs
+    out = {"requests": n, "iters": 50, "backward_requests": sum(g is not None for g in gqs),
+           "edge_states_mean": float(np.mean([s.num_edge_states for s in specs])), "budgets": {}}
+    for budget_mb in budgets_mb:
+        runs = {}
+        for label, frac in (("burst", None), ("0.5R", 0.5), ("0.8R", 0.8), ("1.0R", 1.0)):
+            srv = lbp.Server(ctx, budget_bytes=budget_mb << 20, max_slots=64, steps_per_round=5)
+            if frac is None:
+                arr = np.zeros(n)
+            else:
+                arr = W.poisson_arrivals(n, qps=frac * runs["burst"]["requests_per_s"], seed=seed)
+            _, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10)
+            srv.close()
+            st = summ.pop("stats")
+            for k in ("max_resident", "rounds", "busy_us", "round_us", "prep_us", "prep_threads"):
+                summ[k] = st[k]
+            runs[label] = summ
+            print("serving budget %d MB %s: %.0f req/s p50 %.2f ms p99 %.2f ms" % (
+                budget_mb, label, summ["requests_per_s"] or 0, 1e3 * (summ["p50_s"] or 0),
+                1e3 * (summ["p99_s"] or 0)), file=sys.stderr, flush=True)
+        out["budgets"]["%d MB" % budget_mb] = runs
     return out
 
 
@@ -192,7 +196,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--serving", type=int, default=0, metavar="N",
                     help="also run the served stream with N requests (0: skip)")
-    ap.add_argument("--serving-budget-mb", type=int, default=2048)
+    ap.add_argument("--serving-budget-mb", default="512,2048",
+                    help="comma-separated HBM budgets of the served stream, in MiB")
     ap.add_argument("--gradient", action="store_true",
                     help="also time a recorded solve plus its reverse sweep against the forward solve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -299,7 +304,8 @@ def main():
         "device": tune.device_key(0),
     }
     if args.serving:
-        out["serving"] = serving_leg(lbp, W, ctx, args.serving, args.serving_budget_mb)
+        out["serving"] = serving_leg(lbp, W, ctx, args.serving,
+                                     [int(x) for x in str(args.serving_budget_mb).split(",") if x])
     if args.gradient:
         out["gradient"] = gradient_leg(lbp, W, ctx)
     if not args.no_cpu_baseline:

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <cmath>
 #include <map>
 #include <string>
@@ -21,6 +22,25 @@ namespace {
 int bad(std::string *err, const std::string &msg, int code = LBP_E_INVALID) {
     *err = msg;
     return code;
+}
+
+// Index of the first infinite or NaN element, or -1: an exponent-bits test
+// over blocks (branch-free, so it vectorises), then a scan of a hit block.
+int64_t first_nonfinite(const float *x, int64_t n) {
+    constexpr int64_t B = 4096;
+    for (int64_t b = 0; b < n; b += B) {
+        const int64_t e = std::min(n, b + B);
+        uint32_t hit = 0;
+        for (int64_t i = b; i < e; ++i) {
+            uint32_t u;
+            std::memcpy(&u, x + i, sizeof u);
+            hit |= (uint32_t)((u & 0x7f800000u) == 0x7f800000u);
+        }
+        if (hit)
+            for (int64_t i = b; i < e; ++i)
+                if (!std::isfinite(x[i])) return i;
+    }
+    return -1;
 }
 
 std::string at(const char *what, int64_t i) { return std::string(what) + "[" + std::to_string(i) + "]"; }
@@ -58,9 +78,10 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
             return bad(err, at("var_num_states", v) + " = " + std::to_string(n) + " outside [2, 64]");
         VS += n;
     }
-    if (d->evidence)
-        for (int64_t i = 0; i < VS; ++i)
-            if (!std::isfinite(d->evidence[i])) return bad(err, at("evidence", i) + " is not finite");
+    if (d->evidence) {
+        const int64_t i = first_nonfinite(d->evidence, VS);
+        if (i >= 0) return bad(err, at("evidence", i) + " is not finite");
+    }
 
     if (!monotone_from_zero(d->factor_edge_off, F))
         return bad(err, "factor_edge_off must start at 0 and be non-decreasing");
@@ -75,9 +96,10 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
         return bad(err, "logpot_off must start at 0 and be non-decreasing");
     const int64_t Tn = d->logpot_off[F];
     if (Tn > 0 && !d->log_potentials) return bad(err, "log_potentials is NULL");
-    for (int64_t i = 0; i < Tn; ++i)
-        if (!std::isfinite(d->log_potentials[i]))
-            return bad(err, at("log_potentials", i) + " is not finite");
+    {
+        const int64_t i = first_nonfinite(d->log_potentials, Tn);
+        if (i >= 0) return bad(err, at("log_potentials", i) + " is not finite");
+    }
 
     if (NT > 0) {
         if (!monotone_from_zero(d->cfg_table_off, NT))
@@ -215,7 +237,9 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
     const int32_t b_zero = (int32_t)VB;
     VB += (int64_t)kLanes * kMaxStates;
     L->VB = VB;
+    std::vector<int32_t> tile_fac;  // factor of each (tile, lane) with a potential panel, -1 otherwise
     auto add_vb_rows = [&](int32_t rows) {
+        tile_fac.resize((L->ftile.size() + 1) * kLanes, -1);
         const size_t base = L->fvb.size();
         L->fvb.resize(base + (size_t)rows * kLanes);
         L->fvar.resize(base + (size_t)rows * kLanes, -1);
@@ -349,6 +373,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                     L->fvar[ft.vb_off + l] = d->edge_var[e0];
                     L->fvar[ft.vb_off + kLanes + l] = d->edge_var[e0 + 1];
                     L->fac_phi[f] = (int32_t)(P + l);
+                    tile_fac[L->ftile.size() * kLanes + l] = (int32_t)f;
                 }
                 M += (int64_t)kLanes * (na + nb);
                 P += (int64_t)kLanes * na * nb;
@@ -458,6 +483,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
                         L->fvar[ft.vb_off + j * kLanes + l] = d->edge_var[e0 + j];
                     }
                     L->fac_phi[f] = (int32_t)(P + l);
+                    tile_fac[L->ftile.size() * kLanes + l] = (int32_t)f;
                 }
                 M += (int64_t)kLanes * rows;
                 P += (int64_t)kLanes * gc.ncfg;
@@ -544,16 +570,29 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
         if (fg.kind != TK_PAIR || fg.a != fg.b) L->fusable = false;
 
     // -------------------------------------------------------------- values
-    L->theta_panel.assign(L->VB, 0.0f);
-    if (d->evidence)
-        for (int64_t v = 0; v < V; ++v)
-            for (int32_t s = 0; s < L->vn[v]; ++s)
-                L->theta_panel[vaddr[v] + (int64_t)s * kLanes] = d->evidence[L->vs_off[v] + s];
-    L->phi_panel.assign(L->P, 0.0f);
-    for (int64_t f = 0; f < F; ++f) {
-        if (L->fac_phi[f] < 0) continue;
-        for (int64_t c = 0; c < L->lp_off[f + 1] - L->lp_off[f]; ++c)
-            L->phi_panel[L->fac_phi[f] + c * kLanes] = d->log_potentials[L->lp_off[f] + c];
+    // Panels are written front to back, every element once (padding zero).
+    L->theta_panel.resize(L->VB);
+    for (int64_t t = 0; t < nvt; ++t) {
+        const VTile &vt = L->vtile[t];
+        float *row = L->theta_panel.data() + vt.b_off;
+        for (int32_t s = 0; s < vt.n; ++s, row += kLanes)
+            for (int32_t l = 0; l < kLanes; ++l) {
+                const int64_t v = t * kLanes + l;
+                row[l] = (d->evidence && v < V && s < L->vn[v]) ? d->evidence[L->vs_off[v] + s] : 0.0f;
+            }
+    }
+    std::fill(L->theta_panel.begin() + b_zero, L->theta_panel.end(), 0.0f);
+    L->phi_panel.resize(L->P);
+    if (P == 0) std::fill(L->phi_panel.begin(), L->phi_panel.end(), 0.0f);
+    for (size_t t = 0; t < L->ftile.size(); ++t) {
+        const FTile &ft = L->ftile[t];
+        if (ft.kind != TK_PAIR && ft.kind != TK_GEN) continue;
+        const int32_t ncfg = ft.kind == TK_PAIR ? ft.a * ft.b : L->gcls[ft.a].ncfg;
+        const int32_t *lf = tile_fac.data() + t * kLanes;
+        float *row = L->phi_panel.data() + ft.phi_off;
+        for (int32_t c = 0; c < ncfg; ++c, row += kLanes)
+            for (int32_t l = 0; l < kLanes; ++l)
+                row[l] = lf[l] >= 0 ? d->log_potentials[L->lp_off[lf[l]] + c] : 0.0f;
     }
     return LBP_OK;
 }

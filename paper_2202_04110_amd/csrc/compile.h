@@ -2,7 +2,9 @@
 // 64-lane panel layout described in lbp_internal.h.
 #pragma once
 
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/lbp.h"
@@ -25,6 +27,28 @@ struct VGroup {
     std::vector<int32_t> tiles;
 };
 
+// A std::allocator that default-initialises: resize() of a float vector then
+// leaves the elements unwritten (panels are filled completely afterwards).
+template <class T>
+struct DefaultInitAllocator : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = DefaultInitAllocator<U>;
+    };
+    DefaultInitAllocator() = default;
+    template <class U>
+    DefaultInitAllocator(const DefaultInitAllocator<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+using PanelBuf = std::vector<float, DefaultInitAllocator<float>>;
+
 struct HostLayout {
     int64_t V = 0, VS = 0, F = 0, E = 0, ES = 0, Tn = 0;
     int64_t M = 0, VB = 0, P = 0;  // floats in the message, belief and potential arrays
@@ -44,7 +68,7 @@ struct HostLayout {
     std::vector<int64_t> es_off, vs_off;
     std::vector<int32_t> vn, fac_phi;
     std::vector<int64_t> lp_off;
-    std::vector<float> theta_panel, phi_panel;
+    PanelBuf theta_panel, phi_panel;  // every element written by compile_desc
     std::vector<FGroup> fgroups;
     std::vector<VGroup> vgroups;
 };

@@ -396,7 +396,9 @@ struct lbp_server {
     int64_t n_submitted = 0, n_finished = 0, n_completed = 0, n_rejected = 0, n_failed = 0, n_cancelled = 0;
     int64_t n_rounds = 0, max_resident = 0;
     int64_t now_resident = 0, now_pending = 0, arena_used = 0, arena_peak = 0;
-    double busy_s = 0.0;
+    double busy_s = 0.0;   // worker: rounds, admissions, read-outs
+    double prep_s = 0.0;   // prep threads: compile and check, summed
+    double round_s = 0.0;  // worker: launching rounds and waiting for them
 
     double clock() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
@@ -424,6 +426,7 @@ struct lbp_server {
                 to_prep.pop_front();
             }
             int rc = LBP_OK;
+            const double tp = clock();
             try {
                 std::string err;
                 rc = compile_desc(&r->desc->d, &r->L, &err);  // validates first
@@ -442,7 +445,9 @@ struct lbp_server {
                 rc = LBP_E_OOM;
             }
             r->desc.reset();
+            const double dt = clock() - tp;
             std::lock_guard<std::mutex> lk(mu);
+            prep_s += dt;
             r->prep = rc == LBP_OK ? 1 : 2;
             r->prep_status = rc;
             cv.notify_one();
@@ -562,6 +567,10 @@ struct lbp_server {
                 int rc = exec->round(active, s);
                 if (rc == LBP_OK) admit();  // uploads on the copy stream overlap the round
                 if (rc == LBP_OK) rc = exec->wait();
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    round_s += clock() - tr;
+                }
                 if (rc != LBP_OK) {
                     for (Request *r : active) {
                         drop_resident(r);
@@ -760,7 +769,7 @@ int lbp_server_drain(lbp_server *s, double timeout_s) {
     return ok ? LBP_OK : set_error(LBP_E_STATE, "drain timed out");
 }
 
-int lbp_server_stats(lbp_server *s, int64_t out[12]) {
+int lbp_server_stats(lbp_server *s, int64_t out[15]) {
     if (!s || !out) return set_error(LBP_E_INVALID, "server or out is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     out[0] = s->n_submitted;
@@ -775,6 +784,9 @@ int lbp_server_stats(lbp_server *s, int64_t out[12]) {
     out[9] = s->max_resident;
     out[10] = s->arena_peak;
     out[11] = (int64_t)(s->busy_s * 1e6);
+    out[12] = (int64_t)(s->round_s * 1e6);
+    out[13] = (int64_t)(s->prep_s * 1e6);
+    out[14] = (int64_t)s->preps.size();
     return LBP_OK;
 }
 

@@ -34,6 +34,11 @@ class LBPError(RuntimeError):
 if not os.path.exists(LIB_PATH):
     raise ImportError("liblbp.so is not built (%s); run python -m paper_2202_04110_amd.build" % LIB_PATH)
 
+# torch first: liblbp.so then binds to the HIP runtime torch already loaded
+# (same soname), so streams and device pointers are shared with torch and
+# one runtime serves the process whatever the import order.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 
@@ -368,7 +373,8 @@ class Batch:
 
 
 SERVER_STATS = ("accepted", "finished", "completed", "rejected", "failed", "cancelled", "rounds",
-                "resident", "queued", "max_resident", "arena_peak_bytes", "busy_us")
+                "resident", "queued", "max_resident", "arena_peak_bytes", "busy_us", "round_us", "prep_us",
+                "prep_threads")
 
 
 class Server:
@@ -420,7 +426,7 @@ class Server:
         check(_lib.lbp_server_drain(self.h, float(timeout)))
 
     def stats(self) -> dict:
-        s = np.zeros(12, np.int64)
+        s = np.zeros(len(SERVER_STATS), np.int64)
         check(_lib.lbp_server_stats(self.h, _ptr(s)))
         return dict(zip(SERVER_STATS, (int(x) for x in s)))
 

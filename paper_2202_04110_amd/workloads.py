@@ -193,6 +193,28 @@ def potts_grid(L: int = 512, n: int = 5, seed: int = 2, diag: float = 1.0,
                            f"potts{L}x{n}", {"L": L, "n": n, "seed": seed})
 
 
+def random_pairwise(seed: int, num_vars: int, num_factors: int, n: int = 4, max_degree: int = 12,
+                    ev_sd: float = 1.0, lp_sd: float = 1.0) -> GraphSpec:
+    """Loopy pairwise graph with no spatial locality: each factor joins two
+    distinct variables drawn uniformly (redrawn while either already has
+    ``max_degree`` edges); n states everywhere, evidence N(0, ev_sd), tables
+    N(0, lp_sd)."""
+    rng = np.random.default_rng(seed)
+    deg = np.zeros(num_vars, np.int64)
+    pairs = []
+    while len(pairs) < num_factors:
+        a, b = rng.integers(0, num_vars, size=2)
+        if a == b or deg[a] >= max_degree or deg[b] >= max_degree:
+            continue
+        deg[a] += 1
+        deg[b] += 1
+        pairs.append((a, b))
+    ev = rng.normal(0.0, ev_sd, size=num_vars * n).astype(np.float32)
+    tab = rng.normal(0.0, lp_sd, size=(num_factors, n * n)).astype(np.float32)
+    return _pairwise_graph(np.full(num_vars, n, np.int32), ev, np.array(pairs, np.int64), tab,
+                           f"randpair{num_vars}x{n}", {"seed": seed})
+
+
 def rbm(nv: int = 784, nh: int = 500, seed: int = 3, w_sd: float = 0.05,
         b_sd: float = 0.1) -> GraphSpec:
     """Restricted Boltzmann machine as a factor graph: visible 0..nv-1, hidden

@@ -455,11 +455,16 @@ def test_launch_shapes_do_not_change_bits(lbp, ctx, tmp_path):
 
 
 def test_fused_iterations_match_two_phase(lbp, ctx):
-    """Grids run fused iterations (beliefs recomputed inside the factor
-    launch, double-buffered messages); odd counts end with one two-phase
-    iteration.  Bitwise equal to two-phase iterations (a batch of one graph
-    runs the two-phase path)."""
-    for spec, T in ((W.potts_grid(41, 5, 101), 1.0), (W.ising_grid(33, 102), 0.0), (W.potts_grid(20, 8, 103), 0.5)):
+    """Low-degree square pairwise graphs run fused iterations (beliefs
+    recomputed inside the factor launch, double-buffered messages); odd
+    counts end with one two-phase iteration.  Bitwise equal to two-phase
+    iterations (a batch of one graph runs the two-phase path): grids, a graph
+    with no locality, and two square classes in one graph (two fused
+    launches)."""
+    cases = ((W.potts_grid(41, 5, 101), 1.0), (W.ising_grid(33, 102), 0.0), (W.potts_grid(20, 8, 103), 0.5),
+             (W.random_pairwise(105, 3000, 9000, 3), 1.0),
+             (W.disjoint_union([W.potts_grid(30, 3, 106), W.potts_grid(25, 6, 107)]), 0.0))
+    for spec, T in cases:
         g = lbp.Graph(ctx, spec)
         assert g.fused and not g.fused_in_use
         g.use_fused(True)
@@ -470,19 +475,38 @@ def test_fused_iterations_match_two_phase(lbp, ctx):
             b.run_bp(iters, 0.5, T)
             np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
         np.testing.assert_array_equal(g.get_beliefs(), ref.get_beliefs())
+        np.testing.assert_array_equal(g.decode_map(), ref.decode_map())
         # every fused launch shape gives the same bits
-        m_ref = ref.get_messages()
-        last = len(g.launches()) - 1
-        for w in (1, 2, 4):
-            for z in (0, 1):
-                g.set_fused_launch(last, w, z)
-                g.reset_messages()
-                ref.reset_messages()
-                g.run_bp(4, 0.5, T)
-                b.run_bp(4, 0.5, T)
-                np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
+        for i, ln in enumerate(g.launches()):
+            if ln["phase"] != 1:
+                continue
+            for w in (1, 2, 4):
+                for z in (0, 1):
+                    g.set_fused_launch(i, w, z)
+                    g.reset_messages()
+                    ref.reset_messages()
+                    g.run_bp(4, 0.5, T)
+                    b.run_bp(4, 0.5, T)
+                    np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
         b.free()
     mg = lbp.Graph(ctx, mixed_graph(104))
     assert not mg.fused
     with pytest.raises(lbp.LBPError):
         mg.use_fused(True)
+
+
+def test_binding_imported_before_torch():
+    """The binding loads torch before the library, so both share one HIP
+    runtime whatever the caller imported first."""
+    import subprocess
+    import sys
+    code = ("from paper_2202_04110_amd import lbp\n"
+            "from paper_2202_04110_amd import workloads as W\n"
+            "ctx = lbp.Context(0)\n"
+            "g = lbp.Graph(ctx, W.ising_grid(8, 1))\n"
+            "g.run_bp(3, 0.5, 0.0)\n"
+            "print(int(g.decode_map().shape[0]))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "64"
