@@ -269,9 +269,13 @@ def main():
         kernel, kbytes, kms = "fused iteration (dense pairwise factors, beliefs recomputed)", \
             bm["floor_bytes"], t_fused
         tkey, shape = "fused", (fl[0]["fused_wpb"], fl[0]["fused_swizzle"])
-    else:
+    elif t_fac >= t_var:
         kernel, kbytes, kms = "factor phase (every factor launch of one iteration)", bm["factor_bytes"], t_fac
         tkey, shape = "factor", (fl[0]["wpb"], fl[0]["swizzle"]) if len(fl) == 1 else (None, None)
+    else:
+        vl = [l for l in g.launches() if l["phase"] == 0]
+        kernel, kbytes, kms = "variable phase (belief sums)", bm["variable_bytes"], t_var
+        tkey, shape = "variable", (vl[0]["wpb"], vl[0]["swizzle"]) if len(vl) == 1 else (None, None)
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, tkey, shape)
     out = {

@@ -190,14 +190,18 @@ __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int la
     }
 }
 
-// high: thread i sums edges i, i+256, ... in order (fetched 4 at a time),
-// then a fixed LDS tree combines the 256 partial sums.
+// high: thread i sums edges i, i+256, ... in order (fetched 4 at a time);
+// each wavefront combines its 64 partial sums with a butterfly (every lane
+// ends with the same bits), and the four wavefront sums are added in order.
 constexpr int kHighThreads = 256;
-__device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int tid, float (*red)[kHighThreads]) {
+constexpr int kHighWaves = kHighThreads / 64;
+__device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int tid, float (*red)[kHighWaves]) {
     constexpr int SC = 8;  // states per pass
     constexpr int KC = 4;  // edges per thread fetched together
     const HVar h = G.hvar[hv];
+    const int lane = tid & 63, wave = tid >> 6;
     for (int s0 = 0; s0 < h.n; s0 += SC) {
+        const int ns = min(SC, h.n - s0);  // uniform
         float part[SC];
 #pragma unroll
         for (int j = 0; j < SC; ++j) part[j] = 0.0f;
@@ -213,27 +217,27 @@ __device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int t
             for (int u = 0; u < KC; ++u)
 #pragma unroll
                 for (int j = 0; j < SC; ++j)
-                    x[u][j] = (a[u] >= 0 && s0 + j < h.n) ? G.m[a[u] + (s0 + j) * kLanes] : 0.0f;
+                    x[u][j] = (a[u] >= 0 && j < ns) ? G.m[a[u] + (s0 + j) * kLanes] : 0.0f;
 #pragma unroll
             for (int u = 0; u < KC; ++u)
 #pragma unroll
                 for (int j = 0; j < SC; ++j)
-                    if (a[u] >= 0 && s0 + j < h.n) part[j] += x[u][j];
+                    if (a[u] >= 0 && j < ns) part[j] += x[u][j];
         }
 #pragma unroll
-        for (int j = 0; j < SC; ++j) red[j][tid] = part[j];
-        __syncthreads();
+        for (int j = 0; j < SC; ++j)
+            if (j < ns) {
 #pragma unroll
-        for (int half = kHighThreads / 2; half > 0; half >>= 1) {
-            if (tid < half) {
-#pragma unroll
-                for (int j = 0; j < SC; ++j) red[j][tid] += red[j][tid + half];
+                for (int off = 32; off > 0; off >>= 1) part[j] += __shfl_xor(part[j], off, 64);
+                if (lane == 0) red[j][wave] = part[j];
             }
-            __syncthreads();
-        }
-        if (tid < SC && s0 + tid < h.n) {
+        __syncthreads();
+        if (tid < ns) {
+            float v = red[tid][0];
+#pragma unroll
+            for (int w = 1; w < kHighWaves; ++w) v += red[tid][w];
             const int b = h.b_addr + (s0 + tid) * kLanes;
-            G.B[b] = G.theta[b] + red[tid][0];
+            G.B[b] = G.theta[b] + v;
         }
         __syncthreads();
     }
@@ -242,22 +246,24 @@ __device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int t
 template <int NB>
 __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
                                                 int n_low, int n_mid, int n_high, int swz) {
-    __shared__ float red[8][kHighThreads];
-    const int nwave = n_low + n_mid;
-    const int wave_blocks = (nwave + 3) / 4;
-    if ((int)blockIdx.x < wave_blocks) {
-        const int b = swz ? swizzle_block(blockIdx.x, wave_blocks) : (int)blockIdx.x;
-        const int w = __builtin_amdgcn_readfirstlane(b * 4 + (int)(threadIdx.x >> 6));
-        if (w >= nwave) return;
-        const WorkItem it = items[w];
-        if (w < n_low) belief_low_tile<NB>(gs[it.g], it.t, lane_id());
-        else belief_mid_var(gs[it.g], it.t, lane_id());
+    __shared__ float red[8][kHighWaves];
+    // block-per-variable items first: they are the longest, so they start
+    // before the wavefront items fill the machine
+    if ((int)blockIdx.x < n_high) {
+        const int hb = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+        const WorkItem it = items[n_low + n_mid + hb];
+        belief_high_var(gs[it.g], it.t, threadIdx.x, red);
         return;
     }
-    const int hb = __builtin_amdgcn_readfirstlane((int)blockIdx.x - wave_blocks);
-    if (hb >= n_high) return;
-    const WorkItem it = items[nwave + hb];
-    belief_high_var(gs[it.g], it.t, threadIdx.x, red);
+    const int nwave = n_low + n_mid;
+    const int wave_blocks = (nwave + 3) / 4;
+    const int bx = (int)blockIdx.x - n_high;
+    const int b = swz ? swizzle_block(bx, wave_blocks) : bx;
+    const int w = __builtin_amdgcn_readfirstlane(b * 4 + (int)(threadIdx.x >> 6));
+    if (w >= nwave) return;
+    const WorkItem it = items[w];
+    if (w < n_low) belief_low_tile<NB>(gs[it.g], it.t, lane_id());
+    else belief_mid_var(gs[it.g], it.t, lane_id());
 }
 
 // --------------------------------------------------------------------------

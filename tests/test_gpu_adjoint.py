@@ -135,3 +135,38 @@ def test_backward_state_and_argument_errors(lbp, ctx):
     with pytest.raises(lbp.LBPError) as ei:
         lg.run_bp_record(5, 0.5, 1.0, 2)
     assert ei.value.code == lbp.LBP_E_UNSUPPORTED
+
+
+def test_gradient_matches_finite_differences(lbp, ctx):
+    """GPU dL/dphi and dL/dtheta against central differences of the FP64
+    oracle's loss L = sum(gq * q(N iterations)), perturbing single float32
+    inputs by +-2^-7 (exact in float32 at these magnitudes)."""
+    import copy
+    spec = W.random_factor_graph(33, num_vars=10, tree=False, extra_factors=6, max_arity=3,
+                                 explicit_frac=0.4, lp_sd=0.7)
+    iters, d, T = 12, 0.5, 1.0
+    og = OracleGraph(spec)
+    gq = np.random.default_rng(7).normal(0, 1, og.VS)
+    _, gphi, gth = gpu_grad(lbp, ctx, spec, iters, d, T, gq, 5)
+
+    def loss(s):
+        o = OracleGraph(s)
+        _, q, _ = o.beliefs(o.run(iters, d, T), T)
+        return float(np.dot(gq, q))
+
+    h = 2.0 ** -7
+    rng = np.random.default_rng(8)
+    scale = max(1.0, float(np.abs(gphi).max()), float(np.abs(gth).max()))
+    for field, grad, picks in (("log_potentials", gphi, rng.choice(len(spec.log_potentials), 6, replace=False)),
+                               ("evidence", gth, rng.choice(len(spec.evidence), 4, replace=False))):
+        for i in picks:
+            vals = []
+            for sgn in (1.0, -1.0):
+                s = copy.deepcopy(spec)
+                arr = getattr(s, field).astype(np.float32).copy()
+                arr[i] = np.float32(arr[i] + sgn * h)
+                setattr(s, field, arr)
+                vals.append(loss(s))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            print("%s[%d]: gpu %.6f fd %.6f" % (field, i, grad[i], fd))
+            assert abs(grad[i] - fd) <= 1e-3 * scale
