@@ -261,7 +261,8 @@ typedef struct lbp_completion {
     const float *beliefs;      /* VS normalised beliefs (host), NULL on failure */
     const int32_t *map;        /* V MAP states (host), NULL on failure */
     const float *grad_logpot;  /* Tn gradient (host) for backward requests, else NULL */
-    double t_arrival, t_admit, t_done;  /* seconds on the server clock */
+    double t_arrival, t_ready, t_admit, t_done;  /* seconds on the server clock: arrival,
+                                                  * compiled and checked, admitted, completed */
 } lbp_completion;
 
 /* Server on ctx's device with an arena of hbm_budget_bytes, at most max_slots

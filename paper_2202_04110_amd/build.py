@@ -11,8 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbp.so")
-SOURCES = ["kernels.hip", "compile.cpp", "runtime.cpp", "api.cpp", "server.cpp"]
-HEADERS = ["kernels.h", "compile.h", "lbp_internal.h", "runtime.h", "arena.h"]
+SOURCES = ["kernels.hip", "compile.cpp", "hostmem.cpp", "runtime.cpp", "api.cpp", "server.cpp"]
+HEADERS = ["kernels.h", "compile.h", "hostmem.h", "lbp_internal.h", "runtime.h", "arena.h"]
 
 # -ffp-contract=off: no implicit fused multiply-adds, so every element is
 # computed with the same roundings in every kernel that inlines the same

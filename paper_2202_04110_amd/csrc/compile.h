@@ -3,11 +3,13 @@
 #pragma once
 
 #include <memory>
+#include <new>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "../../include/lbp.h"
+#include "hostmem.h"
 #include "lbp_internal.h"
 
 namespace lbp {
@@ -27,17 +29,21 @@ struct VGroup {
     std::vector<int32_t> tiles;
 };
 
-// A std::allocator that default-initialises: resize() of a float vector then
-// leaves the elements unwritten (panels are filled completely afterwards).
+// Allocator of the host panels: storage from panel_alloc (page-locked when
+// possible) and default-initialised elements, so resize() leaves them
+// unwritten (panels are filled completely afterwards).
 template <class T>
-struct DefaultInitAllocator : std::allocator<T> {
+struct PanelAllocator {
+    using value_type = T;
+    PanelAllocator() = default;
     template <class U>
-    struct rebind {
-        using other = DefaultInitAllocator<U>;
-    };
-    DefaultInitAllocator() = default;
-    template <class U>
-    DefaultInitAllocator(const DefaultInitAllocator<U> &) noexcept {}
+    PanelAllocator(const PanelAllocator<U> &) noexcept {}
+    T *allocate(size_t n) {
+        void *p = panel_alloc(n * sizeof(T));
+        if (!p) throw std::bad_alloc();
+        return (T *)p;
+    }
+    void deallocate(T *p, size_t) noexcept { panel_free(p); }
     template <class U>
     void construct(U *p) noexcept {
         ::new ((void *)p) U;
@@ -46,8 +52,16 @@ struct DefaultInitAllocator : std::allocator<T> {
     void construct(U *p, A &&...a) {
         ::new ((void *)p) U(std::forward<A>(a)...);
     }
+    template <class U>
+    bool operator==(const PanelAllocator<U> &) const noexcept {
+        return true;
+    }
+    template <class U>
+    bool operator!=(const PanelAllocator<U> &) const noexcept {
+        return false;
+    }
 };
-using PanelBuf = std::vector<float, DefaultInitAllocator<float>>;
+using PanelBuf = std::vector<float, PanelAllocator<float>>;
 
 struct HostLayout {
     int64_t V = 0, VS = 0, F = 0, E = 0, ES = 0, Tn = 0;

@@ -89,15 +89,14 @@ size_t lists_bytes(const LaunchLists &ll) {
     return b;
 }
 
-hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::vector<Launch> *vl,
-                        std::vector<Launch> *fl) {
+// The lists' work items sit one 256-aligned run per launch: variable
+// launches, then factor launches.
+void describe_lists(const LaunchLists &ll, char *mem, std::vector<Launch> *vl, std::vector<Launch> *fl) {
     vl->clear();
     fl->clear();
     size_t off = 0;
-    hipError_t e = hipSuccess;
-    for (size_t i = 0; i < ll.vitems.size() && e == hipSuccess; ++i) {
+    for (size_t i = 0; i < ll.vitems.size(); ++i) {
         const auto &v = ll.vitems[i];
-        if (!v.empty()) e = hipMemcpyAsync(mem + off, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice, st);
         Launch L{-1, ll.vbucket[i], 0, 0, (WorkItem *)(mem + off)};
         L.n_mid = i == 0 ? ll.n_mid : 0;
         L.n_high = i == 0 ? ll.n_high : 0;
@@ -105,13 +104,34 @@ hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::v
         vl->push_back(L);
         off += align256(std::max<size_t>(1, v.size()) * sizeof(WorkItem));
     }
-    for (size_t i = 0; i < ll.fitems.size() && e == hipSuccess; ++i) {
+    for (size_t i = 0; i < ll.fitems.size(); ++i) {
         const auto &v = ll.fitems[i];
-        if (!v.empty()) e = hipMemcpyAsync(mem + off, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice, st);
         fl->push_back(Launch{ll.fshape[i].kind, ll.fshape[i].a, ll.fshape[i].b, (int32_t)v.size(),
                              (WorkItem *)(mem + off)});
         off += align256(std::max<size_t>(1, v.size()) * sizeof(WorkItem));
     }
+}
+
+void pack_lists(const LaunchLists &ll, char *host) {
+    size_t off = 0;
+    for (const auto *lists : {&ll.vitems, &ll.fitems})
+        for (const auto &v : *lists) {
+            if (!v.empty()) std::memcpy(host + off, v.data(), sizeof(WorkItem) * v.size());
+            off += align256(std::max<size_t>(1, v.size()) * sizeof(WorkItem));
+        }
+}
+
+hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::vector<Launch> *vl,
+                        std::vector<Launch> *fl) {
+    describe_lists(ll, mem, vl, fl);
+    hipError_t e = hipSuccess;
+    for (const auto *ls : {vl, fl})
+        for (size_t i = 0; i < ls->size() && e == hipSuccess; ++i) {
+            const Launch &L = (*ls)[i];
+            const auto &v = ls == vl ? ll.vitems[i] : ll.fitems[i];
+            if (!v.empty())
+                e = hipMemcpyAsync(L.items, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice, st);
+        }
     return e;
 }
 
@@ -205,12 +225,14 @@ struct Piece {
 };
 
 // The pieces of one graph's allocation in a fixed order (shared by the size
-// query and the upload).
+// query, the host image and the upload): the pieces with host data first,
+// then the pieces that start as zeros.
 struct GraphPieces {
     std::vector<Piece> p;
     size_t total = 0;
     size_t m, B, th, phi, ft, fvb, fvar, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
     size_t m2 = 0, fdg = 0;
+    size_t data_end = 0;
     bool fused;
     LaunchLists ll;
 
@@ -220,8 +242,6 @@ struct GraphPieces {
             total += align256(std::max<size_t>(bytes, 4));
             return p.size() - 1;
         };
-        m = add(nullptr, sizeof(float) * L.M);
-        B = add(nullptr, sizeof(float) * L.VB);
         th = add(L.theta_panel.data(), sizeof(float) * L.VB);
         phi = add(L.phi_panel.data(), sizeof(float) * L.P);
         ft = add(L.ftile.data(), sizeof(FTile) * L.ftile.size());
@@ -240,15 +260,18 @@ struct GraphPieces {
         vn = add(L.vn.data(), sizeof(int32_t) * L.vn.size());
         fp = add(L.fac_phi.data(), sizeof(int32_t) * L.fac_phi.size());
         lp = add(L.lp_off.data(), sizeof(int64_t) * L.lp_off.size());
-        fl = add(nullptr, sizeof(int32_t) * 4);
-        dg = add(nullptr, sizeof(DevGraph));
-        q = add(nullptr, sizeof(float) * L.VS);
-        map = add(nullptr, sizeof(int32_t) * L.V);
         GraphShape s{L.fgroups, L.vgroups, L.mids, L.highs};
         std::vector<WorkItem> mids, highs;
         add_to_lists(ll, 0, s, &mids, &highs);
         finish_lists(ll, mids, highs);
-        items = add(nullptr, lists_bytes(ll));
+        items = add(nullptr, lists_bytes(ll));  // packed by pack_lists
+        data_end = total;  // everything above is copied from the host image, everything below starts zero
+        m = add(nullptr, sizeof(float) * L.M);
+        B = add(nullptr, sizeof(float) * L.VB);
+        fl = add(nullptr, sizeof(int32_t) * 4);
+        dg = add(nullptr, sizeof(DevGraph));
+        q = add(nullptr, sizeof(float) * L.VS);
+        map = add(nullptr, sizeof(int32_t) * L.V);
         if (fused) {
             m2 = add(nullptr, sizeof(float) * L.M);
             fdg = add(nullptr, sizeof(DevGraph) * 2);
@@ -260,8 +283,19 @@ struct GraphPieces {
 
 size_t graph_device_bytes(const HostLayout &L, bool with_fused) { return GraphPieces(L, with_fused).total; }
 
-int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out) {
+size_t graph_image_bytes(const HostLayout &L) { return GraphPieces(L, false).data_end; }
+
+void graph_fill_image(const HostLayout &L, char *image) {
+    GraphPieces gp(L, false);
+    for (const Piece &p : gp.p)
+        if (p.src && p.bytes) std::memcpy(image + p.off, p.src, p.bytes);
+    pack_lists(gp.ll, image + gp.p[gp.items].off);
+}
+
+int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
+                 const char *image) {
     lbp_graph *g = nullptr;
+    char *own_image = nullptr;  // built here when the caller brings none
     try {
         GraphPieces gp(L, with_fused);
         g = new lbp_graph;
@@ -279,15 +313,16 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         }
         g->dbytes = gp.total;
         auto ptr = [&](size_t i) { return (void *)(g->dmem + gp.p[i].off); };
-        hipError_t e = hipSuccess;
-        for (const Piece &p : gp.p)
-            if (p.src && p.bytes) {
-                e = hipMemcpyAsync(g->dmem + p.off, p.src, p.bytes, hipMemcpyHostToDevice, st);
-                if (e != hipSuccess) break;
-            }
-        if (e == hipSuccess) e = hipMemsetAsync(ptr(gp.m), 0, sizeof(float) * L.M, st);
-        if (e == hipSuccess) e = hipMemsetAsync(ptr(gp.B), 0, sizeof(float) * L.VB, st);
-        if (e == hipSuccess) e = hipMemsetAsync(ptr(gp.fl), 0, sizeof(int32_t) * 4, st);
+        if (!image) {
+            own_image = (char *)panel_alloc(gp.data_end);
+            if (!own_image) throw std::bad_alloc();
+            graph_fill_image(L, own_image);
+            image = own_image;
+        }
+        // one copy of every host piece (a single DMA when the image is
+        // page-locked), one fill for messages, beliefs, flag and scratch
+        hipError_t e = hipMemcpyAsync(g->dmem, image, gp.data_end, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(g->dmem + gp.data_end, 0, gp.total - gp.data_end, st);
         DevGraph &h = g->host;
         h.m = (float *)ptr(gp.m);
         h.mo = h.m;
@@ -328,12 +363,13 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
             fv[1].m = m2;
             fv[1].mo = g->host.m;
             g->fused = (DevGraph *)ptr(gp.fdg);
-            if (e == hipSuccess) e = hipMemsetAsync(m2, 0, sizeof(float) * L.M, st);  // its zero panel
             if (e == hipSuccess) e = hipMemcpyAsync(g->fused, fv, sizeof(fv), hipMemcpyHostToDevice, st);
         }
-        if (e == hipSuccess) e = upload_lists(gp.ll, (char *)ptr(gp.items), st, &g->vl, &g->fl);
-        // the host staging (L, gp) must outlive the copies
+        describe_lists(gp.ll, (char *)ptr(gp.items), &g->vl, &g->fl);
+        // the host image and the descriptors must outlive the copies
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        panel_free(own_image);
+        own_image = nullptr;
         if (e != hipSuccess) {
             if (g->owns_memory) (void)hipFree(g->dmem);
             delete g;
@@ -348,6 +384,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         *out = g;
         return LBP_OK;
     } catch (const std::bad_alloc &) {
+        panel_free(own_image);
         if (g) {
             if (g->dmem && g->owns_memory) (void)hipFree(g->dmem);
             delete g;

@@ -56,6 +56,10 @@ void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<
 void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs);
 // Device bytes of the lists' work items (one 256-aligned piece per launch).
 size_t lists_bytes(const LaunchLists &ll);
+// Launch descriptors of lists whose items sit at device address `mem`.
+void describe_lists(const LaunchLists &ll, char *mem, std::vector<Launch> *vl, std::vector<Launch> *fl);
+// Writes the lists' items at host address `host` in the same arrangement.
+void pack_lists(const LaunchLists &ll, char *host);
 // Copies the lists into `mem` on `st` and fills the launch descriptors.
 hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::vector<Launch> *vl,
                         std::vector<Launch> *fl);
@@ -148,10 +152,17 @@ hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph
 // Device bytes an uploaded layout occupies (with_fused: plus the second
 // message buffer and views of the fused iteration, if the layout allows it).
 size_t graph_device_bytes(const HostLayout &L, bool with_fused);
+// Host image of a graph's device data: the layout's arrays and launch lists
+// packed in device order (graph_image_bytes(L) bytes, written by
+// graph_fill_image), uploaded with one copy.
+size_t graph_image_bytes(const HostLayout &L);
+void graph_fill_image(const HostLayout &L, char *image);
 // Creates a graph from a compiled (and checked) layout.  mem: a 256-aligned
 // region of graph_device_bytes(L, with_fused) bytes the caller owns, or
-// nullptr to allocate.  Copies run on `st`, and the call waits for them.
-int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out);
+// nullptr to allocate.  image: the layout's host image, or nullptr to build
+// one here.  Copies run on `st`, and the call waits for them.
+int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
+                 const char *image = nullptr);
 void graph_destroy(lbp_graph *g);
 
 // Read-out (beliefs and/or MAP) on `st`; host outputs are copied with

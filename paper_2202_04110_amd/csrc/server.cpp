@@ -100,11 +100,17 @@ struct Request {
     int32_t done = 0;
     int32_t status = LBP_OK;
     bool cancel = false;
-    double t_arrival = 0, t_admit = -1, t_done = -1;
+    double t_arrival = 0, t_ready = -1, t_admit = -1, t_done = -1;
     float *q = nullptr;
     int32_t *map = nullptr;
     float *gphi = nullptr;
     float *gq_dev = nullptr, *gphi_dev = nullptr;
+    // device data packed for one upload (built by a prep thread; freed at
+    // admission or with the request)
+    struct ImageFree {
+        void operator()(char *p) const { panel_free(p); }
+    };
+    std::unique_ptr<char, ImageFree> image;
 };
 
 // What the scheduler asks of the machine.  The GPU executor runs the HIP
@@ -120,6 +126,8 @@ public:
     virtual void release(Request &r) = 0;
     virtual int alloc_outputs(Request &r) = 0;
     virtual void free_outputs(Request &r) = 0;
+    // whether prep threads should pack each request's upload image
+    virtual bool wants_image() const { return false; }
 };
 
 class HostExecutor : public Executor {
@@ -180,9 +188,12 @@ public:
     // Called on the worker thread before any other call.
     void bind() { (void)hipSetDevice(ctx_.device); }
 
+    bool wants_image() const override { return true; }
+
     int admit(Request &r) override {
         char *mem = base_ + r.off;
-        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g);
+        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get());
+        r.image.reset();  // uploaded (graph_create waits for its copies)
         if (rc != LBP_OK) return rc;
         r.g->last_T = r.T;
         if (r.backward) {
@@ -441,13 +452,23 @@ struct lbp_server {
                     }
                     if (r->bytes > arena.capacity()) rc = LBP_E_BUDGET;
                 }
+                if (rc == LBP_OK && exec->wants_image()) {
+                    // pack the upload here, off the worker thread; the host
+                    // panels are then no longer needed
+                    r->image.reset((char *)panel_alloc(graph_image_bytes(r->L)));
+                    if (!r->image) throw std::bad_alloc();
+                    graph_fill_image(r->L, r->image.get());
+                    PanelBuf().swap(r->L.phi_panel);
+                    PanelBuf().swap(r->L.theta_panel);
+                }
             } catch (const std::bad_alloc &) {
                 rc = LBP_E_OOM;
             }
             r->desc.reset();
-            const double dt = clock() - tp;
+            const double tn = clock();
+            r->t_ready = tn;
             std::lock_guard<std::mutex> lk(mu);
-            prep_s += dt;
+            prep_s += tn - tp;
             r->prep = rc == LBP_OK ? 1 : 2;
             r->prep_status = rc;
             cv.notify_one();
@@ -753,6 +774,7 @@ int lbp_server_poll(lbp_server *s, lbp_completion *out, int32_t max, int32_t *n_
         c.map = ok ? r->map : nullptr;
         c.grad_logpot = ok && r->backward ? r->gphi : nullptr;
         c.t_arrival = r->t_arrival;
+        c.t_ready = r->t_ready;
         c.t_admit = r->t_admit;
         c.t_done = r->t_done;
         s->handed_out.push_back(r);

@@ -92,7 +92,8 @@ class Completion(C.Structure):
                 ("num_vars", C.c_int64), ("num_var_states", C.c_int64), ("num_logpots", C.c_int64),
                 ("beliefs", C.POINTER(C.c_float)), ("map", C.POINTER(C.c_int32)),
                 ("grad_logpot", C.POINTER(C.c_float)),
-                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+                ("t_arrival", C.c_double), ("t_ready", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
 
 
 _sig("lbp_server_create", C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)])
@@ -413,7 +414,7 @@ class Server:
         for i in range(n.value):
             c = buf[i]
             rec = {"req_id": int(c.req_id), "status": int(c.status), "t_arrival": c.t_arrival,
-                   "t_admit": c.t_admit, "t_done": c.t_done, "beliefs": None, "map": None, "grad_logpot": None}
+                   "t_ready": c.t_ready, "t_admit": c.t_admit, "t_done": c.t_done, "beliefs": None, "map": None, "grad_logpot": None}
             if c.beliefs:
                 rec["beliefs"] = np.ctypeslib.as_array(c.beliefs, (c.num_var_states,)).copy()
                 rec["map"] = np.ctypeslib.as_array(c.map, (c.num_vars,)).copy()

@@ -54,12 +54,15 @@ def run_stream(server, specs, arrivals, iters: int, damping: float, temperature:
     lat = np.array([r["t_done"] - r["t_arrival"] for r in ok]) if ok else np.zeros(0)
     makespan = (max(r["t_done"] for r in ok) - t_start) if ok else 0.0
     es_total = sum(int(specs[r["req_id"]].num_edge_states) for r in ok) * iters
-    wait = np.array([r["t_admit"] - r["t_arrival"] for r in ok]) if ok else np.zeros(0)
-    serve = np.array([r["t_done"] - r["t_admit"] for r in ok]) if ok else np.zeros(0)
+    def p50(xs):
+        return float(np.percentile(np.array(xs), 50)) if xs else None
+
     summary = {
         "requests": n, "ok": len(ok),
-        "queue_p50_s": float(np.percentile(wait, 50)) if wait.size else None,
-        "service_p50_s": float(np.percentile(serve, 50)) if serve.size else None,
+        "prep_p50_s": p50([r["t_ready"] - r["t_arrival"] for r in ok]),
+        "admit_wait_p50_s": p50([r["t_admit"] - r["t_ready"] for r in ok]),
+        "service_p50_s": p50([r["t_done"] - r["t_admit"] for r in ok]),
+        "last_ready_s": (max(r["t_ready"] for r in ok) - t_start) if ok else None,
         "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
         "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
         "mean_s": float(lat.mean()) if lat.size else None,
