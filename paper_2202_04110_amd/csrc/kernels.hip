@@ -163,6 +163,64 @@ __device__ __forceinline__ void belief_regs(const DevGraph &G, int v, int n, flo
     }
 }
 
+// The beliefs of two lane-path variables at once (va with na states, vb with
+// nb), each with belief_regs' additions in its order; both gathers are in
+// flight together.
+template <int NA, int NB>
+__device__ __forceinline__ void belief_regs2(const DevGraph &G, int va, int na, int vb, int nb, float (&ba)[NA],
+                                             float (&bb)[NB]) {
+    constexpr int KU = 4;
+#pragma unroll
+    for (int s = 0; s < NA; ++s) ba[s] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < NB; ++s) bb[s] = 0.0f;
+    const int ka = va >= 0 ? G.vtile[va >> 6].kmax : 0;
+    const int kb = vb >= 0 ? G.vtile[vb >> 6].kmax : 0;
+    const int32_t *ea = nullptr, *eb = nullptr;
+    if (va >= 0) {
+        const VTile vt = G.vtile[va >> 6];
+        const int base = vt.b_off + (va & (kLanes - 1));
+#pragma unroll
+        for (int s = 0; s < NA; ++s)
+            if (s < na) ba[s] = G.theta[base + s * kLanes];
+        ea = G.vedge + vt.e_off + (va & (kLanes - 1));
+    }
+    if (vb >= 0) {
+        const VTile vt = G.vtile[vb >> 6];
+        const int base = vt.b_off + (vb & (kLanes - 1));
+#pragma unroll
+        for (int s = 0; s < NB; ++s)
+            if (s < nb) bb[s] = G.theta[base + s * kLanes];
+        eb = G.vedge + vt.e_off + (vb & (kLanes - 1));
+    }
+    const int kmax = ka > kb ? ka : kb;
+    for (int k0 = 0; k0 < kmax; k0 += KU) {
+        int a[KU], b[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            a[u] = (k0 + u < ka) ? ea[(k0 + u) * kLanes] : -1;
+            b[u] = (k0 + u < kb) ? eb[(k0 + u) * kLanes] : -1;
+        }
+        float x[KU][NA], y[KU][NB];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+#pragma unroll
+            for (int s = 0; s < NA; ++s) x[u][s] = (a[u] >= 0 && s < na) ? G.m[a[u] + s * kLanes] : 0.0f;
+#pragma unroll
+            for (int s = 0; s < NB; ++s) y[u][s] = (b[u] >= 0 && s < nb) ? G.m[b[u] + s * kLanes] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+#pragma unroll
+            for (int s = 0; s < NA; ++s)
+                if (a[u] >= 0 && s < na) ba[s] += x[u][s];
+#pragma unroll
+            for (int s = 0; s < NB; ++s)
+                if (b[u] >= 0 && s < nb) bb[s] += y[u][s];
+        }
+    }
+}
+
 // mid: lane l holds edge l; a butterfly over the wavefront (every lane ends
 // with the same bits) sums each state.
 __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int lane) {
@@ -274,9 +332,10 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
 // own incoming term.  EXACT: NA x NB known at compile time; otherwise the
 // tile's (a, b) <= (NA, NB) are read at run time with the same arithmetic.
 // FUSED: the two slot beliefs are recomputed here from the messages being
-// read (belief_regs, the variable phase's exact arithmetic) instead of being
-// read from B, so one launch does a whole iteration; messages are then read
-// from G.m and written to G.mo, a different buffer.
+// read (belief_regs2: the variable phase's additions in its order, both
+// gathers in flight together) instead of being read from B, so one launch
+// does a whole iteration; messages are then read from G.m and written to
+// G.mo, a different buffer.
 template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED>
 __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
     const int na = EXACT ? NA : ft.a;
@@ -288,8 +347,7 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
     float m0[NA], m1[NB], x0[NA], x1[NB];
     if (FUSED) {
         float b0[NA], b1[NB];
-        belief_regs<NA>(G, G.fvar[ft.vb_off + lane], na, b0);
-        belief_regs<NB>(G, G.fvar[ft.vb_off + kLanes + lane], nb, b1);
+        belief_regs2<NA, NB>(G, G.fvar[ft.vb_off + lane], na, G.fvar[ft.vb_off + kLanes + lane], nb, b0, b1);
 #pragma unroll
         for (int i = 0; i < NA; ++i)
             if (i < na) {
