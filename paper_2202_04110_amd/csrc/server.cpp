@@ -16,6 +16,7 @@
 // The same kernels and per-element arithmetic run whether a graph is alone or
 // in the mix, so served results are bitwise equal to lone runs.
 #include <hip/hip_runtime.h>
+#include <sched.h>
 
 #include <algorithm>
 #include <chrono>
@@ -655,7 +656,11 @@ int server_create(lbp_ctx *ctx, int64_t budget, int32_t max_slots, int32_t steps
         }
         lbp_server *raw = s.get();
         s->th = std::thread([raw] { raw->run(); });
-        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        // preparation threads: half the CPUs this process may run on, at
+        // most 8 (more contend for host memory bandwidth and run slower)
+        unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        cpu_set_t set;
+        if (sched_getaffinity(0, sizeof(set), &set) == 0) hw = std::max(1, CPU_COUNT(&set));
         const unsigned np = std::min(8u, std::max(1u, hw / 2));
         for (unsigned i = 0; i < np; ++i) s->preps.emplace_back([raw] { raw->prep_loop(); });
         *out = s.release();
