@@ -38,6 +38,10 @@ def test_budget_and_slots_respected(lbp):
     # first in, first out: admission times follow submission order
     adm = [recs[i]["t_admit"] for i in range(len(specs))]
     assert all(a <= b for a, b in zip(adm, adm[1:]))
+    # each request was prepared after it arrived and admitted after that
+    for r in recs.values():
+        assert r["t_arrival"] <= r["t_ready"] <= r["t_admit"] <= r["t_done"]
+    assert st["prep_threads"] >= 1 and st["prep_us"] > 0 and st["round_us"] <= st["busy_us"]
     # zero-filled outputs of the right sizes from the bookkeeping executor
     assert recs[3]["beliefs"].shape == (specs[3].num_var_states,)
     assert recs[3]["map"].shape == (specs[3].num_vars,)
