@@ -185,6 +185,45 @@ def gradient_leg(lbp, W, ctx, reps=10, side=64, states=6, iters=50, every=10):
             "record_plus_backward_ms": t_b, "backward_over_forward": (t_b - t_r) / t_f}
 
 
+def sampling_leg(lbp, W, ctx, S, iters=1000, reps=3):
+    """Perturb-and-MAP on the deconvolution workload: S samples (Gumbel(0,1)
+    noise on the evidence, max-product, damping 0.5, `iters` iterations)
+    in shared launches, against one plain solve of the same graph."""
+    import torch
+
+    spec = W.deconv(seed=4)
+    g = lbp.Graph(ctx, spec)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    u = torch.rand((S, g.VS), device="cuda", generator=gen).clamp_(1e-12, 1 - 1e-12)
+    noise = (-torch.log(-torch.log(u))).contiguous()
+    sp = lbp.Sampler(g, S)
+    mp = torch.empty((S, g.V), device="cuda", dtype=torch.int32)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def one():
+        g.reset_messages()
+        g.run_bp(iters, 0.5, 0.0)
+        g.decode_map(out=mp[0])
+
+    t1 = timed(one)
+    ts = timed(lambda: sp.run(iters, 0.5, 0.0, noise, map_out=mp))
+    sp.free()
+    g.free()
+    return {"graph": "binary deconvolution (OR/AND factors), max-product, damping 0.5, %d iterations" % iters,
+            "samples": S, "edge_states": spec.num_edge_states, "single_solve_ms": t1 * 1e3,
+            "sample_batch_ms": ts * 1e3, "samples_per_s": S / ts,
+            "edge_state_updates_per_s": spec.num_edge_states * iters * S / ts,
+            "speedup_over_sequential": S * t1 / ts}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +237,8 @@ def main():
                     help="also run the served stream with N requests (0: skip)")
     ap.add_argument("--serving-budget-mb", default="512,2048",
                     help="comma-separated HBM budgets of the served stream, in MiB")
+    ap.add_argument("--samples", type=int, default=0, metavar="S",
+                    help="also time S perturb-and-MAP samples of the deconvolution graph in shared launches")
     ap.add_argument("--gradient", action="store_true",
                     help="also time a recorded solve plus its reverse sweep against the forward solve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -312,6 +353,8 @@ def main():
                                      [int(x) for x in str(args.serving_budget_mb).split(",") if x])
     if args.gradient:
         out["gradient"] = gradient_leg(lbp, W, ctx)
+    if args.samples:
+        out["sampling"] = sampling_leg(lbp, W, ctx, args.samples)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, iters, d, T)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

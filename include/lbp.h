@@ -60,6 +60,7 @@ enum { LBP_FACTOR_ENUM = 0, LBP_FACTOR_OR = 1, LBP_FACTOR_AND = 2 };
 typedef struct lbp_ctx lbp_ctx;
 typedef struct lbp_graph lbp_graph;
 typedef struct lbp_batch lbp_batch;
+typedef struct lbp_sampler lbp_sampler;
 typedef struct lbp_server lbp_server;
 
 /*
@@ -241,6 +242,31 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
                      lbp_batch **out);
 int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature);
 void lbp_batch_free(lbp_batch *b);
+
+/*
+ * Sample batches: many solves of one graph under perturbed evidence in
+ * shared launches, for perturb-and-MAP sampling (the method of the blind
+ * deconvolution example the paper cites, Sec. "Specifying complex factor
+ * graphs"; batches of samples in parallel, Sec. "Exciting new
+ * possibilities").  A sampler owns num_samples (1 .. 65535) private sets of
+ * messages, beliefs and evidence panels; it shares the graph's structure,
+ * potentials and evidence, and the graph must outlive it.
+ * lbp_sampler_run: for every sample s, evidence_s = the graph's current
+ * evidence + noise[s] (noise: device, num_samples x VS floats, flat
+ * variable-state order, summed in FP32), messages from zero, then `iters`
+ * iterations at (damping, temperature) and the read-out of sample s:
+ * MAP states (map_out: device, num_samples x V int32) and, if q_out is not
+ * NULL, normalised beliefs (device, num_samples x VS floats).  Each sample's
+ * outputs are bitwise those of the graph run alone with evidence_s set.
+ * Perturb-and-MAP: noise drawn i.i.d. from Gumbel(0, 1), scaled, and
+ * temperature 0.  The caller draws the noise; asynchronous on the context's
+ * stream; the graph's own messages are untouched.  LBP_E_OOM when the
+ * sample panels do not fit; LBP_E_INVALID on bad arguments.
+ */
+int lbp_sampler_create(lbp_graph *g, int32_t num_samples, lbp_sampler **out);
+int lbp_sampler_run(lbp_sampler *s, int32_t iters, float damping, float temperature, const float *noise,
+                    int32_t *map_out, float *q_out);
+void lbp_sampler_free(lbp_sampler *s);
 
 /*
  * Serving with continuous batching.  Requests arrive while others run: a

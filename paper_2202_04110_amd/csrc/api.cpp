@@ -611,6 +611,105 @@ int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature)
     return LBP_OK;
 }
 
+// ---------------------------------------------------------------- samplers
+int lbp_sampler_create(lbp_graph *g, int32_t num_samples, lbp_sampler **out) {
+    if (!g || !out) return fail(LBP_E_INVALID, "graph or out is NULL");
+    if (num_samples < 1 || num_samples > 65535) return fail(LBP_E_INVALID, "num_samples must be in [1, 65535]");
+    lbp_sampler *sp = nullptr;
+    try {
+        HIP_TRY(hipSetDevice(g->ctx->device));
+        const int32_t S = num_samples;
+        LaunchLists ll;
+        std::vector<WorkItem> mids, highs;
+        for (int32_t s = 0; s < S; ++s) add_to_lists(ll, s, g->shape, &mids, &highs);
+        finish_lists(ll, mids, highs);
+        const size_t vbytes = align256(sizeof(DevGraph) * S), lbytes = lists_bytes(ll);
+        const size_t mb = align256(sizeof(float) * g->M), bb = align256(sizeof(float) * g->VB),
+                     fb = align256(sizeof(int32_t) * 4);
+        const size_t per = mb + 2 * bb + fb;
+        const size_t total = vbytes + lbytes + per * (size_t)S;
+        sp = new lbp_sampler;
+        sp->g = g;
+        sp->S = S;
+        hipError_t e = hipMalloc((void **)&sp->dmem, total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete sp;
+            return fail(LBP_E_OOM, "sampler allocation of " + std::to_string(total) + " bytes failed");
+        }
+        hipStream_t st = g->ctx->stream;
+        std::vector<DevGraph> hv(S, g->host);
+        char *p = sp->dmem + vbytes + lbytes;
+        for (int32_t s = 0; s < S; ++s, p += per) {
+            DevGraph &h = hv[s];
+            h.m = h.mo = (float *)p;
+            h.B = (float *)(p + mb);
+            h.theta = (float *)(p + mb + bb);
+            h.flag = (int32_t *)(p + mb + 2 * bb);
+            sp->m.push_back(h.m);
+            sp->flag.push_back(h.flag);
+            // zero panels and idle lanes as in the graph; real entries are
+            // rewritten by every run
+            if (e == hipSuccess) e = hipMemsetAsync(h.m, 0, sizeof(float) * g->M, st);
+            if (e == hipSuccess) e = hipMemsetAsync(h.B, 0, sizeof(float) * g->VB, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h.theta, g->host.theta, sizeof(float) * g->VB, hipMemcpyDeviceToDevice, st);
+        }
+        sp->views = (DevGraph *)sp->dmem;
+        if (e == hipSuccess) e = hipMemcpyAsync(sp->views, hv.data(), sizeof(DevGraph) * S, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = upload_lists(ll, sp->dmem + vbytes, st, &sp->vl, &sp->fl);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipFree(sp->dmem);
+            delete sp;
+            return hip_error(e, "sampler upload");
+        }
+        *out = sp;
+        return LBP_OK;
+    } catch (const std::bad_alloc &) {
+        if (sp) {
+            if (sp->dmem) (void)hipFree(sp->dmem);
+            delete sp;
+        }
+        return fail(LBP_E_OOM, "host allocation failed");
+    }
+}
+
+int lbp_sampler_run(lbp_sampler *sp, int32_t iters, float damping, float temperature, const float *noise,
+                    int32_t *map_out, float *q_out) {
+    if (!sp) return fail(LBP_E_INVALID, "sampler is NULL");
+    if (!noise || !map_out) return fail(LBP_E_INVALID, "noise or map_out is NULL");
+    std::string why;
+    if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
+    lbp_graph *g = sp->g;
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t st = g->ctx->stream;
+    hipError_t e = launch_evidence_perturb(sp->views, sp->S, (int)g->V, g->host.theta, noise, g->VS, st);
+    for (int32_t s = 0; s < sp->S && e == hipSuccess; ++s) {
+        e = hipMemsetAsync(sp->m[s], 0, sizeof(float) * g->M, st);
+        if (e == hipSuccess) e = hipMemsetAsync(sp->flag[s], 0, sizeof(int32_t) * 4, st);
+    }
+    if (e == hipSuccess)
+        e = run_loop(g->ctx, sp->loops, sp->views, nullptr, sp->vl, sp->fl, iters, damping, temperature);
+    const TParams P = make_params(damping, temperature);
+    const bool maxp = temperature == 0.0f;
+    if (e == hipSuccess) e = launch_iteration(sp->views, sp->vl, sp->fl, P, maxp, st, 1);  // beliefs
+    for (int32_t s = 0; s < sp->S && e == hipSuccess; ++s)
+        e = launch_readout(sp->views + s, g->nvt, maxp, P, q_out ? q_out + (int64_t)s * g->VS : nullptr, 1,
+                           map_out + (int64_t)s * g->V, st);
+    if (e != hipSuccess) return hip_error(e, "sampler run");
+    return LBP_OK;
+}
+
+void lbp_sampler_free(lbp_sampler *sp) {
+    if (!sp) return;
+    (void)hipSetDevice(sp->g->ctx->device);
+    (void)hipStreamSynchronize(sp->g->ctx->stream);
+    destroy_loops(sp->loops);
+    (void)hipFree(sp->dmem);
+    delete sp;
+}
+
 void lbp_batch_free(lbp_batch *b) {
     if (!b) return;
     (void)hipSetDevice(b->ctx->device);

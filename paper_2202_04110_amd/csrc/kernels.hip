@@ -1145,6 +1145,19 @@ __global__ void k_evidence_in(const DevGraph *__restrict__ gs, const float *__re
     for (int s = 0; s < G.vn[v]; ++s) row[s * kLanes] = in[o + s];
 }
 
+// Evidence panel of sample blockIdx.y = base panel + that sample's noise
+// (flat variable-state order), in FP32.
+__global__ void k_evidence_perturb(const DevGraph *__restrict__ views, const float *__restrict__ base,
+                                   const float *__restrict__ noise, int64_t VS) {
+    const int s = blockIdx.y;
+    const DevGraph &G = views[s];
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= G.V) return;
+    const int64_t addr = G.vtile[v / kLanes].b_off + (v % kLanes);
+    const float *nz = noise + (int64_t)s * VS + G.vs_off[v];
+    for (int t = 0; t < G.vn[v]; ++t) G.theta[addr + t * kLanes] = base[addr + t * kLanes] + nz[t];
+}
+
 __global__ void k_logpot_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
     const DevGraph &G = gs[0];
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1263,6 +1276,13 @@ hipError_t launch_msgs_in(const DevGraph *gs, int E, const float *in, hipStream_
 hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStream_t st) {
     if (V <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_evidence_in, dim3(blocks_for(V, 256)), dim3(256), 0, st, gs, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_evidence_perturb(const DevGraph *views, int S, int V, const float *base, const float *noise,
+                                  int64_t VS, hipStream_t st) {
+    if (V <= 0 || S <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_evidence_perturb, dim3(blocks_for(V, 256), S), dim3(256), 0, st, views, base, noise, VS);
     return hipGetLastError();
 }
 

@@ -140,6 +140,17 @@ struct lbp_batch {
     std::vector<lbp::CachedLoop> loops;
 };
 
+struct lbp_sampler {
+    lbp_graph *g = nullptr;
+    int32_t S = 0;
+    char *dmem = nullptr;
+    lbp::DevGraph *views = nullptr;  // device [S]: the graph with sample s's messages, beliefs, evidence
+    std::vector<float *> m;          // sample s's message panels (device)
+    std::vector<int32_t *> flag;     // sample s's read-out flags (device)
+    std::vector<lbp::Launch> vl, fl;
+    std::vector<lbp::CachedLoop> loops;
+};
+
 namespace lbp {
 
 // Runs `iters` iterations on the context's stream: through a cached captured

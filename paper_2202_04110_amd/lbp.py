@@ -85,6 +85,9 @@ _sig("lbp_run_bp_backward", C.c_int, [_P, _P, _P, _P])
 _sig("lbp_batch_create", C.c_int, [_P, _P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_batch_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
 _sig("lbp_batch_free", None, [_P])
+_sig("lbp_sampler_create", C.c_int, [_P, C.c_int32, C.POINTER(_P)])
+_sig("lbp_sampler_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, _P, _P, _P])
+_sig("lbp_sampler_free", None, [_P])
 
 
 class Completion(C.Structure):
@@ -364,6 +367,44 @@ class Batch:
     def free(self):
         if getattr(self, "h", None):
             _lib.lbp_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Sampler:
+    """num_samples solves of one graph under perturbed evidence in shared
+    launches (perturb-and-MAP: Gumbel noise, temperature 0).  The graph must
+    outlive the sampler."""
+
+    def __init__(self, graph: Graph, num_samples: int):
+        self.graph = graph
+        self.S = int(num_samples)
+        h = _P()
+        check(_lib.lbp_sampler_create(graph.h, self.S, C.byref(h)))
+        self.h = h
+
+    def run(self, iters: int, damping: float, temperature: float, noise, map_out=None, q_out=None):
+        """noise: CUDA float32 tensor (num_samples, VS).  Returns the MAP
+        states, a CUDA int32 tensor (num_samples, V) (and q_out, if given, holds
+        (num_samples, VS) normalised beliefs).  Asynchronous on the context's
+        stream."""
+        import torch
+        assert noise.is_cuda and noise.dtype == torch.float32 and noise.is_contiguous()
+        assert noise.numel() == self.S * self.graph.VS
+        if map_out is None:
+            map_out = torch.empty((self.S, self.graph.V), device=noise.device, dtype=torch.int32)
+        check(_lib.lbp_sampler_run(self.h, int(iters), float(damping), float(temperature), _ptr(noise),
+                                   _ptr(map_out), _ptr(q_out) if q_out is not None else None))
+        return map_out
+
+    def free(self):
+        if getattr(self, "h", None):
+            _lib.lbp_sampler_free(self.h)
             self.h = None
 
     def __del__(self):
