@@ -189,6 +189,18 @@ int lbp_reset_messages(lbp_graph *g);
  * Messages persist, so a second call continues where the first stopped. */
 int lbp_run_bp(lbp_graph *g, int32_t iters, float damping, float temperature);
 
+/* Runs iterations as lbp_run_bp until the messages settle: after every
+ * check_every >= 1 iterations it measures the residual of the last one, the
+ * largest |change| of any edge-state message (NaN or infinity count as not
+ * settled), and stops once it is below tol >= 0, or after max_iters >= 0
+ * iterations.  iters_done (may be NULL) receives the iterations run and
+ * residual_out (may be NULL) the last residual measured (0 if none).  Each
+ * check waits for the device; the messages are those of lbp_run_bp with
+ * iters_done iterations.  The first call allocates a message-sized
+ * workspace kept with the graph (LBP_E_OOM if it does not fit). */
+int lbp_run_bp_until(lbp_graph *g, int32_t max_iters, float damping, float temperature, float tol,
+                     int32_t check_every, int32_t *iters_done, float *residual_out);
+
 /* Beliefs from the current messages at the temperature of the last run (0
  * before any run), VS floats variable-major: normalised q = B - LSE_T(B) when
  * `normalized`, else B.  MAP: lowest-index argmax of B per variable (V int32;

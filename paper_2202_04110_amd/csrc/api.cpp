@@ -220,6 +220,50 @@ int lbp_run_bp(lbp_graph *g, int32_t iters, float damping, float temperature) {
     return LBP_OK;
 }
 
+int lbp_run_bp_until(lbp_graph *g, int32_t max_iters, float damping, float temperature, float tol,
+                     int32_t check_every, int32_t *iters_done, float *residual_out) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    std::string why;
+    if (!valid_params(max_iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
+    if (!(tol >= 0.0f) || !std::isfinite(tol)) return fail(LBP_E_INVALID, "tol must be finite and >= 0");
+    if (check_every < 1) return fail(LBP_E_INVALID, "check_every must be >= 1");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t st = g->ctx->stream;
+    const size_t mb = align256(sizeof(float) * std::max<int64_t>(1, g->M));
+    const int nb = residual_blocks((int)g->E);
+    if (!g->conv) {
+        hipError_t e = hipMalloc((void **)&g->conv, mb + align256(sizeof(float) * (nb + 1)));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            g->conv = nullptr;
+            return fail(LBP_E_OOM, "convergence workspace");
+        }
+    }
+    float *mprev = (float *)g->conv, *partial = (float *)(g->conv + mb), *res = partial + nb;
+    ++g->version;
+    g->last_T = temperature;
+    int32_t done = 0;
+    float r = 0.0f;
+    while (done < max_iters) {
+        const int32_t c = std::min(check_every, max_iters - done);
+        hipError_t e = hipSuccess;
+        if (c > 1)
+            e = run_loop(g->ctx, g->loops, g->dgraph, g->use_fused ? g->fused : nullptr, g->vl, g->fl, c - 1, damping,
+                         temperature);
+        if (e == hipSuccess) e = hipMemcpyAsync(mprev, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = run_loop(g->ctx, g->loops, g->dgraph, nullptr, g->vl, g->fl, 1, damping, temperature);
+        if (e == hipSuccess) e = launch_residual(g->dgraph, (int)g->E, mprev, partial, res, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&r, res, sizeof(float), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_error(e, "iteration launch");
+        done += c;
+        if (r < tol) break;
+    }
+    if (iters_done) *iters_done = done;
+    if (residual_out) *residual_out = r;
+    return LBP_OK;
+}
+
 int lbp_graph_status(lbp_graph *g) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");
     HIP_TRY(hipSetDevice(g->ctx->device));

@@ -54,6 +54,11 @@ hipError_t launch_readout(const DevGraph *gs, int nvtiles, bool maxp, const TPar
 hipError_t launch_msgs_out(const DevGraph *gs, int E, float *out, hipStream_t st);
 hipError_t launch_msgs_in(const DevGraph *gs, int E, const float *in, hipStream_t st);
 hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStream_t st);
+// Residual of the last iteration of a single graph (gs[0]): out[0] = max over
+// edge-state entries of |m - mprev| (non-finite as infinity); partial holds
+// residual_blocks(E) floats.
+int residual_blocks(int E);
+hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float *partial, float *out, hipStream_t st);
 // Sample s (0 <= s < S) of views: evidence = base panel + noise[s * VS + ...].
 hipError_t launch_evidence_perturb(const DevGraph *views, int S, int V, const float *base, const float *noise,
                                   int64_t VS, hipStream_t st);

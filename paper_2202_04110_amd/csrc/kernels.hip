@@ -23,6 +23,7 @@
 // batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -1145,6 +1146,46 @@ __global__ void k_evidence_in(const DevGraph *__restrict__ gs, const float *__re
     for (int s = 0; s < G.vn[v]; ++s) row[s * kLanes] = in[o + s];
 }
 
+// Residual of an iteration: the largest |m - mprev| over the edge-state
+// entries (flat mapping; padding lanes excluded), per block, NaN and
+// infinity as infinity; then one block takes the maximum of the block
+// results.  Maxima do not depend on the order of reduction.
+__global__ __launch_bounds__(256) void k_residual(const DevGraph *__restrict__ gs, const float *__restrict__ mprev,
+                                                  float *__restrict__ partial) {
+    __shared__ float red[256];
+    const DevGraph &G = gs[0];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    float r = 0.0f;
+    if (e < G.E) {
+        const int a = G.edge_maddr[e];
+        const int n = (int)(G.es_off[e + 1] - G.es_off[e]);
+        for (int s = 0; s < n; ++s) {
+            const float d = fabsf(G.m[a + s * kLanes] - mprev[a + s * kLanes]);
+            r = (d == d && d <= 3.0e38f) ? fmaxf(r, d) : INFINITY;
+        }
+    }
+    red[threadIdx.x] = r;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_max_final(const float *__restrict__ partial, int n, float *__restrict__ out) {
+    __shared__ float red[256];
+    float r = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) r = fmaxf(r, partial[i]);
+    red[threadIdx.x] = r;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // Evidence panel of sample blockIdx.y = base panel + that sample's noise
 // (flat variable-state order), in FP32.
 __global__ void k_evidence_perturb(const DevGraph *__restrict__ views, const float *__restrict__ base,
@@ -1276,6 +1317,15 @@ hipError_t launch_msgs_in(const DevGraph *gs, int E, const float *in, hipStream_
 hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStream_t st) {
     if (V <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_evidence_in, dim3(blocks_for(V, 256)), dim3(256), 0, st, gs, in);
+    return hipGetLastError();
+}
+
+int residual_blocks(int E) { return blocks_for(std::max(E, 1), 256); }
+
+hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float *partial, float *out, hipStream_t st) {
+    const int nb = residual_blocks(E);
+    hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, st, gs, mprev, partial);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, partial, nb, out);
     return hipGetLastError();
 }
 

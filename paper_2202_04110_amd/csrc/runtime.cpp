@@ -396,6 +396,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
 void graph_destroy(lbp_graph *g) {
     if (!g) return;
     destroy_loops(g->loops);
+    if (g->conv) (void)hipFree(g->conv);
     if (g->adj.dmem && g->adj.owns_memory) (void)hipFree(g->adj.dmem);
     if (g->owns_memory) (void)hipFree(g->dmem);
     delete g;

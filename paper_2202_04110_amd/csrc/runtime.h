@@ -116,6 +116,7 @@ struct lbp_graph {
     std::vector<lbp::CachedLoop> loops;
     bool has_logical = false;
     uint64_t version = 0;  // bumped by every call that changes messages or inputs
+    char *conv = nullptr;  // lbp_run_bp_until workspace: previous messages, partial and final residuals
     // reverse-sweep workspace and the record it belongs to
     struct Adjoint {
         bool valid = false;

@@ -85,6 +85,8 @@ _sig("lbp_run_bp_backward", C.c_int, [_P, _P, _P, _P])
 _sig("lbp_batch_create", C.c_int, [_P, _P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_batch_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
 _sig("lbp_batch_free", None, [_P])
+_sig("lbp_run_bp_until", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32,
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_float)])
 _sig("lbp_sampler_create", C.c_int, [_P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_sampler_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, _P, _P, _P])
 _sig("lbp_sampler_free", None, [_P])
@@ -259,6 +261,17 @@ class Graph:
 
     def run_bp(self, iters: int, damping: float, temperature: float):
         check(_lib.lbp_run_bp(self.h, int(iters), float(damping), float(temperature)))
+
+    def run_bp_until(self, max_iters: int, damping: float, temperature: float, tol: float,
+                     check_every: int = 1):
+        """Iterates until the last iteration's largest message change is
+        below tol (checked every check_every iterations) or max_iters; returns
+        (iterations run, last residual)."""
+        done = C.c_int32()
+        res = C.c_float()
+        check(_lib.lbp_run_bp_until(self.h, int(max_iters), float(damping), float(temperature), float(tol),
+                                    int(check_every), C.byref(done), C.byref(res)))
+        return int(done.value), float(res.value)
 
     def reset_messages(self):
         check(_lib.lbp_reset_messages(self.h))

@@ -510,3 +510,39 @@ def test_binding_imported_before_torch():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "64"
+
+
+def test_run_until_converged(lbp, ctx):
+    """Early exit: the iteration count at which the largest message change
+    first drops below tol matches the FP64 oracle's residual history (where
+    the crossing is clear of FP32 noise); messages equal lbp_run_bp with that
+    many iterations; checks every k iterations stop on a multiple of k."""
+    spec = W.potts_grid(24, 4, 31)
+    og = OracleGraph(spec)
+    _, res = og.run(300, 0.5, 1.0, threads=NT, residuals=True)
+    tol = 1e-3
+    t_or = int(np.argmax(res < tol)) + 1  # iterations until the first residual below tol
+    g = lbp.Graph(ctx, spec)
+    done, r = g.run_bp_until(300, 0.5, 1.0, tol)
+    print("oracle stops after %d iterations (residual %.3g), GPU after %d (%.3g)" % (t_or, res[t_or - 1], done, r))
+    clear = abs(res[t_or - 1] - tol) > 1e-4 * tol and abs(res[t_or - 2] - tol) > 1e-4 * tol
+    assert done == t_or if clear else abs(done - t_or) <= 1
+    assert r < tol and abs(r - res[done - 1]) <= 1e-5 + 1e-3 * res[done - 1]
+    ref = lbp.Graph(ctx, spec)
+    ref.run_bp(done, 0.5, 1.0)
+    np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
+    g.reset_messages()
+    done7, r7 = g.run_bp_until(300, 0.5, 1.0, tol, check_every=7)
+    assert done7 % 7 == 0 and r7 < tol and done7 - 7 < done <= done7
+    # a cap below the crossing runs exactly the cap
+    g.reset_messages()
+    assert g.run_bp_until(5, 0.5, 1.0, 0.0)[0] == 5
+    with pytest.raises(lbp.LBPError):
+        g.run_bp_until(10, 0.5, 1.0, -1.0)
+    with pytest.raises(lbp.LBPError):
+        g.run_bp_until(10, 0.5, 1.0, 1e-3, check_every=0)
+    # fused iterations stop at the same count with the same messages
+    f = lbp.Graph(ctx, spec)
+    f.use_fused(True)
+    assert f.run_bp_until(300, 0.5, 1.0, tol) == (done, r)
+    np.testing.assert_array_equal(f.get_messages(), ref.get_messages())
