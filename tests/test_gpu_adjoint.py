@@ -170,3 +170,37 @@ def test_gradient_matches_finite_differences(lbp, ctx):
             fd = (vals[0] - vals[1]) / (2 * h)
             print("%s[%d]: gpu %.6f fd %.6f" % (field, i, grad[i], fd))
             assert abs(grad[i] - fd) <= 1e-3 * scale
+
+
+def test_learning_loop_matches_oracle_gradient_descent(lbp, ctx):
+    """Gradient descent on a marginal-matching cross-entropy through the
+    reverse sweep (learn.fit) follows the trajectory of the same descent
+    driven by the FP64 oracle's gradients, and lowers the loss."""
+    import copy
+    import torch
+    from paper_2202_04110_amd.learn import fit
+    spec = W.potts_grid(8, 3, seed=21)
+    teacher = copy.deepcopy(spec)
+    teacher.log_potentials = np.random.default_rng(22).normal(0, 1.0, len(spec.log_potentials)).astype(np.float32)
+    iters, d, lr, steps = 30, 0.5, 0.5, 6
+    ot = OracleGraph(teacher)
+    _, qt, _ = ot.beliefs(ot.run(iters, d, 1.0), 1.0)
+    target = np.exp(qt)
+    g = lbp.Graph(ctx, spec)
+    phi_g, _, losses = fit(g, torch.from_numpy(target.astype(np.float32)).cuda(),
+                           torch.from_numpy(spec.log_potentials.copy()).cuda(),
+                           torch.from_numpy(spec.evidence.copy()).cuda(), steps=steps, lr=lr, iters=iters, damping=d,
+                           ckpt_every=10)
+    phi_g = phi_g.cpu().numpy()
+    # the same descent on the oracle's gradients (FP32 tables, as the library holds them)
+    phi = spec.log_potentials.astype(np.float32).copy()
+    s = copy.deepcopy(spec)
+    for _ in range(steps):
+        s.log_potentials = phi
+        og = OracleGraph(s)
+        gphi, _, _ = og.backward(iters, d, 1.0, -target / spec.num_vars)
+        phi = (phi - np.float32(lr) * gphi.astype(np.float32)).astype(np.float32)
+    err = float(np.abs(phi_g - phi).max())
+    print("losses %s; max |phi_gpu - phi_oracle| after %d steps = %.2e" % (np.round(losses, 5), steps, err))
+    assert err <= 2e-4 * max(1.0, float(np.abs(phi).max()))
+    assert losses[-1] < losses[0]
