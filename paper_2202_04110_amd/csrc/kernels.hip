@@ -234,10 +234,11 @@ __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int la
 #pragma unroll
         for (int j = 0; j < SC; ++j) x[j] = (a >= 0 && s0 + j < h.n) ? G.m[a + (s0 + j) * kLanes] : 0.0f;
 #pragma unroll
-        for (int j = 0; j < SC; ++j) {
+        for (int j = 0; j < SC; ++j)
+            if (s0 + j < h.n) {  // uniform
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) x[j] += __shfl_xor(x[j], off, 64);
-        }
+                for (int off = 32; off > 0; off >>= 1) x[j] += __shfl_xor(x[j], off, 64);
+            }
         if (lane < SC && s0 + lane < h.n) {
             float v = 0.0f;
 #pragma unroll
@@ -539,6 +540,24 @@ __device__ __forceinline__ void logl_tile(const DevGraph &G, const FTile &ft, in
         }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP moves:
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes (lanes without a source
+// add 0), then row 15's and row 31's values carried into the rows above.
+// A fixed sequence of additions, so every wavefront gets the same bits.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_take(float y) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), CTRL, ROW_MASK, 0xf, true));
+}
+__device__ __forceinline__ float wave_incl_scan(float y) {
+    y += dpp_take<0x111, 0xf>(y);  // row_shr:1
+    y += dpp_take<0x112, 0xf>(y);  // row_shr:2
+    y += dpp_take<0x114, 0xf>(y);  // row_shr:4
+    y += dpp_take<0x118, 0xf>(y);  // row_shr:8
+    y += dpp_take<0x142, 0xa>(y);  // row_bcast:15 into rows 1 and 3
+    y += dpp_take<0x143, 0xc>(y);  // row_bcast:31 into rows 2 and 3
+    return y;
+}
+
 // one wavefront per factor; edge j sits in chunk j/64 at lane j%64
 template <int CH, bool MAXP>
 __device__ __forceinline__ void logw_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
@@ -567,38 +586,28 @@ __device__ __forceinline__ void logw_tile(const DevGraph &G, const FTile &ft, in
 #pragma unroll
     for (int c = 0; c < CH; ++c)
         if (c == p / kLanes) dc = __shfl(dl[c], p % kLanes, 64);
-    // exclusive prefix sums over parents, chunk-major
+    // exclusive prefix sums over parents, chunk-major (DPP scans)
     float carry = 0.0f;
 #pragma unroll
     for (int c = 0; c < CH; ++c)
         if (c < nch) {
-            float x = t[c];
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const float y = __shfl_up(x, off, 64);
-                if (lane >= off) x += y;
-            }
+            const float x = wave_incl_scan(t[c]);
             float ex = __shfl_up(x, 1, 64);
             if (lane == 0) ex = 0.0f;
             pre[c] = carry + ex;
-            carry += __shfl(x, 63, 64);
+            carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
         }
     const float total = carry;
-    // exclusive suffix sums
+    // exclusive suffix sums: the same scan over the lanes in reverse order
     carry = 0.0f;
 #pragma unroll
     for (int c = CH - 1; c >= 0; --c)
         if (c < nch) {
-            float x = t[c];
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const float y = __shfl_down(x, off, 64);
-                if (lane + off < 64) x += y;
-            }
-            float ex = __shfl_down(x, 1, 64);
+            const float x = wave_incl_scan(__shfl(t[c], 63 - lane, 64));  // lane l: sum of t[63-l..63]
+            float ex = __shfl(x, 62 - lane, 64);                          // sum of t[l+1..63]
             if (lane == 63) ex = 0.0f;
             suf[c] = carry + ex;
-            carry += __shfl(x, 0, 64);
+            carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
         }
     float max1 = -INFINITY, max2 = -INFINITY;
     int amax = 0x7fffffff;
