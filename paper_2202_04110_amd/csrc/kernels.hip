@@ -55,6 +55,74 @@ __device__ __forceinline__ int wave_item(int swz) {
 }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP moves:
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes (lanes without a source
+// add 0), then row 15's and row 31's values carried into the rows above.
+// A fixed sequence of additions, so every wavefront gets the same bits.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_take(float y) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), CTRL, ROW_MASK, 0xf, true));
+}
+// the same move, lanes without a source (or masked off) reading `fill`
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_take_or(float y, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(y), CTRL, ROW_MASK, 0xf,
+                                                      false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_take_or_i(int y, int fill) {
+    return __builtin_amdgcn_update_dpp(fill, y, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ float wave_incl_scan(float y) {
+    y += dpp_take<0x111, 0xf>(y);  // row_shr:1
+    y += dpp_take<0x112, 0xf>(y);  // row_shr:2
+    y += dpp_take<0x114, 0xf>(y);  // row_shr:4
+    y += dpp_take<0x118, 0xf>(y);  // row_shr:8
+    y += dpp_take<0x142, 0xa>(y);  // row_bcast:15 into rows 1 and 3
+    y += dpp_take<0x143, 0xc>(y);  // row_bcast:31 into rows 2 and 3
+    return y;
+}
+
+// Sum over the wavefront's 64 lanes, the same bits in every lane (the last
+// lane of the DPP scan, read as a scalar).
+__device__ __forceinline__ float wave_sum(float y) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_incl_scan(y)), 63));
+}
+
+// Largest value over the wavefront and the lowest lane index holding it
+// (index, not value, order on ties), by a DPP max-scan of (value, index)
+// pairs; the same result in every lane.
+__device__ __forceinline__ void wave_argmax(float &v, int &i) {
+#define ARGMAX_STEP(CTRL, RM)                                   \
+    {                                                          \
+        const float ov = dpp_take_or<CTRL, RM>(v, -INFINITY);  \
+        const int oi = dpp_take_or_i<CTRL, RM>(i, 0x7fffffff); \
+        if (ov > v || (ov == v && oi < i)) {                   \
+            v = ov;                                            \
+            i = oi;                                            \
+        }                                                      \
+    }
+    ARGMAX_STEP(0x111, 0xf)
+    ARGMAX_STEP(0x112, 0xf)
+    ARGMAX_STEP(0x114, 0xf)
+    ARGMAX_STEP(0x118, 0xf)
+    ARGMAX_STEP(0x142, 0xa)
+    ARGMAX_STEP(0x143, 0xc)
+#undef ARGMAX_STEP
+    v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    i = __builtin_amdgcn_readlane(i, 63);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, dpp_take_or<0x111, 0xf>(v, -INFINITY));
+    v = fmaxf(v, dpp_take_or<0x112, 0xf>(v, -INFINITY));
+    v = fmaxf(v, dpp_take_or<0x114, 0xf>(v, -INFINITY));
+    v = fmaxf(v, dpp_take_or<0x118, 0xf>(v, -INFINITY));
+    v = fmaxf(v, dpp_take_or<0x142, 0xa>(v, -INFINITY));
+    v = fmaxf(v, dpp_take_or<0x143, 0xc>(v, -INFINITY));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
 
@@ -222,8 +290,8 @@ __device__ __forceinline__ void belief_regs2(const DevGraph &G, int va, int na, 
     }
 }
 
-// mid: lane l holds edge l; a butterfly over the wavefront (every lane ends
-// with the same bits) sums each state.
+// mid: lane l holds edge l; a wavefront sum (wave_sum: the same bits in
+// every lane) adds up each state.
 __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int lane) {
     constexpr int SC = 8;
     const HVar h = G.hvar[hv];
@@ -235,10 +303,7 @@ __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int la
         for (int j = 0; j < SC; ++j) x[j] = (a >= 0 && s0 + j < h.n) ? G.m[a + (s0 + j) * kLanes] : 0.0f;
 #pragma unroll
         for (int j = 0; j < SC; ++j)
-            if (s0 + j < h.n) {  // uniform
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) x[j] += __shfl_xor(x[j], off, 64);
-            }
+            if (s0 + j < h.n) x[j] = wave_sum(x[j]);  // uniform condition
         if (lane < SC && s0 + lane < h.n) {
             float v = 0.0f;
 #pragma unroll
@@ -251,8 +316,8 @@ __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int la
 }
 
 // high: thread i sums edges i, i+256, ... in order (fetched 4 at a time);
-// each wavefront combines its 64 partial sums with a butterfly (every lane
-// ends with the same bits), and the four wavefront sums are added in order.
+// each wavefront combines its 64 partial sums (wave_sum), and the four
+// wavefront sums are added in order.
 constexpr int kHighThreads = 256;
 constexpr int kHighWaves = kHighThreads / 64;
 __device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int tid, float (*red)[kHighWaves]) {
@@ -287,8 +352,7 @@ __device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int t
 #pragma unroll
         for (int j = 0; j < SC; ++j)
             if (j < ns) {
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) part[j] += __shfl_xor(part[j], off, 64);
+                part[j] = wave_sum(part[j]);
                 if (lane == 0) red[j][wave] = part[j];
             }
         __syncthreads();
@@ -540,24 +604,6 @@ __device__ __forceinline__ void logl_tile(const DevGraph &G, const FTile &ft, in
         }
 }
 
-// Inclusive prefix sum over the 64 lanes of a wavefront with DPP moves:
-// shifts by 1, 2, 4, 8 inside each row of 16 lanes (lanes without a source
-// add 0), then row 15's and row 31's values carried into the rows above.
-// A fixed sequence of additions, so every wavefront gets the same bits.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_take(float y) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), CTRL, ROW_MASK, 0xf, true));
-}
-__device__ __forceinline__ float wave_incl_scan(float y) {
-    y += dpp_take<0x111, 0xf>(y);  // row_shr:1
-    y += dpp_take<0x112, 0xf>(y);  // row_shr:2
-    y += dpp_take<0x114, 0xf>(y);  // row_shr:4
-    y += dpp_take<0x118, 0xf>(y);  // row_shr:8
-    y += dpp_take<0x142, 0xa>(y);  // row_bcast:15 into rows 1 and 3
-    y += dpp_take<0x143, 0xc>(y);  // row_bcast:31 into rows 2 and 3
-    return y;
-}
-
 // one wavefront per factor; edge j sits in chunk j/64 at lane j%64
 template <int CH, bool MAXP>
 __device__ __forceinline__ void logw_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
@@ -621,22 +667,13 @@ __device__ __forceinline__ void logw_tile(const DevGraph &G, const FTile &ft, in
                 amax = j;
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float ov = __shfl_xor(max1, off, 64);
-            const int oi = __shfl_xor(amax, off, 64);
-            if (ov > max1 || (ov == max1 && oi < amax)) {
-                max1 = ov;
-                amax = oi;
-            }
-        }
+        wave_argmax(max1, amax);
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const int j = c * kLanes + lane;
             if (c < nch && j < p && j != amax) max2 = fmaxf(max2, dl[c]);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) max2 = fmaxf(max2, __shfl_xor(max2, off, 64));
+        max2 = wave_max(max2);
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
