@@ -466,6 +466,10 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
             }
             const int32_t gidx = (int32_t)L->gcls.size();
             L->gcls.push_back(gc);
+            // launch groups: dense three-way classes with 2..4 states in every
+            // slot run in registers (code -N); the others by LDS need
+            const bool tri = t < 0 && k == 3 && ns[0] == ns[1] && ns[1] == ns[2] && ns[0] >= 2 && ns[0] <= 4;
+            grp.a = tri ? -ns[0] : gen_lds_code(gc.ncfg * gc.arity, gc.nrows);
             for (size_t i0 = 0; i0 < facs.size(); i0 += kLanes) {
                 FTile ft{};
                 ft.kind = TK_GEN;
@@ -679,6 +683,21 @@ int check_layout(const HostLayout &L, std::string *err) {
                 if (!in(ft.a, (int64_t)L.gcls.size())) return oob("generic class index");
                 const GenClass &gc = L.gcls[ft.a];
                 if (gc.arity > kGenArityMax || gc.ncfg > kGenCfgMax || gc.nrows > kGenRowsMax) return oob("generic limits");
+                if (fg.a < 0) {  // the register kernel: a dense three-way class with -a states per slot
+                    const int N = -fg.a;
+                    if (gc.arity != 3 || gc.ncfg != N * N * N || gc.nrows != 3 * N) return oob("three-way class");
+                    for (int32_t j = 0; j < 3; ++j)
+                        if (gc.slot_n[j] != N || gc.slot_row[j] != j * N) return oob("three-way slots");
+                    for (int32_t c = 0; c < gc.ncfg; ++c)  // dense order, last slot fastest
+                        for (int32_t j = 0; j < 3; ++j) {
+                            const int32_t st = j == 0 ? c / (N * N) : j == 1 ? (c / N) % N : c % N;
+                            if (L.grows[gc.rows_off + (int64_t)c * 3 + j] != j * N + st) return oob("three-way table");
+                        }
+                } else if (fg.a != 0) {  // the dynamic-LDS kernel: the class must fit the group's LDS
+                    int rb, nr;
+                    gen_lds_decode(fg.a, &rb, &nr);
+                    if ((int64_t)gc.ncfg * gc.arity > rb || gc.nrows > nr) return oob("generic class exceeds its LDS");
+                }
                 if (gc.rows_off + (int64_t)gc.ncfg * gc.arity > (int64_t)L.grows.size()) return oob("generic rows");
                 for (int64_t i = 0; i < (int64_t)gc.ncfg * gc.arity; ++i)
                     if (L.grows[gc.rows_off + i] >= gc.nrows) return oob("generic row entry");

@@ -46,7 +46,11 @@ hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na,
 // true for factors of 257..1024 edges.
 hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool wide, bool maxp, const TParams &P,
                           const LaunchShape &S, hipStream_t st);
-hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
+// Generic classes.  lds_code -N: dense three-way classes with N (2..4)
+// states per slot, in registers; 0: the kernel with LDS for the largest
+// class; otherwise gen_lds_code(rows bytes, summed slot states) of the
+// classes in the launch, which sizes its dynamic LDS.
+hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P, int lds_code,
                       hipStream_t st);
 // Read-out of a single graph (gs[0]).
 hipError_t launch_readout(const DevGraph *gs, int nvtiles, bool maxp, const TParams &P, float *q, int normalized,

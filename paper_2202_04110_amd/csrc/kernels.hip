@@ -736,21 +736,13 @@ __global__ __launch_bounds__(256) void k_logical_wide(const DevGraph *__restrict
 // LDS, incoming terms and per-(slot,state) accumulators live in LDS.
 // u[e_j,s] = LSE_T{score(c) : c_j = s} - n[e_j,s],  score(c) = phi(c) + sum_l n[e_l,c_l]
 // --------------------------------------------------------------------------
+// One tile of a generic class: `rows` holds the class's configuration rows
+// (C x A bytes), nv / acc / sacc are [R][64] float arrays in LDS.
 template <bool MAXP>
-__global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
-                                            int nitems, TParams P) {
-    __shared__ uint8_t rows[kGenCfgMax * kGenArityMax];
-    __shared__ float nv[kGenRowsMax][kLanes];
-    __shared__ float acc[kGenRowsMax][kLanes];
-    __shared__ float sacc[kGenRowsMax][kLanes];
-    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
-    if (w >= nitems) return;
-    const int lane = lane_id();
-    const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
-    const FTile ft = G.ftile[it.t];
+__device__ __forceinline__ void gen_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P,
+                                         uint8_t *rows, float *nv, float *acc, float *sacc) {
     const GenClass gc = G.gcls[ft.a];
-    const int A = gc.arity, C = gc.ncfg, R = gc.nrows;
+    const int A = gc.arity, C = gc.ncfg;
     for (int i = lane; i < C * A; i += kLanes) rows[i] = G.grows[gc.rows_off + i];
     const float *mrow = G.m + ft.m_off + lane;
     float *wrow = G.mo + ft.m_off + lane;
@@ -758,28 +750,28 @@ __global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, con
         const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
         for (int s = 0; s < gc.slot_n[j]; ++s) {
             const int r = gc.slot_row[j] + s;
-            nv[r][lane] = G.B[vb + s * kLanes] - mrow[r * kLanes];
-            acc[r][lane] = -INFINITY;
-            sacc[r][lane] = 0.0f;
+            nv[r * kLanes + lane] = G.B[vb + s * kLanes] - mrow[r * kLanes];
+            acc[r * kLanes + lane] = -INFINITY;
+            sacc[r * kLanes + lane] = 0.0f;
         }
     }
     __syncthreads();
     const float *ph = G.phi + ft.phi_off + lane;
     for (int c = 0; c < C; ++c) {
         float sc = ph[c * kLanes];
-        for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j]][lane];
+        for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j] * kLanes + lane];
         for (int j = 0; j < A; ++j) {
             const int r = rows[c * A + j];
-            acc[r][lane] = fmaxf(acc[r][lane], sc);
+            acc[r * kLanes + lane] = fmaxf(acc[r * kLanes + lane], sc);
         }
     }
     if (!MAXP) {
         for (int c = 0; c < C; ++c) {
             float sc = ph[c * kLanes];
-            for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j]][lane];
+            for (int j = 0; j < A; ++j) sc += nv[rows[c * A + j] * kLanes + lane];
             for (int j = 0; j < A; ++j) {
                 const int r = rows[c * A + j];
-                sacc[r][lane] += fexp2((sc - acc[r][lane]) * P.c);
+                sacc[r * kLanes + lane] += fexp2((sc - acc[r * kLanes + lane]) * P.c);
             }
         }
     }
@@ -788,18 +780,118 @@ __global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, con
         float mx = -INFINITY;
         for (int s = 0; s < n; ++s) {
             const int r = r0 + s;
-            const float lse = MAXP ? acc[r][lane] : acc[r][lane] + flog2(sacc[r][lane]) * P.r;
-            const float u = lse - nv[r][lane];
+            const float lse =
+                MAXP ? acc[r * kLanes + lane] : acc[r * kLanes + lane] + flog2(sacc[r * kLanes + lane]) * P.r;
+            const float u = lse - nv[r * kLanes + lane];
             const float mn = P.d * mrow[r * kLanes] + P.omd * u;
-            sacc[r][lane] = mn;  // reuse as staging for the normalisation
+            sacc[r * kLanes + lane] = mn;  // reuse as staging for the normalisation
             mx = fmaxf(mx, mn);
         }
         for (int s = 0; s < n; ++s) {
             const int r = r0 + s;
-            wrow[r * kLanes] = sacc[r][lane] - mx;
+            wrow[r * kLanes] = sacc[r * kLanes + lane] - mx;
         }
     }
-    (void)R;
+}
+
+// Dense three-way classes with N states in every slot (N^3 <= 64
+// configurations, last slot fastest): one lane per factor with the table,
+// incoming terms and scores in registers.  The generic class layout (rows of
+// slot j at j*N), so the reverse sweep's generic kernel serves these tiles.
+// u_j[s] = LSE_T{score(c) : c_j = s} - n_j[s], score = phi + n_0 + n_1 + n_2.
+template <int N, bool MAXP>
+__device__ __forceinline__ void tri_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+    const float *mrow = G.m + ft.m_off + lane;
+    float m[3][N], x[3][N];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
+#pragma unroll
+        for (int s = 0; s < N; ++s) {
+            m[j][s] = mrow[(j * N + s) * kLanes];
+            x[j][s] = G.B[vb + s * kLanes] - m[j][s];
+        }
+    }
+    const float *ph = G.phi + ft.phi_off + lane;
+    float sc[N][N][N];
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int c = 0; c < N; ++c) sc[a][b][c] = ph[((a * N + b) * N + c) * kLanes] + x[0][a] + x[1][b] + x[2][c];
+    float u[3][N];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int s = 0; s < N; ++s) {
+            float M = -INFINITY;
+#pragma unroll
+            for (int p = 0; p < N; ++p)
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    const float v = j == 0 ? sc[s][p][q] : j == 1 ? sc[p][s][q] : sc[p][q][s];
+                    M = fmaxf(M, v);
+                }
+            if (MAXP) {
+                u[j][s] = M - x[j][s];
+            } else {
+                float e = 0.0f;
+#pragma unroll
+                for (int p = 0; p < N; ++p)
+#pragma unroll
+                    for (int q = 0; q < N; ++q) {
+                        const float v = j == 0 ? sc[s][p][q] : j == 1 ? sc[p][s][q] : sc[p][q][s];
+                        e += fexp2((v - M) * P.c);
+                    }
+                u[j][s] = M + flog2(e) * P.r - x[j][s];
+            }
+        }
+    float *wrow = G.mo + ft.m_off + lane;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) damp_store<N>(wrow + j * N * kLanes, m[j], u[j], N, P);
+}
+
+template <int N, bool MAXP>
+__global__ __launch_bounds__(256) void k_tri(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                             int nitems, TParams P) {
+    const int w = wave_index(4);
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    tri_tile<N, MAXP>(G, G.ftile[it.t], lane_id(), P);
+}
+
+// Any class within the kernel limits: LDS for the largest (80 KB), which
+// leaves room for two such blocks per CU.
+template <bool MAXP>
+__global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                            int nitems, TParams P) {
+    __shared__ uint8_t rows[kGenCfgMax * kGenArityMax];
+    __shared__ float nv[kGenRowsMax * kLanes];
+    __shared__ float acc[kGenRowsMax * kLanes];
+    __shared__ float sacc[kGenRowsMax * kLanes];
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    gen_tile<MAXP>(G, G.ftile[it.t], lane_id(), P, rows, nv, acc, sacc);
+}
+
+// Classes whose rows and accumulators fit the launch's dynamic LDS (sized
+// per launch group from its classes), so many blocks share a CU.
+template <bool MAXP>
+__global__ __launch_bounds__(64) void k_gen_dyn(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                                int nitems, TParams P, int rows_bytes, int nrows) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    float *nv = (float *)(smem + rows_bytes);
+    float *acc = nv + nrows * kLanes;
+    float *sacc = acc + nrows * kLanes;
+    gen_tile<MAXP>(G, G.ftile[it.t], lane_id(), P, smem, nv, acc, sacc);
 }
 
 // --------------------------------------------------------------------------
@@ -1331,11 +1423,33 @@ hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool
     return hipGetLastError();
 }
 
-hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P,
+hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P, int lds_code,
                       hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    if (maxp) hipLaunchKernelGGL((k_gen<true>), dim3(n), dim3(64), 0, st, gs, items, n, P);
-    else hipLaunchKernelGGL((k_gen<false>), dim3(n), dim3(64), 0, st, gs, items, n, P);
+    if (lds_code < 0) {  // dense three-way, -N states per slot
+        dim3 grid(blocks_for(n, 4)), block(256);
+        switch (-lds_code) {
+#define TRI_CASE(K)                                                                                 \
+    case K:                                                                                         \
+        if (maxp) hipLaunchKernelGGL((k_tri<K, true>), grid, block, 0, st, gs, items, n, P);     \
+        else hipLaunchKernelGGL((k_tri<K, false>), grid, block, 0, st, gs, items, n, P);         \
+        break;
+            TRI_CASE(2)
+            TRI_CASE(3)
+            TRI_CASE(4)
+#undef TRI_CASE
+        default: return hipErrorInvalidValue;
+        }
+    } else if (lds_code == 0) {
+        if (maxp) hipLaunchKernelGGL((k_gen<true>), dim3(n), dim3(64), 0, st, gs, items, n, P);
+        else hipLaunchKernelGGL((k_gen<false>), dim3(n), dim3(64), 0, st, gs, items, n, P);
+    } else {
+        int rows_bytes, nrows;
+        gen_lds_decode(lds_code, &rows_bytes, &nrows);
+        const size_t shm = (size_t)rows_bytes + (size_t)3 * nrows * kLanes * sizeof(float);
+        if (maxp) hipLaunchKernelGGL((k_gen_dyn<true>), dim3(n), dim3(64), shm, st, gs, items, n, P, rows_bytes, nrows);
+        else hipLaunchKernelGGL((k_gen_dyn<false>), dim3(n), dim3(64), shm, st, gs, items, n, P, rows_bytes, nrows);
+    }
     return hipGetLastError();
 }
 

@@ -69,6 +69,22 @@ struct GenClass {
     int32_t slot_row[kGenArityMax];
 };
 
+// LDS of the generic-class kernel for a class of `cells` = configurations x
+// arity row bytes and `nrows` summed slot states: rows rounded up to 256
+// bytes, then three [nrows][64] float arrays.  Launch groups of generic
+// classes are keyed by gen_lds_code (0 when the need exceeds kGenDynLdsMax,
+// for the kernel with static LDS for the largest class).
+constexpr int kGenDynLdsMax = 48 * 1024;
+inline int gen_lds_code(int cells, int nrows) {
+    const int rb = (cells + 255) / 256 * 256;
+    const int need = rb + 3 * nrows * 64 * 4;
+    return need <= kGenDynLdsMax ? (rb / 256) * 128 + nrows : 0;
+}
+inline void gen_lds_decode(int code, int *rows_bytes, int *nrows) {
+    *rows_bytes = (code / 128) * 256;
+    *nrows = code % 128;
+}
+
 // Device pointers of one uploaded graph.
 struct DevGraph {
     float *m;             // messages (panels) + a zero panel at zero_addr

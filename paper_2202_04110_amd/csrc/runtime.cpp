@@ -149,7 +149,7 @@ hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, c
             case TK_PAIR: e = launch_pair(gs, L.items, L.n, L.a, L.b, maxp, P, L.shape, st); break;
             case TK_LOGL: e = launch_logical(gs, L.items, L.n, false, maxp, P, L.shape, st); break;
             case TK_LOGW: e = launch_logical(gs, L.items, L.n, true, maxp, P, L.shape, st); break;
-            default: e = launch_gen(gs, L.items, L.n, maxp, P, st); break;
+            default: e = launch_gen(gs, L.items, L.n, maxp, P, L.a, st); break;
             }
             if (e != hipSuccess) return e;
         }

@@ -215,6 +215,36 @@ def random_pairwise(seed: int, num_vars: int, num_factors: int, n: int = 4, max_
                            f"randpair{num_vars}x{n}", {"seed": seed})
 
 
+def triplet_grid(L: int = 256, n: int = 3, seed: int = 12, sd: float = 0.5) -> GraphSpec:
+    """Higher-order grid: L x L variables with n states, one dense three-way
+    factor per three consecutive variables along every row (r,c),(r,c+1),(r,c+2)
+    (all row triples first) and every column; evidence N(0,1), tables N(0, sd)
+    (n^3 entries, last slot fastest)."""
+    rng = np.random.default_rng(seed)
+    V = L * L
+    ev = rng.normal(0.0, 1.0, size=V * n).astype(np.float32)
+    idx = np.arange(V, dtype=np.int64).reshape(L, L)
+    h = np.stack([idx[:, :-2], idx[:, 1:-1], idx[:, 2:]], -1).reshape(-1, 3)
+    v = np.stack([idx[:-2, :], idx[1:-1, :], idx[2:, :]], -1).reshape(-1, 3)
+    tri = np.concatenate([h, v], 0)
+    F = tri.shape[0]
+    tab = rng.normal(0.0, sd, size=(F, n ** 3)).astype(np.float32)
+    return GraphSpec(
+        var_num_states=np.full(V, n, np.int32), evidence=ev,
+        factor_kind=np.zeros(F, np.int32),
+        factor_edge_off=np.arange(F + 1, dtype=np.int64) * 3,
+        edge_var=tri.reshape(-1).astype(np.int32),
+        factor_cfg_table=np.zeros(F, np.int32),
+        cfg_table_num_cfgs=np.zeros(1, np.int32),
+        cfg_table_arity=np.full(1, 3, np.int32),
+        cfg_table_off=np.zeros(2, np.int64),
+        cfg_table_states=np.zeros(0, np.int32),
+        logpot_off=np.arange(F + 1, dtype=np.int64) * n ** 3,
+        log_potentials=tab.reshape(-1),
+        name=f"triplet{L}x{n}", meta={"L": L, "n": n, "seed": seed},
+    )
+
+
 def rbm(nv: int = 784, nh: int = 500, seed: int = 3, w_sd: float = 0.05,
         b_sd: float = 0.1) -> GraphSpec:
     """Restricted Boltzmann machine as a factor graph: visible 0..nv-1, hidden

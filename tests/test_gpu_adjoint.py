@@ -57,10 +57,11 @@ def small_graphs():
         ("potts10x4", W.potts_grid(10, 4, seed=5)),
         ("potts9x3", W.potts_grid(9, 3, seed=6)),
         ("rect", W.disjoint_union([W.potts_grid(6, 2, 1), W.potts_grid(5, 7, 2)])),
+        ("triplet7x3", W.triplet_grid(7, 3, 9)),
     ]
 
 
-@pytest.mark.parametrize("idx", range(5))
+@pytest.mark.parametrize("idx", range(6))
 @pytest.mark.parametrize("T,d", [(1.0, 0.5), (0.5, 0.3)])
 def test_adjoint_matches_oracle(lbp, ctx, idx, T, d):
     name, spec = small_graphs()[idx]

@@ -146,6 +146,10 @@ STEP_CASES = [
     ("rbm40x30", lambda: W.rbm(40, 30, 3), [0.0, 0.05]),
     ("rbm100x90", lambda: W.rbm(100, 90, 5), [0.0]),
     ("deconv_small", lambda: W.deconv(seed=4, K=2, tw=4, sd=10, img=12), [0.0, 0.5]),
+    ("triplet20x3", lambda: W.triplet_grid(20, 3, 5), [1.0, 0.0]),
+    ("triplet9x5", lambda: W.triplet_grid(9, 5, 6), [0.5]),
+    ("triplet12x2", lambda: W.triplet_grid(12, 2, 7), [0.0, 1.0]),
+    ("triplet10x4", lambda: W.triplet_grid(10, 4, 8), [1.0, 0.0]),
     ("mixed1", lambda: mixed_graph(1), [0.0, 0.7]),
     ("mixed2", lambda: mixed_graph(2, max_arity=4, max_states=3), [0.0, 1.0]),
     ("biglogic", lambda: big_logical(5, parents=150), [0.0, 0.3, 1.0]),
@@ -245,6 +249,14 @@ def test_deconv_or_and(lbp, ctx):
         mo = r["og"].run(1, 0.5, 0.0, m0=mg.astype(np.float64))
         r["g"].run_bp(1, 0.5, 0.0)
         assert np.abs(r["g"].get_messages() - mo).max() <= 2 * TOL_STEP
+
+
+def test_triplet_grid_end_to_end(lbp, ctx):
+    """Three-way dense factors (generic enumeration kernel) on a 48x48 grid,
+    3 states, sum-product T=1, damping 0.5, 100 iterations."""
+    r = end_to_end(lbp, ctx, W.triplet_grid(48, 3, 12), 100, 0.5, 1.0)
+    if not r["converged"]:
+        end_to_end(lbp, ctx, W.triplet_grid(48, 3, 12), 10, 0.5, 1.0)
 
 
 def test_mixed_graph_end_to_end(lbp, ctx):
