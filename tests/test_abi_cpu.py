@@ -129,6 +129,29 @@ def test_context_without_gpu_reports_error(lbp):
     assert lbp.last_error()
 
 
+def test_null_handles_are_rejected(lbp):
+    """Every entry point taking a handle rejects NULL with LBP_E_INVALID
+    (no GPU needed) and leaves out-parameters untouched."""
+    import ctypes as C
+    L = lbp._lib
+    out = C.c_void_p(777)
+    n = C.c_int32(5)
+    f = C.c_float(2.5)
+    for rc in (L.lbp_run_bp(None, 1, 0.5, 1.0),
+               L.lbp_run_bp_until(None, 10, 0.5, 1.0, 1e-3, 1, C.byref(n), C.byref(f)),
+               L.lbp_sampler_create(None, 4, C.byref(out)),
+               L.lbp_sampler_run(None, 1, 0.5, 0.0, None, None, None),
+               L.lbp_batch_run(None, 1, 0.5, 1.0),
+               L.lbp_graph_num_launches(None, C.byref(n)),
+               L.lbp_graph_use_fused(None, 1),
+               L.lbp_reset_messages(None),
+               L.lbp_run_bp_record(None, 5, 0.5, 1.0, 2)):
+        assert rc == lbp.LBP_E_INVALID
+    assert out.value == 777 and n.value == 5 and f.value == 2.5
+    L.lbp_sampler_free(None)
+    L.lbp_batch_free(None)
+
+
 def _layout_cases():
     import test_gpu_parity as T
     cases = [(n, mk) for n, mk, _ in T.STEP_CASES]
