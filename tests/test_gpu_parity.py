@@ -132,6 +132,29 @@ def rect_pairs(seed, na=3, nb=5, F=200):
     return W._general_graph(ns, ev, facs, "rect%dx%d" % (na, nb))
 
 
+def logic1024(seed):
+    """one OR factor of exactly 1024 edges (the widest supported) and one AND of 600"""
+    rng = np.random.default_rng(seed)
+    V = 1023 + 2
+    ev = rng.normal(0, 1.5, V * 2).astype(np.float32)
+    facs = [{"kind": W.OR, "vars": list(range(1023)) + [1023]},
+            {"kind": W.AND, "vars": list(rng.choice(1023, size=599, replace=False)) + [1024]}]
+    return W._general_graph(np.full(V, 2, np.int32), ev, facs, "logic1024")
+
+
+def states64(seed):
+    """a 64-state variable (the most states a variable may have) under a unary
+    enumeration factor (64 configurations, 64 summed rows), beside a small
+    chain of pairwise factors"""
+    rng = np.random.default_rng(seed)
+    ns = np.array([64, 2, 2, 3], np.int32)
+    ev = rng.normal(0, 1, int(ns.sum())).astype(np.float32)
+    facs = [{"kind": W.ENUM, "vars": [0], "logpot": rng.normal(0, 1, 64)},
+            {"kind": W.ENUM, "vars": [1, 2], "logpot": rng.normal(0, 1, 4)},
+            {"kind": W.ENUM, "vars": [2, 3], "logpot": rng.normal(0, 1, 6)}]
+    return W._general_graph(ns, ev, facs, "states64")
+
+
 def wide_states(seed, n=16, L=6):
     g = W.potts_grid(L, n, seed=seed)
     g.name = "potts%dx%d" % (L, n)
@@ -154,6 +177,9 @@ STEP_CASES = [
     ("mixed2", lambda: mixed_graph(2, max_arity=4, max_states=3), [0.0, 1.0]),
     ("biglogic", lambda: big_logical(5, parents=150), [0.0, 0.3, 1.0]),
     ("biglogic_wide", lambda: big_logical(6, parents=700, nfac=3), [0.0, 1.0]),
+    ("logic1024", lambda: logic1024(41), [0.0, 0.7]),
+    ("states64", lambda: states64(42), [0.0, 1.0]),
+    ("potts3x32", lambda: W.potts_grid(3, 32, 43), [1.0]),
     ("star300", lambda: star(7, 300, 3), [0.0, 1.0]),
     ("star40", lambda: star(11, 40, 4), [0.0, 1.0]),
     ("star40x20", lambda: star(12, 40, 20), [1.0]),
