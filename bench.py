@@ -312,7 +312,7 @@ def main():
         # it moves the floor bytes: phi, messages in and out, evidence
         kernel, kbytes, kms = "fused iteration (dense pairwise factors, beliefs recomputed)", \
             bm["floor_bytes"], t_fused
-        tkey, shape = "fused", (fl[0]["fused_wpb"], fl[0]["fused_swizzle"])
+        tkey, shape = "fused", (fl[0]["fused_wpb"], fl[0]["fused_variant"])
     elif t_fac >= t_var:
         kernel, kbytes, kms = "factor phase (every factor launch of one iteration)", bm["factor_bytes"], t_fac
         tkey, shape = "factor", (fl[0]["wpb"], fl[0]["swizzle"]) if len(fl) == 1 else (None, None)
@@ -346,7 +346,7 @@ def main():
         "solve_gbps": bm["iter_bytes"] * iters / (ms_step * 1e-3) / 1e9,
         "kernel_src_sha": kernel_source_sha(),
         "launch_shapes": [{k: l[k] for k in ("phase", "kind", "a", "b", "wpb", "swizzle", "fused_wpb",
-                                              "fused_swizzle")} for l in g.launches()],
+                                              "fused_variant")} for l in g.launches()],
         "tune_source": tuned["source"] if tuned else "default",
         "fused_iterations": g.fused_in_use,
         "device": tune.device_key(0),

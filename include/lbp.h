@@ -358,14 +358,19 @@ void lbp_server_destroy(lbp_server *s);
  * fastest; best_ms_out (may be NULL) receives the chosen launch time per
  * group.  lbp_graph_get_launch returns {phase (0 variable, 1 factor), kind,
  * a, b, waves per block, swizzle, work items, fused waves per block, fused
- * swizzle} for group i.
+ * variant} for group i.
  */
 int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out);
 int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[9]);
 int lbp_graph_set_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle);
 /* Shape of the fused variant of factor launch i (see lbp_graph_use_fused);
- * lbp_graph_get_launch returns it in out[7], out[8]. */
-int lbp_graph_set_fused_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle);
+ * lbp_graph_get_launch returns it in out[7], out[8].  variant: bit 0 = the
+ * XCD swizzle; bit 1 = each wavefront loads its factors' tables before
+ * gathering their variables' beliefs instead of after (more loads in flight,
+ * more registers, fewer wavefronts resident: it pays when the graph streams
+ * from HBM rather than sitting in the last-level cache).  Bitwise the same
+ * results for every variant. */
+int lbp_graph_set_fused_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t variant);
 int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, float *best_ms_out);
 /* Fused iterations: for a graph whose variables all have at most 16 edges and
  * 16 states and whose factors are all dense pairwise with equal slot sizes,

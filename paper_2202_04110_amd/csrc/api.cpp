@@ -434,20 +434,20 @@ int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[9]) {
     out[5] = L.shape.swizzle;
     out[6] = L.n + L.n_mid + L.n_high;
     out[7] = L.fshape.wpb;
-    out[8] = L.fshape.swizzle;
+    out[8] = L.fshape.swizzle | (L.fshape.early << 1);
     return LBP_OK;
 }
 
-int lbp_graph_set_fused_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t swizzle) {
+int lbp_graph_set_fused_launch(lbp_graph *g, int32_t i, int32_t waves_per_block, int32_t variant) {
     if (!g) return fail(LBP_E_INVALID, "graph is NULL");
     const int32_t nv = (int32_t)g->vl.size(), nf = (int32_t)g->fl.size();
     if (i < nv || i >= nv + nf || !g->fused) return fail(LBP_E_INVALID, "not a launch with a fused variant");
-    if ((swizzle != 0 && swizzle != 1) || (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4))
-        return fail(LBP_E_INVALID, "waves_per_block must be 1, 2 or 4 and swizzle 0 or 1");
+    if (variant < 0 || variant > 3 || (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4))
+        return fail(LBP_E_INVALID, "waves_per_block must be 1, 2 or 4 and variant 0 to 3");
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
     destroy_loops(g->loops);
-    g->fl[i - nv].fshape = LaunchShape{waves_per_block, swizzle};
+    g->fl[i - nv].fshape = LaunchShape{waves_per_block, variant & 1, variant >> 1};
     return LBP_OK;
 }
 
@@ -522,9 +522,9 @@ int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, f
             LaunchShape best = L.fshape;
             float best_t = 1e30f;
             for (int w : {1, 2, 4})
-                for (int z : {0, 1}) {
+                for (int v : {0, 1, 2, 3}) {
                     if (e != hipSuccess) break;
-                    L.fshape = LaunchShape{w, z};
+                    L.fshape = LaunchShape{w, v & 1, v >> 1};
                     float ms = 0.0f;
                     e = time_loop(g->fused, &ms);
                     if (e == hipSuccess && ms < best_t) {

@@ -18,11 +18,13 @@ struct TParams {
 TParams make_params(float damping, float temperature);
 
 // Launch shape of a wavefront-per-item kernel: wavefronts per block (1, 2 or
-// 4) and whether blocks are remapped so each XCD takes a contiguous range.
-// Neither changes any element's arithmetic.
+// 4), whether blocks are remapped so each XCD takes a contiguous range, and
+// (fused pairwise launches only) whether tables are loaded before the belief
+// gathers.  None changes any element's arithmetic.
 struct LaunchShape {
     int wpb = 4;
     int swizzle = 0;
+    int early = 0;
 };
 
 // Buffers of the reverse sweep (message panels A, nbar; belief panel Bbar;

@@ -401,8 +401,12 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
 // read (belief_regs2: the variable phase's additions in its order, both
 // gathers in flight together) instead of being read from B, so one launch
 // does a whole iteration; messages are then read from G.m and written to
-// G.mo, a different buffer.
-template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED>
+// G.mo, a different buffer.  EARLY (fused only): the table is loaded before
+// the belief gathers rather than after them, so more loads are in flight per
+// wavefront at the cost of registers (fewer wavefronts per SIMD): faster when
+// the graph streams from HBM, slower when it sits in the last-level cache.
+// The arithmetic is the same either way.
+template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED, bool EARLY = false>
 __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
     const int na = EXACT ? NA : ft.a;
     const int nb = EXACT ? NB : ft.b;
@@ -410,6 +414,16 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
     const float *r1 = r0 + na * kLanes;
     float *w0 = G.mo + ft.m_off + lane;
     float *w1 = w0 + na * kLanes;
+    const float *ph = G.phi + ft.phi_off + lane;
+    float p[NA][NB];
+    auto load_table = [&]() {
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (i < na && j < nb) p[i][j] = ph[(i * nb + j) * kLanes];
+    };
+    if (EARLY) load_table();
     float m0[NA], m1[NB], x0[NA], x1[NB];
     if (FUSED) {
         float b0[NA], b1[NB];
@@ -442,13 +456,7 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
                 x1[j] = G.B[vb + j * kLanes] - m1[j];
             }
     }
-    const float *ph = G.phi + ft.phi_off + lane;
-    float p[NA][NB];
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-            if (i < na && j < nb) p[i][j] = ph[(i * nb + j) * kLanes];
+    if (!EARLY) load_table();
     float u0[NA], u1[NB];
     // to slot 0
 #pragma unroll
@@ -498,7 +506,7 @@ __device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, in
     damp_store<NB>(w1, m1, u1, nb, P);
 }
 
-template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED>
+template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED, bool EARLY>
 __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
                                               int nitems, TParams P, int swz) {
     const int w = wave_item(swz);
@@ -506,7 +514,7 @@ __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, c
     const WorkItem it = items[w];
     const DevGraph &G = gs[it.g];
     const FTile ft = G.ftile[it.t];
-    pair_tile<NA, NB, EXACT, MAXP, FUSED>(G, ft, lane_id(), P);
+    pair_tile<NA, NB, EXACT, MAXP, FUSED, EARLY>(G, ft, lane_id(), P);
 }
 
 // --------------------------------------------------------------------------
@@ -1367,14 +1375,14 @@ hipError_t launch_belief(const DevGraph *gs, const WorkItem *items, int n_low, i
     return hipGetLastError();
 }
 
-template <bool MAXP, bool FUSED>
+template <bool MAXP, bool FUSED, bool EARLY>
 static void pair_dispatch(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, const TParams &P,
                           const LaunchShape &S, hipStream_t st) {
     dim3 grid(blocks_for(n, S.wpb)), block(64 * S.wpb);
     const int z = S.swizzle;
-#define PAIR_CASE(N)                                                                                   \
-    case N:                                                                                            \
-        hipLaunchKernelGGL((k_pair<N, N, true, MAXP, FUSED>), grid, block, 0, st, gs, items, n, P, z); \
+#define PAIR_CASE(N)                                                                                          \
+    case N:                                                                                                   \
+        hipLaunchKernelGGL((k_pair<N, N, true, MAXP, FUSED, EARLY>), grid, block, 0, st, gs, items, n, P, z); \
         return;
     if (na == nb) {
         switch (na) {
@@ -1390,20 +1398,23 @@ static void pair_dispatch(const DevGraph *gs, const WorkItem *items, int n, int 
     }
 #undef PAIR_CASE
     if (!FUSED)
-        hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP, false>), grid, block, 0, st, gs,
-                           items, n, P, z);
+        hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP, false, false>), grid, block, 0, st,
+                           gs, items, n, P, z);
 }
 
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
                        const TParams &P, const LaunchShape &S, hipStream_t st, bool fused) {
     if (n <= 0) return hipSuccess;
     if (fused && (na != nb || na < 2 || na > kPairStatesMax)) return hipErrorInvalidValue;
-    if (fused) {
-        if (maxp) pair_dispatch<true, true>(gs, items, n, na, nb, P, S, st);
-        else pair_dispatch<false, true>(gs, items, n, na, nb, P, S, st);
+    if (fused && S.early) {
+        if (maxp) pair_dispatch<true, true, true>(gs, items, n, na, nb, P, S, st);
+        else pair_dispatch<false, true, true>(gs, items, n, na, nb, P, S, st);
+    } else if (fused) {
+        if (maxp) pair_dispatch<true, true, false>(gs, items, n, na, nb, P, S, st);
+        else pair_dispatch<false, true, false>(gs, items, n, na, nb, P, S, st);
     } else {
-        if (maxp) pair_dispatch<true, false>(gs, items, n, na, nb, P, S, st);
-        else pair_dispatch<false, false>(gs, items, n, na, nb, P, S, st);
+        if (maxp) pair_dispatch<true, false, false>(gs, items, n, na, nb, P, S, st);
+        else pair_dispatch<false, false, false>(gs, items, n, na, nb, P, S, st);
     }
     return hipGetLastError();
 }

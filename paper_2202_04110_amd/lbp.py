@@ -324,7 +324,9 @@ class Graph:
                                        _ptr(grad_evidence) if grad_evidence is not None else None))
 
     def launches(self):
-        """Launch groups: dicts with phase, kind, a, b, wpb, swizzle, items."""
+        """Launch groups: dicts with phase, kind, a, b, wpb, swizzle, items, fused_wpb,
+        fused_variant (bit 0 swizzle, bit 1 tables loaded before the belief
+        gathers)."""
         n = C.c_int32()
         check(_lib.lbp_graph_num_launches(self.h, C.byref(n)))
         out = []
@@ -332,11 +334,11 @@ class Graph:
             v = np.zeros(9, np.int32)
             check(_lib.lbp_graph_get_launch(self.h, i, _ptr(v)))
             out.append(dict(zip(("phase", "kind", "a", "b", "wpb", "swizzle", "items", "fused_wpb",
-                                 "fused_swizzle"), (int(x) for x in v))))
+                                 "fused_variant"), (int(x) for x in v))))
         return out
 
-    def set_fused_launch(self, i: int, wpb: int, swizzle: int):
-        check(_lib.lbp_graph_set_fused_launch(self.h, int(i), int(wpb), int(swizzle)))
+    def set_fused_launch(self, i: int, wpb: int, variant: int):
+        check(_lib.lbp_graph_set_fused_launch(self.h, int(i), int(wpb), int(variant)))
 
     def use_fused(self, enable: bool):
         check(_lib.lbp_graph_use_fused(self.h, int(bool(enable))))

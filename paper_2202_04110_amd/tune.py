@@ -66,7 +66,7 @@ def apply_or_tune(graph, damping: float, temperature: float, reps: int = 20, pat
         for i, k in enumerate(keys):
             graph.set_launch(i, cache[k]["wpb"], cache[k]["swizzle"])
             if fkey is not None and lns[i]["phase"] == 1:
-                graph.set_fused_launch(i, cache[k]["fused_wpb"], cache[k]["fused_swizzle"])
+                graph.set_fused_launch(i, cache[k]["fused_wpb"], cache[k].get("fused_variant", 0))
         if fkey is not None:
             graph.use_fused(cache[fkey]["use"])
         return {"source": "cache", "shapes": [cache[k] for k in keys],
@@ -76,7 +76,7 @@ def apply_or_tune(graph, damping: float, temperature: float, reps: int = 20, pat
     cache = user
     for k, ln, t in zip(keys, lns, ms):
         cache[k] = {"wpb": ln["wpb"], "swizzle": ln["swizzle"], "ms": float(t),
-                    "fused_wpb": ln["fused_wpb"], "fused_swizzle": ln["fused_swizzle"]}
+                    "fused_wpb": ln["fused_wpb"], "fused_variant": ln["fused_variant"]}
     if fkey is not None:
         cache[fkey] = {"use": graph.fused_in_use}
     try:

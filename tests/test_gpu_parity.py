@@ -514,18 +514,23 @@ def test_fused_iterations_match_two_phase(lbp, ctx):
             np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
         np.testing.assert_array_equal(g.get_beliefs(), ref.get_beliefs())
         np.testing.assert_array_equal(g.decode_map(), ref.decode_map())
-        # every fused launch shape gives the same bits
+        # every fused launch shape and variant (swizzle; tables loaded before
+        # or after the belief gathers) gives the same bits
         for i, ln in enumerate(g.launches()):
             if ln["phase"] != 1:
                 continue
             for w in (1, 2, 4):
-                for z in (0, 1):
+                for z in (0, 1, 2, 3):
                     g.set_fused_launch(i, w, z)
+                    assert g.launches()[i]["fused_variant"] == z
                     g.reset_messages()
                     ref.reset_messages()
                     g.run_bp(4, 0.5, T)
                     b.run_bp(4, 0.5, T)
                     np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
+            for w, z in ((4, 4), (4, -1), (3, 0)):
+                with pytest.raises(lbp.LBPError):
+                    g.set_fused_launch(i, w, z)
         b.free()
     mg = lbp.Graph(ctx, mixed_graph(104))
     assert not mg.fused
