@@ -118,7 +118,9 @@ def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
     states, sum-product T=1, damping 0.5, 50 iterations; 10% carry a backward
     pass with checkpoints every 10), per HBM budget.  Capacity R is measured
     with every request arriving at once; then Poisson arrivals at 0.5R, 0.8R
-    and 1.0R give p50/p99 latency (completion minus scheduled arrival)."""
+    and 1.0R give p50/p99 latency (completion minus scheduled arrival).
+    "burst, early exit": the burst again with the forward requests stopping
+    once their residual (checked every 5 iterations) is below 1e-3."""
     from paper_2202_04110_amd.serving import run_stream
 
     reqs = W.served_requests(n, seed=seed, backward_count=max(1, n // 10))
@@ -128,21 +130,23 @@ def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
            "edge_states_mean": float(np.mean([s.num_edge_states for s in specs])), "budgets": {}}
     for budget_mb in budgets_mb:
         runs = {}
-        for label, frac in (("burst", None), ("0.5R", 0.5), ("0.8R", 0.8), ("1.0R", 1.0)):
+        for label, frac in (("burst", None), ("0.5R", 0.5), ("0.8R", 0.8), ("1.0R", 1.0),
+                            ("burst, early exit", None)):
             srv = lbp.Server(ctx, budget_bytes=budget_mb << 20, max_slots=64, steps_per_round=5)
             if frac is None:
                 arr = np.zeros(n)
             else:
                 arr = W.poisson_arrivals(n, qps=frac * runs["burst"]["requests_per_s"], seed=seed)
-            _, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10)
+            tol = 1e-3 if "early" in label else None
+            _, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10, tol=tol, check_every=5)
             srv.close()
             st = summ.pop("stats")
             for k in ("max_resident", "rounds", "busy_us", "round_us", "prep_us", "prep_threads"):
                 summ[k] = st[k]
             runs[label] = summ
-            print("serving budget %d MB %s: %.0f req/s p50 %.2f ms p99 %.2f ms" % (
+            print("serving budget %d MB %s: %.0f req/s p50 %.2f ms p99 %.2f ms, %.1f iterations per request" % (
                 budget_mb, label, summ["requests_per_s"] or 0, 1e3 * (summ["p50_s"] or 0),
-                1e3 * (summ["p99_s"] or 0)), file=sys.stderr, flush=True)
+                1e3 * (summ["p99_s"] or 0), summ["iters_mean"] or 0), file=sys.stderr, flush=True)
         out["budgets"]["%d MB" % budget_mb] = runs
     return out
 

@@ -294,13 +294,17 @@ void lbp_sampler_free(lbp_sampler *s);
 typedef struct lbp_completion {
     uint64_t req_id;
     int32_t status;            /* LBP_OK, LBP_E_NONFINITE, LBP_E_STATE (cancelled), other errors */
-    int32_t reserved;
+    int32_t iters_done;        /* iterations run (fewer than asked when a request submitted with
+                                * lbp_server_submit_until settled early) */
     int64_t num_vars, num_var_states, num_logpots;
     const float *beliefs;      /* VS normalised beliefs (host), NULL on failure */
     const int32_t *map;        /* V MAP states (host), NULL on failure */
     const float *grad_logpot;  /* Tn gradient (host) for backward requests, else NULL */
     double t_arrival, t_ready, t_admit, t_done;  /* seconds on the server clock: arrival,
                                                   * compiled and checked, admitted, completed */
+    float residual;            /* lbp_server_submit_until requests: the last residual measured
+                                * (0 if none); other requests: -1 */
+    int32_t reserved;
 } lbp_completion;
 
 /* Server on ctx's device with an arena of hbm_budget_bytes, at most max_slots
@@ -329,6 +333,20 @@ double lbp_server_clock(const lbp_server *s);
  * LBP_E_BUDGET. */
 int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, float damping, float temperature,
                       const float *grad_q, int32_t ckpt_every, double t_arrival, uint64_t req_id);
+/* Queues a forward request that stops once its messages settle, as
+ * lbp_run_bp_until(max_iters, damping, temperature, tol, check_every) on the
+ * graph alone: the residual of the last iteration is measured whenever the
+ * request's own iteration count reaches a multiple of check_every (or
+ * max_iters), and the request leaves at that round boundary once it is below
+ * tol, freeing its slot and memory for queued requests.  Rounds never step
+ * over a request's check points, so the iterations run, the messages, the
+ * beliefs and the residual are bitwise those of the lone lbp_run_bp_until
+ * call whatever else is resident.  The completion reports iters_done and the
+ * residual.  The previous-message workspace (a message-sized buffer) counts
+ * against the budget.  tol must be finite and >= 0, check_every >= 1; other
+ * arguments as for lbp_server_submit (no gradient). */
+int lbp_server_submit_until(lbp_server *s, const lbp_graph_desc *desc, int32_t max_iters, float damping,
+                            float temperature, float tol, int32_t check_every, double t_arrival, uint64_t req_id);
 /* Marks a queued or resident request cancelled; it completes with
  * LBP_E_STATE at the next round boundary. */
 int lbp_server_cancel(lbp_server *s, uint64_t req_id);

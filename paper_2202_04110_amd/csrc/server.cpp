@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <cmath>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
@@ -93,6 +94,16 @@ struct Request {
     int32_t iters = 0, k = 10;
     float d = 0.5f, T = 1.0f;
     bool backward = false;
+    // early exit (lbp_server_submit_until): tol >= 0 enables it; the
+    // residual is measured when done reaches a multiple of check or iters
+    float tol = -1.0f;
+    int32_t check = 0;
+    bool check_now = false;   // this round ends at one of the request's check points
+    int32_t res_slot = 0;     // index of its residual in the round's read-back
+    bool settled = false;     // a check found the residual below tol
+    float residual = -1.0f;   // last residual measured (0 before the first check)
+    size_t conv_bytes = 0;    // previous messages, partial maxima, residual
+    char *conv = nullptr;
     std::vector<float> grad_q;
     HostLayout L;
     size_t bytes = 0, graph_bytes = 0, adj_bytes = 0;
@@ -124,6 +135,8 @@ public:
     virtual int round(const std::vector<Request *> &active, int32_t steps) = 0;
     virtual int wait() = 0;
     virtual int finish(Request &r) = 0;
+    // after wait(): the residual of every request with check_now
+    virtual void residuals(const std::vector<Request *> &active) = 0;
     virtual void release(Request &r) = 0;
     virtual int alloc_outputs(Request &r) = 0;
     virtual void free_outputs(Request &r) = 0;
@@ -137,6 +150,11 @@ public:
     int round(const std::vector<Request *> &, int32_t) override { return LBP_OK; }
     int wait() override { return LBP_OK; }
     int finish(Request &) override { return LBP_OK; }
+    // the bookkeeping executor's messages stay zero, so they never change
+    void residuals(const std::vector<Request *> &active) override {
+        for (Request *r : active)
+            if (r->check_now) r->residual = 0.0f;
+    }
     void release(Request &) override {}
     int alloc_outputs(Request &r) override {
         r.q = (float *)calloc((size_t)std::max<int64_t>(1, r.L.VS), sizeof(float));
@@ -164,18 +182,25 @@ public:
         if (base_) (void)hipFree(base_);
         for (auto &kv : pool_)
             for (void *p : kv.second) (void)hipHostFree(p);
+        if (res_host_) (void)hipHostFree(res_host_);
         if (ev_) (void)hipEventDestroy(ev_);
         if (compute_) (void)hipStreamDestroy(compute_);
         if (copy_) (void)hipStreamDestroy(copy_);
     }
 
-    int init(int device, size_t budget) {
+    int init(int device, size_t budget, int32_t max_slots) {
         ctx_.device = device;
         ctx_.use_graphs = false;
         HIP_TRY(hipSetDevice(device));
         HIP_TRY(hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking));
         HIP_TRY(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+        // one residual per resident request, read back after each round
+        if (hipHostMalloc((void **)&res_host_, sizeof(float) * (size_t)max_slots) != hipSuccess) {
+            (void)hipGetLastError();
+            res_host_ = nullptr;
+            return set_error(LBP_E_OOM, "pinned residual buffer");
+        }
         ctx_.stream = compute_;
         hipError_t e = hipMalloc((void **)&base_, std::max<size_t>(budget, 256));
         if (e != hipSuccess) {
@@ -197,6 +222,7 @@ public:
         r.image.reset();  // uploaded (graph_create waits for its copies)
         if (rc != LBP_OK) return rc;
         r.g->last_T = r.T;
+        if (r.tol >= 0.0f) r.conv = mem + Arena::round(r.graph_bytes);
         if (r.backward) {
             char *am = mem + Arena::round(r.graph_bytes);
             rc = adjoint_prepare(r.g, r.iters, r.d, r.T, r.k, am, copy_);
@@ -222,12 +248,29 @@ public:
                 int rc = adjoint_checkpoint(r->g, r->done / r->g->adj.k, compute_);
                 if (rc != LBP_OK) return rc;
             }
+        for (size_t i = 0; i < active.size(); ++i) active[i]->res_slot = (int32_t)i;
         for (const Part &p : parts_) {
             const TParams P = make_params(p.d, p.T);
             for (int32_t it = 0; it < steps; ++it) {
+                // requests at a check point keep their messages from before
+                // the round's last iteration
+                if (it == steps - 1)
+                    for (Request *r : p.reqs)
+                        if (r->check_now)
+                            HIP_TRY(hipMemcpyAsync(r->conv, r->g->host.m, sizeof(float) * r->g->M,
+                                                   hipMemcpyDeviceToDevice, compute_));
                 hipError_t e = launch_iteration(p.dgs, p.vl, p.fl, P, p.T == 0.0f, compute_);
                 if (e != hipSuccess) return hip_error(e, "served iteration launch");
             }
+            for (Request *r : p.reqs)
+                if (r->check_now) {
+                    const float *mprev = (const float *)r->conv;
+                    float *partial = (float *)(r->conv + align256(sizeof(float) * std::max<int64_t>(1, r->g->M)));
+                    float *res = partial + residual_blocks((int)r->g->E);
+                    HIP_TRY(launch_residual(r->g->dgraph, (int)r->g->E, mprev, partial, res, compute_));
+                    HIP_TRY(hipMemcpyAsync(res_host_ + r->res_slot, res, sizeof(float), hipMemcpyDeviceToHost,
+                                           compute_));
+                }
         }
         HIP_TRY(hipEventRecord(ev_, compute_));
         return LBP_OK;
@@ -236,6 +279,11 @@ public:
     int wait() override {
         HIP_TRY(hipEventSynchronize(ev_));
         return LBP_OK;
+    }
+
+    void residuals(const std::vector<Request *> &active) override {
+        for (Request *r : active)
+            if (r->check_now) r->residual = res_host_[r->res_slot];
     }
 
     int finish(Request &r) override {
@@ -314,6 +362,7 @@ private:
     // Active graphs sharing (damping, temperature) launch together.
     struct Part {
         float d, T;
+        std::vector<Request *> reqs;
         std::vector<DevGraph> hgs;
         LaunchLists ll;
         DevGraph *dgs = nullptr;
@@ -332,6 +381,7 @@ private:
                 p->d = r->d;
                 p->T = r->T;
             }
+            p->reqs.push_back(r);
             p->hgs.push_back(r->g->host);
         }
         size_t total = 0;
@@ -379,6 +429,7 @@ private:
     std::vector<Part> parts_;
     std::mutex pool_mu_;
     std::map<size_t, std::vector<void *>> pool_;
+    float *res_host_ = nullptr;
 };
 
 }  // namespace
@@ -450,6 +501,11 @@ struct lbp_server {
                         r->adj_bytes = adjoint_bytes(r->L.M, r->L.VB, r->L.P, r->iters, r->k);
                         r->bytes += Arena::round(r->adj_bytes) + Arena::round(sizeof(float) * r->L.VS) +
                                     Arena::round(sizeof(float) * r->L.Tn);
+                    }
+                    if (r->tol >= 0.0f) {
+                        r->conv_bytes = align256(sizeof(float) * std::max<int64_t>(1, r->L.M)) +
+                                        sizeof(float) * (residual_blocks((int)r->L.E) + 1);
+                        r->bytes += Arena::round(r->conv_bytes);
                     }
                     if (r->bytes > arena.capacity()) rc = LBP_E_BUDGET;
                 }
@@ -579,11 +635,14 @@ struct lbp_server {
             std::vector<Request *> active;
             int32_t s = steps;
             for (Request *r : resident)
-                if (r->done < r->iters) {
+                if (r->done < r->iters && !r->settled) {
                     active.push_back(r);
                     s = std::min(s, r->iters - r->done);
                     if (r->backward) s = std::min(s, r->k - r->done % r->k);
+                    if (r->tol >= 0.0f) s = std::min(s, r->check - r->done % r->check);
                 }
+            for (Request *r : active)
+                r->check_now = r->tol >= 0.0f && ((r->done + s) % r->check == 0 || r->done + s == r->iters);
             const double tr = clock();
             if (!active.empty()) {
                 int rc = exec->round(active, s);
@@ -601,13 +660,17 @@ struct lbp_server {
                     }
                     continue;
                 }
-                for (Request *r : active) r->done += s;
+                exec->residuals(active);
+                for (Request *r : active) {
+                    r->done += s;
+                    if (r->check_now && r->residual < r->tol) r->settled = true;
+                }
                 std::lock_guard<std::mutex> lk(mu);
                 ++n_rounds;
             }
             for (size_t i = 0; i < resident.size();) {
                 Request *r = resident[i];
-                if (r->done >= r->iters) {
+                if (r->done >= r->iters || r->settled) {
                     int rc = exec->finish(*r);
                     drop_resident(r);
                     resident.erase(resident.begin() + i);
@@ -647,7 +710,7 @@ int server_create(lbp_ctx *ctx, int64_t budget, int32_t max_slots, int32_t steps
         if (on_gpu) {
             if (!ctx) return set_error(LBP_E_INVALID, "ctx is NULL");
             std::unique_ptr<GpuExecutor> g(new GpuExecutor);
-            int rc = g->init(ctx->device, (size_t)budget);
+            int rc = g->init(ctx->device, (size_t)budget, max_slots);
             if (rc != LBP_OK) return rc;
             s->gpu = g.get();
             s->exec = std::move(g);
@@ -687,8 +750,13 @@ int lbp_server_create_host_only(int64_t budget_bytes, int32_t max_slots, int32_t
 
 double lbp_server_clock(const lbp_server *s) { return s ? s->clock() : 0.0; }
 
-int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, float damping, float temperature,
-                      const float *grad_q, int32_t ckpt_every, double t_arrival, uint64_t req_id) {
+}  // extern "C"
+
+namespace {
+
+int submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, float damping, float temperature,
+           const float *grad_q, int32_t ckpt_every, float tol, int32_t check_every, double t_arrival,
+           uint64_t req_id) {
     if (!s) return set_error(LBP_E_INVALID, "server is NULL");
     std::string why;
     if (!valid_params(iters, damping, temperature, &why)) return set_error(LBP_E_INVALID, why);
@@ -721,6 +789,11 @@ int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, 
         r->T = temperature;
         r->backward = grad_q != nullptr;
         r->t_arrival = t_arrival >= 0.0 ? t_arrival : s->clock();
+        if (tol >= 0.0f) {
+            r->tol = tol;
+            r->check = check_every;
+            r->residual = 0.0f;
+        }
         if (r->backward) {
             if (!(temperature > 0.0f)) return set_error(LBP_E_INVALID, "backward requests need temperature > 0");
             if (ckpt_every < 1) return set_error(LBP_E_INVALID, "ckpt_every must be >= 1");
@@ -745,6 +818,22 @@ int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, 
     } catch (const std::bad_alloc &) {
         return set_error(LBP_E_OOM, "host allocation failed");
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbp_server_submit(lbp_server *s, const lbp_graph_desc *desc, int32_t iters, float damping, float temperature,
+                      const float *grad_q, int32_t ckpt_every, double t_arrival, uint64_t req_id) {
+    return submit(s, desc, iters, damping, temperature, grad_q, ckpt_every, -1.0f, 0, t_arrival, req_id);
+}
+
+int lbp_server_submit_until(lbp_server *s, const lbp_graph_desc *desc, int32_t max_iters, float damping,
+                            float temperature, float tol, int32_t check_every, double t_arrival, uint64_t req_id) {
+    if (!(tol >= 0.0f) || !std::isfinite(tol)) return set_error(LBP_E_INVALID, "tol must be finite and >= 0");
+    if (check_every < 1) return set_error(LBP_E_INVALID, "check_every must be >= 1");
+    return submit(s, desc, max_iters, damping, temperature, nullptr, 10, tol, check_every, t_arrival, req_id);
 }
 
 int lbp_server_cancel(lbp_server *s, uint64_t req_id) {
@@ -782,6 +871,8 @@ int lbp_server_poll(lbp_server *s, lbp_completion *out, int32_t max, int32_t *n_
         c.t_ready = r->t_ready;
         c.t_admit = r->t_admit;
         c.t_done = r->t_done;
+        c.iters_done = r->done;
+        c.residual = r->residual;
         s->handed_out.push_back(r);
     }
     *n_out = n;

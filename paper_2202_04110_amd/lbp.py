@@ -93,12 +93,12 @@ _sig("lbp_sampler_free", None, [_P])
 
 
 class Completion(C.Structure):
-    _fields_ = [("req_id", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("req_id", C.c_uint64), ("status", C.c_int32), ("iters_done", C.c_int32),
                 ("num_vars", C.c_int64), ("num_var_states", C.c_int64), ("num_logpots", C.c_int64),
                 ("beliefs", C.POINTER(C.c_float)), ("map", C.POINTER(C.c_int32)),
                 ("grad_logpot", C.POINTER(C.c_float)),
                 ("t_arrival", C.c_double), ("t_ready", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double)]
+                ("t_done", C.c_double), ("residual", C.c_float), ("reserved", C.c_int32)]
 
 
 _sig("lbp_server_create", C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(_P)])
@@ -106,6 +106,8 @@ _sig("lbp_server_create_host_only", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C
 _sig("lbp_server_clock", C.c_double, [_P])
 _sig("lbp_server_submit", C.c_int, [_P, C.POINTER(GraphDesc), C.c_int32, C.c_float, C.c_float, _P, C.c_int32,
                                     C.c_double, C.c_uint64])
+_sig("lbp_server_submit_until", C.c_int, [_P, C.POINTER(GraphDesc), C.c_int32, C.c_float, C.c_float, C.c_float,
+                                          C.c_int32, C.c_double, C.c_uint64])
 _sig("lbp_server_cancel", C.c_int, [_P, C.c_uint64])
 _sig("lbp_server_poll", C.c_int, [_P, C.POINTER(Completion), C.c_int32, C.POINTER(C.c_int32)])
 _sig("lbp_server_drain", C.c_int, [_P, C.c_double])
@@ -452,8 +454,17 @@ class Server:
         return float(_lib.lbp_server_clock(self.h))
 
     def submit(self, spec, iters: int, damping: float, temperature: float, grad_q=None, ckpt_every: int = 10,
-               t_arrival: float = -1.0, req_id: int = 0):
+               t_arrival: float = -1.0, req_id: int = 0, tol=None, check_every: int = 10):
+        """tol (not None): the request stops once the residual measured every
+        check_every of its iterations is below tol (lbp_server_submit_until;
+        forward only), with at most `iters` iterations."""
         d, keep = make_desc(spec)
+        if tol is not None:
+            if grad_q is not None:
+                raise ValueError("a request with tol cannot carry a gradient")
+            check(_lib.lbp_server_submit_until(self.h, C.byref(d), int(iters), float(damping), float(temperature),
+                                               float(tol), int(check_every), float(t_arrival), int(req_id)))
+            return
         gq = None if grad_q is None else np.ascontiguousarray(grad_q, np.float32)
         check(_lib.lbp_server_submit(self.h, C.byref(d), int(iters), float(damping), float(temperature),
                                      _ptr(gq), int(ckpt_every), float(t_arrival), int(req_id)))
@@ -469,8 +480,9 @@ class Server:
         out = []
         for i in range(n.value):
             c = buf[i]
-            rec = {"req_id": int(c.req_id), "status": int(c.status), "t_arrival": c.t_arrival,
-                   "t_ready": c.t_ready, "t_admit": c.t_admit, "t_done": c.t_done, "beliefs": None, "map": None, "grad_logpot": None}
+            rec = {"req_id": int(c.req_id), "status": int(c.status), "iters": int(c.iters_done),
+                   "residual": float(c.residual), "t_arrival": c.t_arrival, "t_ready": c.t_ready,
+                   "t_admit": c.t_admit, "t_done": c.t_done, "beliefs": None, "map": None, "grad_logpot": None}
             if c.beliefs:
                 rec["beliefs"] = np.ctypeslib.as_array(c.beliefs, (c.num_var_states,)).copy()
                 rec["map"] = np.ctypeslib.as_array(c.map, (c.num_vars,)).copy()

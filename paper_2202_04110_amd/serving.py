@@ -11,12 +11,15 @@ import numpy as np
 
 
 def run_stream(server, specs, arrivals, iters: int, damping: float, temperature: float, grad_qs=None,
-               ckpt_every: int = 10, timeout: float = 900.0, start_delay: float = 0.05, clients: int = 4):
+               ckpt_every: int = 10, timeout: float = 900.0, start_delay: float = 0.05, clients: int = 4,
+               tol=None, check_every: int = 5):
     """Submits request i (graph specs[i]) at server-clock time
     start + arrivals[i] seconds, with its latency measured from that scheduled
     time; ``clients`` threads perform the submissions (each copies its
     request's arrays into the server).  grad_qs[i] (or None) asks for the
-    log-potential gradient.  Returns (results by request id, summary)."""
+    log-potential gradient.  tol (not None): requests without a gradient stop
+    once their residual, checked every check_every iterations, is below tol
+    (at most ``iters``).  Returns (results by request id, summary)."""
     n = len(specs)
     order = np.argsort(arrivals, kind="stable")
     t_start = server.clock() + start_delay
@@ -37,8 +40,9 @@ def run_stream(server, specs, arrivals, iters: int, damping: float, temperature:
             collect()
             time.sleep(min(0.002, due - now))
         gq = None if grad_qs is None else grad_qs[i]
+        t = tol if gq is None else None
         futures.append(pool.submit(server.submit, specs[i], iters, damping, temperature, gq, ckpt_every, due,
-                                   int(i)))
+                                   int(i), t, check_every))
     for f in futures:
         f.result()
     pool.shutdown()
@@ -53,12 +57,13 @@ def run_stream(server, specs, arrivals, iters: int, damping: float, temperature:
     ok = [r for r in results.values() if r["status"] == 0]
     lat = np.array([r["t_done"] - r["t_arrival"] for r in ok]) if ok else np.zeros(0)
     makespan = (max(r["t_done"] for r in ok) - t_start) if ok else 0.0
-    es_total = sum(int(specs[r["req_id"]].num_edge_states) for r in ok) * iters
+    es_total = sum(int(specs[r["req_id"]].num_edge_states) * r["iters"] for r in ok)
     def p50(xs):
         return float(np.percentile(np.array(xs), 50)) if xs else None
 
     summary = {
         "requests": n, "ok": len(ok),
+        "iters_mean": float(np.mean([r["iters"] for r in ok])) if ok else None,
         "prep_p50_s": p50([r["t_ready"] - r["t_arrival"] for r in ok]),
         "admit_wait_p50_s": p50([r["t_admit"] - r["t_ready"] for r in ok]),
         "service_p50_s": p50([r["t_done"] - r["t_admit"] for r in ok]),

@@ -95,3 +95,49 @@ def test_cancel_resident_request(lbp, ctx):
     srv.close()
     assert res[1]["status"] == lbp.LBP_E_STATE
     assert res[2]["status"] == 0
+
+
+def test_early_exit_requests_equal_lone_run_until(lbp, ctx):
+    """Requests with a tolerance (lbp_server_submit_until) served together
+    with fixed-iteration requests: each stops at the same iteration, with
+    bitwise the same residual, beliefs and MAP, as lbp_run_bp_until on the
+    graph alone; some settle early, some run to max_iters, check intervals
+    differ from the round length; fixed requests are unaffected."""
+    import time
+    cases = [(W.potts_grid(24, 3, 11), 1.0, 200, 1e-3, 7), (W.potts_grid(40, 5, 12), 1.0, 200, 1e-4, 10),
+             (W.ising_grid(16, 13), 0.0, 60, 1e-3, 4), (W.potts_grid(30, 4, 14), 0.5, 9, 1e-6, 5),
+             (W.random_pairwise(15, 400, 1200, 3), 1.0, 150, 1e-3, 3),
+             (W.deconv(seed=4, K=2, tw=4, sd=10, img=12), 0.0, 80, 1e-3, 10)]
+    plain = [(W.potts_grid(36, 4, 16), 1.0, 50), (W.potts_grid(20, 6, 17), 0.0, 30)]
+    srv = lbp.Server(ctx, budget_bytes=64 << 20, max_slots=4, steps_per_round=5)
+    for i, (spec, T, it, tol, ce) in enumerate(cases):
+        srv.submit(spec, it, 0.5, T, req_id=i, tol=tol, check_every=ce)
+        if i < len(plain):
+            ps, pT, pit = plain[i]
+            srv.submit(ps, pit, 0.5, pT, req_id=100 + i)
+        time.sleep(0.002)
+    srv.drain(120)
+    recs = {r["req_id"]: r for r in srv.poll(64)}
+    srv.close()
+    assert len(recs) == len(cases) + len(plain) and all(r["status"] == 0 for r in recs.values())
+    early = 0
+    for i, (spec, T, it, tol, ce) in enumerate(cases):
+        g = lbp.Graph(ctx, spec)
+        done, res = g.run_bp_until(it, 0.5, T, tol, ce)
+        q, mp = g.get_beliefs(), g.decode_map()
+        g.free()
+        r = recs[i]
+        print("case %d: lone %d iterations residual %.3e, served %d residual %.3e"
+              % (i, done, res, r["iters"], r["residual"]))
+        assert r["iters"] == done
+        assert np.float32(r["residual"]) == np.float32(res)
+        np.testing.assert_array_equal(r["beliefs"], q)
+        np.testing.assert_array_equal(r["map"], mp)
+        early += done < it
+    assert early >= 3  # most of these settle before max_iters
+    for i, (ps, pT, pit) in enumerate(plain):
+        q, mp, _ = lone(lbp, ctx, ps, pit, 0.5, pT)
+        r = recs[100 + i]
+        assert r["iters"] == pit and r["residual"] == -1.0
+        np.testing.assert_array_equal(r["beliefs"], q)
+        np.testing.assert_array_equal(r["map"], mp)

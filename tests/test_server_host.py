@@ -139,3 +139,40 @@ def test_stream_driver_host_only(lbp):
     res, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, timeout=30)
     srv.close()
     assert summ["ok"] == 24 and summ["p99_s"] >= summ["p50_s"] >= 0
+
+
+def test_early_exit_requests_host_only(lbp):
+    """Requests with a tolerance (lbp_server_submit_until) on the bookkeeping
+    executor, whose messages stay zero and so measure a residual of 0 at
+    every check: with tol > 0 they leave at their first check point (after
+    check_every iterations, or max_iters if fewer), with tol = 0 (0 < 0 is
+    false) they run to max_iters; plain requests report every iteration and
+    residual -1.  Rounds stop at each request's own check points, so
+    iters_done is exactly the check point, not a multiple of the round."""
+    srv = lbp.Server(budget_bytes=64 << 20, max_slots=8, steps_per_round=4, host_only=True)
+    spec = W.potts_grid(12, 3, seed=1)
+    cases = {1: (50, 1e-3, 7), 2: (5, 1e-3, 7), 3: (30, 0.0, 7), 4: (26, 1e-3, 1), 5: (40, None, 10)}
+    for rid, (iters, tol, ce) in cases.items():
+        srv.submit(spec, iters, 0.5, 1.0, req_id=rid, tol=tol, check_every=ce)
+    srv.drain(30)
+    recs = {r["req_id"]: r for r in srv.poll()}
+    srv.close()
+    assert all(r["status"] == 0 for r in recs.values())
+    assert recs[1]["iters"] == 7 and recs[1]["residual"] == 0.0
+    assert recs[2]["iters"] == 5
+    assert recs[3]["iters"] == 30 and recs[3]["residual"] == 0.0
+    assert recs[4]["iters"] == 1
+    assert recs[5]["iters"] == 40 and recs[5]["residual"] == -1.0
+
+
+def test_early_exit_argument_errors(lbp):
+    srv = lbp.Server(budget_bytes=8 << 20, max_slots=2, host_only=True)
+    spec = W.potts_grid(8, 2, seed=3)
+    for tol, ce in ((-1.0, 5), (float("nan"), 5), (float("inf"), 5), (1e-3, 0)):
+        with pytest.raises(lbp.LBPError) as ei:
+            srv.submit(spec, 10, 0.5, 1.0, tol=tol, check_every=ce)
+        assert ei.value.code == lbp.LBP_E_INVALID
+    with pytest.raises(ValueError):
+        srv.submit(spec, 10, 0.5, 1.0, grad_q=np.zeros(spec.num_var_states, np.float32), tol=1e-3)
+    assert srv.stats()["accepted"] == 0
+    srv.close()
