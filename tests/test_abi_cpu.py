@@ -145,7 +145,9 @@ def test_null_handles_are_rejected(lbp):
                L.lbp_graph_num_launches(None, C.byref(n)),
                L.lbp_graph_use_fused(None, 1),
                L.lbp_reset_messages(None),
-               L.lbp_run_bp_record(None, 5, 0.5, 1.0, 2)):
+               L.lbp_run_bp_record(None, 5, 0.5, 1.0, 2),
+               L.lbp_graph_set_fused_launch(None, 0, 4, 2),
+               L.lbp_server_submit_until(None, None, 10, 0.5, 1.0, 1e-3, 5, -1.0, 1)):
         assert rc == lbp.LBP_E_INVALID
     assert out.value == 777 and n.value == 5 and f.value == 2.5
     L.lbp_sampler_free(None)
