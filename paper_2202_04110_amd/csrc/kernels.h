@@ -65,6 +65,20 @@ hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStr
 // residual_blocks(E) floats.
 int residual_blocks(int E);
 hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float *partial, float *out, hipStream_t st);
+// One graph's convergence check inside a multi-graph launch: g is the
+// device copy of its descriptor, mprev (M floats, M a multiple of 4, 16-byte
+// aligned) receives its messages before the checked iteration, partial holds
+// residual_blocks(E) floats, and the residual goes to out[slot].
+struct ConvJob {
+    const DevGraph *g;
+    float *mprev;
+    float *partial;
+    int32_t E, M, slot, pad;
+};
+// mprev = messages for every job (max_M: the largest M); then, after the
+// iteration, out[slot] = residual for every job (max_E: the largest E).
+hipError_t launch_save_multi(const ConvJob *jobs, int n, int max_M, hipStream_t st);
+hipError_t launch_residual_multi(const ConvJob *jobs, int n, int max_E, float *out, hipStream_t st);
 // Sample s (0 <= s < S) of views: evidence = base panel + noise[s * VS + ...].
 hipError_t launch_evidence_perturb(const DevGraph *views, int S, int V, const float *base, const float *noise,
                                   int64_t VS, hipStream_t st);

@@ -1296,11 +1296,14 @@ __global__ void k_evidence_in(const DevGraph *__restrict__ gs, const float *__re
 // entries (flat mapping; padding lanes excluded), per block, NaN and
 // infinity as infinity; then one block takes the maximum of the block
 // results.  Maxima do not depend on the order of reduction.
-__global__ __launch_bounds__(256) void k_residual(const DevGraph *__restrict__ gs, const float *__restrict__ mprev,
-                                                  float *__restrict__ partial) {
-    __shared__ float red[256];
-    const DevGraph &G = gs[0];
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kResidualThreads = 256;
+__host__ __device__ inline int residual_block_count(int E) {
+    return ((E > 1 ? E : 1) + kResidualThreads - 1) / kResidualThreads;
+}
+
+__device__ __forceinline__ void residual_partial(const DevGraph &G, const float *__restrict__ mprev,
+                                                 float *__restrict__ partial, int block, float (&red)[256]) {
+    const int e = block * kResidualThreads + (int)threadIdx.x;
     float r = 0.0f;
     if (e < G.E) {
         const int a = G.edge_maddr[e];
@@ -1316,11 +1319,11 @@ __global__ __launch_bounds__(256) void k_residual(const DevGraph *__restrict__ g
         if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partial[block] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_max_final(const float *__restrict__ partial, int n, float *__restrict__ out) {
-    __shared__ float red[256];
+__device__ __forceinline__ void max_final(const float *__restrict__ partial, int n, float *__restrict__ out,
+                                          float (&red)[256]) {
     float r = 0.0f;
     for (int i = threadIdx.x; i < n; i += 256) r = fmaxf(r, partial[i]);
     red[threadIdx.x] = r;
@@ -1330,6 +1333,41 @@ __global__ __launch_bounds__(256) void k_max_final(const float *__restrict__ par
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_residual(const DevGraph *__restrict__ gs, const float *__restrict__ mprev,
+                                                  float *__restrict__ partial) {
+    __shared__ float red[256];
+    residual_partial(gs[0], mprev, partial, (int)blockIdx.x, red);
+}
+
+__global__ __launch_bounds__(256) void k_max_final(const float *__restrict__ partial, int n, float *__restrict__ out) {
+    __shared__ float red[256];
+    max_final(partial, n, out, red);
+}
+
+// The same checks for several graphs at once (one per blockIdx.y, resp.
+// blockIdx.x): the copy of the messages taken before an iteration, then the
+// residual of that iteration into out[slot].
+__global__ __launch_bounds__(256) void k_save_multi(const ConvJob *__restrict__ jobs) {
+    const ConvJob J = jobs[blockIdx.y];
+    const float4 *src = reinterpret_cast<const float4 *>(J.g->m);
+    float4 *dst = reinterpret_cast<float4 *>(J.mprev);
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < J.M / 4; i += (int)(gridDim.x * blockDim.x))
+        dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_residual_multi(const ConvJob *__restrict__ jobs) {
+    __shared__ float red[256];
+    const ConvJob J = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= residual_block_count(J.E)) return;  // uniform over the block
+    residual_partial(*J.g, J.mprev, J.partial, (int)blockIdx.x, red);
+}
+
+__global__ __launch_bounds__(256) void k_max_final_multi(const ConvJob *__restrict__ jobs, float *__restrict__ out) {
+    __shared__ float red[256];
+    const ConvJob J = jobs[blockIdx.x];
+    max_final(J.partial, residual_block_count(J.E), out + J.slot, red);
 }
 
 // Evidence panel of sample blockIdx.y = base panel + that sample's noise
@@ -1491,12 +1529,26 @@ hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStr
     return hipGetLastError();
 }
 
-int residual_blocks(int E) { return blocks_for(std::max(E, 1), 256); }
+int residual_blocks(int E) { return residual_block_count(E); }
 
 hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float *partial, float *out, hipStream_t st) {
     const int nb = residual_blocks(E);
     hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, st, gs, mprev, partial);
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, partial, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_save_multi(const ConvJob *jobs, int n, int max_M, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned bx = std::min<unsigned>(blocks_for(std::max(max_M / 4, 1), 256), 1024);
+    hipLaunchKernelGGL(k_save_multi, dim3(bx, n), dim3(256), 0, st, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_multi(const ConvJob *jobs, int n, int max_E, float *out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residual_multi, dim3(residual_block_count(max_E), n), dim3(256), 0, st, jobs);
+    hipLaunchKernelGGL(k_max_final_multi, dim3(n), dim3(256), 0, st, jobs, out);
     return hipGetLastError();
 }
 

@@ -183,6 +183,8 @@ public:
         for (auto &kv : pool_)
             for (void *p : kv.second) (void)hipHostFree(p);
         if (res_host_) (void)hipHostFree(res_host_);
+        if (jobs_host_) (void)hipHostFree(jobs_host_);
+        if (jobs_dev_) (void)hipFree(jobs_dev_);
         if (ev_) (void)hipEventDestroy(ev_);
         if (compute_) (void)hipStreamDestroy(compute_);
         if (copy_) (void)hipStreamDestroy(copy_);
@@ -195,12 +197,16 @@ public:
         HIP_TRY(hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking));
         HIP_TRY(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
-        // one residual per resident request, read back after each round
-        if (hipHostMalloc((void **)&res_host_, sizeof(float) * (size_t)max_slots) != hipSuccess) {
+        // convergence checks: one job and one residual per resident request,
+        // staged in pinned memory and read back after each round
+        const size_t jb = align256(sizeof(ConvJob) * (size_t)max_slots);
+        if (hipHostMalloc((void **)&res_host_, sizeof(float) * (size_t)max_slots) != hipSuccess ||
+            hipHostMalloc((void **)&jobs_host_, sizeof(ConvJob) * (size_t)max_slots) != hipSuccess ||
+            hipMalloc((void **)&jobs_dev_, jb + sizeof(float) * (size_t)max_slots) != hipSuccess) {
             (void)hipGetLastError();
-            res_host_ = nullptr;
-            return set_error(LBP_E_OOM, "pinned residual buffer");
+            return set_error(LBP_E_OOM, "convergence-check buffers");
         }
+        res_dev_ = (float *)((char *)jobs_dev_ + jb);
         ctx_.stream = compute_;
         hipError_t e = hipMalloc((void **)&base_, std::max<size_t>(budget, 256));
         if (e != hipSuccess) {
@@ -248,29 +254,39 @@ public:
                 int rc = adjoint_checkpoint(r->g, r->done / r->g->adj.k, compute_);
                 if (rc != LBP_OK) return rc;
             }
-        for (size_t i = 0; i < active.size(); ++i) active[i]->res_slot = (int32_t)i;
-        for (const Part &p : parts_) {
-            const TParams P = make_params(p.d, p.T);
-            for (int32_t it = 0; it < steps; ++it) {
-                // requests at a check point keep their messages from before
-                // the round's last iteration
-                if (it == steps - 1)
-                    for (Request *r : p.reqs)
-                        if (r->check_now)
-                            HIP_TRY(hipMemcpyAsync(r->conv, r->g->host.m, sizeof(float) * r->g->M,
-                                                   hipMemcpyDeviceToDevice, compute_));
-                hipError_t e = launch_iteration(p.dgs, p.vl, p.fl, P, p.T == 0.0f, compute_);
+        // requests at a check point: one job each (all checked in shared
+        // launches), slot = position in the active list
+        int nj = 0, max_m = 0, max_e = 0;
+        for (size_t i = 0; i < active.size(); ++i) {
+            Request *r = active[i];
+            r->res_slot = (int32_t)i;
+            if (!r->check_now) continue;
+            ConvJob &J = jobs_host_[nj++];
+            J.g = r->g->dgraph;
+            J.mprev = (float *)r->conv;
+            J.partial = (float *)(r->conv + align256(sizeof(float) * std::max<int64_t>(1, r->g->M)));
+            J.E = (int32_t)r->g->E;
+            J.M = (int32_t)r->g->M;
+            J.slot = (int32_t)i;
+            J.pad = 0;
+            max_m = std::max(max_m, J.M);
+            max_e = std::max(max_e, J.E);
+        }
+        if (nj > 0)
+            HIP_TRY(hipMemcpyAsync(jobs_dev_, jobs_host_, sizeof(ConvJob) * nj, hipMemcpyHostToDevice, compute_));
+        // every part's iterations but the last, the copies of the checked
+        // requests' messages, then every part's last iteration
+        for (int32_t it = 0; it < steps; ++it) {
+            if (it == steps - 1) HIP_TRY(launch_save_multi(jobs_dev_, nj, max_m, compute_));
+            for (const Part &p : parts_) {
+                hipError_t e = launch_iteration(p.dgs, p.vl, p.fl, make_params(p.d, p.T), p.T == 0.0f, compute_);
                 if (e != hipSuccess) return hip_error(e, "served iteration launch");
             }
-            for (Request *r : p.reqs)
-                if (r->check_now) {
-                    const float *mprev = (const float *)r->conv;
-                    float *partial = (float *)(r->conv + align256(sizeof(float) * std::max<int64_t>(1, r->g->M)));
-                    float *res = partial + residual_blocks((int)r->g->E);
-                    HIP_TRY(launch_residual(r->g->dgraph, (int)r->g->E, mprev, partial, res, compute_));
-                    HIP_TRY(hipMemcpyAsync(res_host_ + r->res_slot, res, sizeof(float), hipMemcpyDeviceToHost,
-                                           compute_));
-                }
+        }
+        if (nj > 0) {
+            HIP_TRY(launch_residual_multi(jobs_dev_, nj, max_e, res_dev_, compute_));
+            HIP_TRY(hipMemcpyAsync(res_host_, res_dev_, sizeof(float) * active.size(), hipMemcpyDeviceToHost,
+                                   compute_));
         }
         HIP_TRY(hipEventRecord(ev_, compute_));
         return LBP_OK;
@@ -362,7 +378,6 @@ private:
     // Active graphs sharing (damping, temperature) launch together.
     struct Part {
         float d, T;
-        std::vector<Request *> reqs;
         std::vector<DevGraph> hgs;
         LaunchLists ll;
         DevGraph *dgs = nullptr;
@@ -381,7 +396,6 @@ private:
                 p->d = r->d;
                 p->T = r->T;
             }
-            p->reqs.push_back(r);
             p->hgs.push_back(r->g->host);
         }
         size_t total = 0;
@@ -429,7 +443,10 @@ private:
     std::vector<Part> parts_;
     std::mutex pool_mu_;
     std::map<size_t, std::vector<void *>> pool_;
-    float *res_host_ = nullptr;
+    float *res_host_ = nullptr;   // pinned, one residual per active slot
+    ConvJob *jobs_host_ = nullptr; // pinned staging of the round's checks
+    ConvJob *jobs_dev_ = nullptr;  // device copy, followed by res_dev_
+    float *res_dev_ = nullptr;
 };
 
 }  // namespace
