@@ -41,6 +41,9 @@ WORKLOADS = {
     "rbm": (lambda W: W.rbm(784, 500, seed=3), 200, 0.5, 0.0,
             "RBM 784 visible x 500 hidden, all 392000 pairwise factors, max-product, damping 0.5, "
             "200 iterations, FP32"),
+    "rbm_t005": (lambda W: W.rbm(784, 500, seed=3), 200, 0.5, 0.05,
+                 "RBM 784 visible x 500 hidden, all 392000 pairwise factors, sum-product at T=0.05, "
+                 "damping 0.5, 200 iterations, FP32"),
     "triplet256": (lambda W: W.triplet_grid(256, 3, seed=12), 100, 0.5, 1.0,
                    "three-way factors on a 256x256 grid (every three consecutive variables along rows and "
                    "columns), 3 states, dense 27-entry tables, sum-product T=1, damping 0.5, 100 iterations, FP32"),

@@ -200,41 +200,9 @@ __device__ __forceinline__ void belief_low_tile(const DevGraph &G, int t, int la
         if (s < n) G.B[base + s * kLanes] = acc[s];
 }
 
-// The belief of variable v (a lane-path variable with n states) in
-// registers: the same additions in the same order as belief_low_tile.
-template <int N>
-__device__ __forceinline__ void belief_regs(const DevGraph &G, int v, int n, float (&b)[N]) {
-    constexpr int KU = N <= 4 ? 8 : 4;
-#pragma unroll
-    for (int s = 0; s < N; ++s) b[s] = 0.0f;
-    if (v < 0) return;
-    const VTile vt = G.vtile[v >> 6];
-    const int l = v & (kLanes - 1);
-    const int base = vt.b_off + l;
-#pragma unroll
-    for (int s = 0; s < N; ++s)
-        if (s < n) b[s] = G.theta[base + s * kLanes];
-    const int32_t *ea = G.vedge + vt.e_off + l;
-    for (int k0 = 0; k0 < vt.kmax; k0 += KU) {
-        int a[KU];
-#pragma unroll
-        for (int u = 0; u < KU; ++u) a[u] = (k0 + u < vt.kmax) ? ea[(k0 + u) * kLanes] : -1;
-        float x[KU][N];
-#pragma unroll
-        for (int u = 0; u < KU; ++u)
-#pragma unroll
-            for (int s = 0; s < N; ++s) x[u][s] = (a[u] >= 0 && s < n) ? G.m[a[u] + s * kLanes] : 0.0f;
-#pragma unroll
-        for (int u = 0; u < KU; ++u)
-#pragma unroll
-            for (int s = 0; s < N; ++s)
-                if (a[u] >= 0 && s < n) b[s] += x[u][s];
-    }
-}
-
 // The beliefs of two lane-path variables at once (va with na states, vb with
-// nb), each with belief_regs' additions in its order; both gathers are in
-// flight together.
+// nb) in registers, each with belief_low_tile's additions in its order (theta
+// first, then the edges in order); both gathers are in flight together.
 template <int NA, int NB>
 __device__ __forceinline__ void belief_regs2(const DevGraph &G, int va, int na, int vb, int nb, float (&ba)[NA],
                                              float (&bb)[NB]) {
