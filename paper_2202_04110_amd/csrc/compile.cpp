@@ -607,6 +607,8 @@ int check_layout(const HostLayout &L, std::string *err) {
     const int64_t M = L.M, VB = L.VB, P = L.P;
     auto oob = [&](const std::string &what) { return bad(err, "layout check: " + what); };
     auto in = [](int64_t a, int64_t n) { return a >= 0 && a < n; };
+    // rows a, a + 64, ..., a + 64 (k - 1) all inside [0, n): the ends suffice
+    auto rows_in = [](int64_t a, int64_t k, int64_t n) { return k <= 0 || (a >= 0 && a + (k - 1) * kLanes < n); };
     // variable phase, low-degree lanes
     for (const VGroup &vg : L.vgroups)
         for (int32_t t : vg.tiles) {
@@ -615,13 +617,11 @@ int check_layout(const HostLayout &L, std::string *err) {
             for (int32_t l = 0; l < kLanes; ++l) {
                 const int32_t n = L.vns[(size_t)t * kLanes + l];
                 if (n > vg.bucket || n > vt.n) return oob("lane states exceed bucket/panel");
-                for (int32_t s = 0; s < n; ++s)
-                    if (!in(vt.b_off + l + (int64_t)s * kLanes, VB)) return oob("belief-low B/theta");
+                if (!rows_in(vt.b_off + l, n, VB)) return oob("belief-low B/theta");
                 for (int32_t k = 0; k < vt.kmax; ++k) {
                     const int64_t ei = vt.e_off + (int64_t)k * kLanes + l;
                     if (!in(ei, (int64_t)L.vedge.size())) return oob("vedge index");
-                    for (int32_t s = 0; s < n; ++s)
-                        if (!in(L.vedge[ei] + (int64_t)s * kLanes, M)) return oob("belief-low message");
+                    if (!rows_in(L.vedge[ei], n, M)) return oob("belief-low message");
                 }
             }
         }
@@ -634,20 +634,16 @@ int check_layout(const HostLayout &L, std::string *err) {
     if (L.mids.size() + L.highs.size() != L.hvar.size()) return oob("variable path lists");
     for (const HVar &h : L.hvar) {
         if (h.e_begin < 0 || h.e_end < h.e_begin || h.e_end > (int64_t)L.hedge.size()) return oob("hedge range");
-        for (int32_t s = 0; s < h.n; ++s) {
-            if (!in(h.b_addr + (int64_t)s * kLanes, VB)) return oob("belief-high B/theta");
-            for (int32_t k = h.e_begin; k < h.e_end; ++k)
-                if (!in(L.hedge[k] + (int64_t)s * kLanes, M)) return oob("belief-high message");
-        }
+        if (!rows_in(h.b_addr, h.n, VB)) return oob("belief-high B/theta");
+        for (int32_t k = h.e_begin; k < h.e_end; ++k)
+            if (!rows_in(L.hedge[k], h.n, M)) return oob("belief-high message");
     }
     // factor phase
     auto vb_rows = [&](const FTile &ft, int32_t rows, const int32_t *row_n) -> bool {
         for (int32_t r = 0; r < rows; ++r)
             for (int32_t l = 0; l < kLanes; ++l) {
                 const int64_t i = ft.vb_off + (int64_t)r * kLanes + l;
-                if (!in(i, (int64_t)L.fvb.size())) return false;
-                for (int32_t s = 0; s < row_n[r]; ++s)
-                    if (!in(L.fvb[i] + (int64_t)s * kLanes, VB)) return false;
+                if (!in(i, (int64_t)L.fvb.size()) || !rows_in(L.fvb[i], row_n[r], VB)) return false;
             }
         return true;
     };

@@ -1,0 +1,178 @@
+// Host-only test of the layout check (check_layout): a compiled layout that
+// mixes every tile kind passes, and each single corruption of an address,
+// offset or table that a kernel would follow out of its array is rejected
+// with the matching message.  Built and run by tests/test_layout_check.py.
+#include <cstdio>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../paper_2202_04110_amd/csrc/compile.h"
+
+using namespace lbp;
+
+namespace {
+
+// A factor graph built factor by factor (dense tables, deterministic values).
+struct Builder {
+    std::vector<int32_t> ns, kind, evar, cfg, ncfg{0}, arity, states;
+    std::vector<int64_t> eoff{0}, coff{0}, lpoff{0};
+    std::vector<float> ev, lp;
+    lbp_graph_desc d{};
+
+    int var(int n) {
+        ns.push_back(n);
+        for (int s = 0; s < n; ++s) ev.push_back(0.1f * (float)((ns.size() * 3 + s) % 7) - 0.3f);
+        return (int)ns.size() - 1;
+    }
+    int table(int a) {  // a dense table of arity a
+        const int t = (int)arity.size();
+        if (t > 0) ncfg.push_back(0);
+        arity.push_back(a);
+        coff.push_back(0);
+        return t;
+    }
+    void enumf(const std::vector<int> &vs, int t) {
+        int64_t c = 1;
+        for (int v : vs) {
+            evar.push_back(v);
+            c *= ns[v];
+        }
+        kind.push_back(LBP_FACTOR_ENUM);
+        cfg.push_back(t);
+        eoff.push_back((int64_t)evar.size());
+        for (int64_t i = 0; i < c; ++i) lp.push_back(0.05f * (float)((i * 5 + vs[0]) % 11));
+        lpoff.push_back((int64_t)lp.size());
+    }
+    void logical(const std::vector<int> &vs, int k) {
+        for (int v : vs) evar.push_back(v);
+        kind.push_back(k);
+        cfg.push_back(-1);
+        eoff.push_back((int64_t)evar.size());
+        lpoff.push_back((int64_t)lp.size());
+    }
+    const lbp_graph_desc *desc() {
+        d = lbp_graph_desc{};
+        d.num_vars = (int32_t)ns.size();
+        d.var_num_states = ns.data();
+        d.evidence = ev.data();
+        d.num_factors = (int32_t)kind.size();
+        d.factor_kind = kind.data();
+        d.factor_edge_off = eoff.data();
+        d.edge_var = evar.data();
+        d.factor_cfg_table = cfg.data();
+        d.num_cfg_tables = (int32_t)arity.size();
+        d.cfg_table_num_cfgs = ncfg.data();
+        d.cfg_table_arity = arity.data();
+        d.cfg_table_off = coff.data();
+        d.cfg_table_states = states.data();
+        d.logpot_off = lpoff.data();
+        d.log_potentials = lp.data();
+        return &d;
+    }
+};
+
+int failures = 0;
+
+void expect(bool ok, const std::string &what) {
+    if (!ok) {
+        std::printf("FAIL: %s\n", what.c_str());
+        ++failures;
+    }
+}
+
+// Compiles `b`, checks the clean layout, then applies each corruption to a
+// fresh copy and expects check_layout to reject it with `msg` in the error.
+void run(const char *name, Builder &b,
+         const std::vector<std::pair<std::string, std::function<void(HostLayout &)>>> &cases) {
+    HostLayout L;
+    std::string err;
+    int rc = compile_desc(b.desc(), &L, &err);
+    expect(rc == LBP_OK, std::string(name) + ": compile: " + err);
+    if (rc != LBP_OK) return;
+    rc = check_layout(L, &err);
+    expect(rc == LBP_OK, std::string(name) + ": clean layout rejected: " + err);
+    for (const auto &c : cases) {
+        HostLayout bad = L;
+        c.second(bad);
+        std::string e;
+        const int r = check_layout(bad, &e);
+        expect(r != LBP_OK && e.find(c.first) != std::string::npos,
+               std::string(name) + ": corruption '" + c.first + "' gave rc " + std::to_string(r) + " '" + e + "'");
+    }
+    std::printf("%s: %zu corruptions rejected (M %lld, VB %lld, P %lld, fusable %d)\n", name, cases.size(),
+                (long long)L.M, (long long)L.VB, (long long)L.P, (int)L.fusable);
+}
+
+}  // namespace
+
+int main() {
+    // a 9 x 9 grid of 3-state variables: lane-path variables, dense pairwise
+    // tiles, fused iterations possible
+    Builder g;
+    const int Lg = 9;
+    for (int i = 0; i < Lg * Lg; ++i) g.var(3);
+    const int t2 = g.table(2);
+    for (int r = 0; r < Lg; ++r)
+        for (int c = 0; c + 1 < Lg; ++c) g.enumf({r * Lg + c, r * Lg + c + 1}, t2);
+    for (int r = 0; r + 1 < Lg; ++r)
+        for (int c = 0; c < Lg; ++c) g.enumf({r * Lg + c, (r + 1) * Lg + c}, t2);
+    run("grid", g,
+        {{"belief-low message", [](HostLayout &L) { L.vedge[3] = (int32_t)L.M; }},
+         {"belief-low message", [](HostLayout &L) { L.vedge[0] = -5; }},
+         {"vedge index", [](HostLayout &L) { L.vtile[0].e_off = (int32_t)L.vedge.size(); }},
+         {"belief-low B/theta", [](HostLayout &L) { L.vtile[1].b_off = (int32_t)L.VB - 1; }},
+         {"pair belief rows", [](HostLayout &L) { L.fvb[5] = (int32_t)L.VB - 64; }},
+         {"pair messages", [](HostLayout &L) { L.ftile[0].m_off = (int32_t)L.M - 64; }},
+         {"pair potentials", [](HostLayout &L) { L.ftile[0].phi_off = (int32_t)L.P - 64; }},
+         {"edge message address", [](HostLayout &L) { L.edge_maddr[7] = (int32_t)L.M - 1; }},
+         {"factor potential address", [](HostLayout &L) { L.fac_phi[2] = (int32_t)L.P; }},
+         {"fused slot variable", [](HostLayout &L) { L.fvar[1] = (int32_t)L.V; }},
+         {"fused slot states", [](HostLayout &L) { L.vns[L.fvar[0]] = 2; }},
+         {"zero panel", [](HostLayout &L) { L.zero_addr = (int32_t)L.M; }}});
+
+    // a hub joined to 40 and to 300 binary leaves (wavefront- and
+    // block-per-variable paths), an OR over 150 parents (wavefront logical
+    // tile), small ANDs (lane logical tiles) and dense three-way factors
+    // (generic class)
+    Builder h;
+    const int hub = h.var(2), hub2 = h.var(4);
+    const int tp = h.table(2), t3 = h.table(3);
+    std::vector<int> leaves;
+    for (int i = 0; i < 300; ++i) leaves.push_back(h.var(2));
+    for (int i = 0; i < 300; ++i) h.enumf({hub, leaves[i]}, tp);
+    for (int i = 0; i < 40; ++i) h.enumf({leaves[i], hub2}, tp);
+    std::vector<int> orv(leaves.begin() + 40, leaves.begin() + 190);
+    orv.push_back(h.var(2));
+    h.logical(orv, LBP_FACTOR_OR);
+    for (int i = 200; i + 2 < 230; i += 3) h.logical({leaves[i], leaves[i + 1], leaves[i + 2]}, LBP_FACTOR_AND);
+    const int a3 = h.var(3), b3 = h.var(3), c3 = h.var(3);
+    h.enumf({a3, b3, c3}, t3);
+    h.enumf({leaves[250], a3, c3}, t3);
+    run("hub", h,
+        {{"belief-high message", [](HostLayout &L) { L.hedge[L.hvar[L.highs[0]].e_begin] = (int32_t)L.M - 1; }},
+         {"belief-high B/theta", [](HostLayout &L) { L.hvar[L.highs[0]].b_addr = (int32_t)L.VB - 1; }},
+         {"hedge range", [](HostLayout &L) { L.hvar[0].e_end = (int32_t)L.hedge.size() + 1; }},
+         {"wavefront-per-variable entry", [](HostLayout &L) { L.mids[0] = (int32_t)L.hvar.size(); }},
+         {"wave logical", [](HostLayout &L) {
+              for (FTile &t : L.ftile)
+                  if (t.kind == TK_LOGW) t.m_off = (int32_t)L.M - 64;
+          }},
+         {"lane logical", [](HostLayout &L) {
+              for (FTile &t : L.ftile)
+                  if (t.kind == TK_LOGL) t.m_off = (int32_t)L.M - 64;
+          }},
+         {"generic", [](HostLayout &L) {
+              for (FTile &t : L.ftile)
+                  if (t.kind == TK_GEN) t.phi_off = (int32_t)L.P - 1;
+          }},
+         {"three-way table", [](HostLayout &L) { L.grows[L.gcls[0].rows_off] = 200; }},
+         {"read-out", [](HostLayout &L) { L.vn[0] = 9; }}});
+
+    if (failures) {
+        std::printf("%d failures\n", failures);
+        return 1;
+    }
+    std::printf("layout check ok\n");
+    return 0;
+}
