@@ -120,8 +120,10 @@ def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
     """Served stream: n Potts requests (side log-uniform 16..256, 2..8
     states, sum-product T=1, damping 0.5, 50 iterations; 10% carry a backward
     pass with checkpoints every 10), per HBM budget.  Capacity R is measured
-    with every request arriving at once; then Poisson arrivals at 0.5R, 0.8R
-    and 1.0R give p50/p99 latency (completion minus scheduled arrival).
+    with every request arriving at once (after one untimed burst that warms
+    the pinned result pool, as a long-running server's would be); then
+    Poisson arrivals at 0.5R, 0.8R and 1.0R give p50/p99 latency (completion
+    minus scheduled arrival).
     "burst, early exit": the burst again with the forward requests stopping
     once their residual (checked every 5 iterations) is below 1e-3."""
     from paper_2202_04110_amd.serving import run_stream
@@ -130,7 +132,11 @@ def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
     specs = [W.request_graph(r) for r in reqs]
     gqs = [W.request_loss_coeffs(r) if r["backward"] else None for r in reqs]
     out = {"requests": n, "iters": 50, "backward_requests": sum(g is not None for g in gqs),
-           "edge_states_mean": float(np.mean([s.num_edge_states for s in specs])), "budgets": {}}
+           "edge_states_mean": float(np.mean([s.num_edge_states for s in specs])), "budgets": {},
+           "warmup": "one untimed burst of the same requests first (fills the process-wide pinned result pool)"}
+    srv = lbp.Server(ctx, budget_bytes=budgets_mb[0] << 20, max_slots=64, steps_per_round=5)
+    run_stream(srv, specs, np.zeros(n), 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10)
+    srv.close()
     for budget_mb in budgets_mb:
         runs = {}
         for label, frac in (("burst", None), ("0.5R", 0.5), ("0.8R", 0.8), ("1.0R", 1.0),
@@ -144,7 +150,8 @@ def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
             _, summ = run_stream(srv, specs, arr, 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10, tol=tol, check_every=5)
             srv.close()
             st = summ.pop("stats")
-            for k in ("max_resident", "rounds", "busy_us", "round_us", "prep_us", "prep_threads"):
+            for k in ("max_resident", "rounds", "busy_us", "round_us", "prep_us", "prep_threads", "admit_us",
+                      "launch_us", "finish_us"):
                 summ[k] = st[k]
             runs[label] = summ
             print("serving budget %d MB %s: %.0f req/s p50 %.2f ms p99 %.2f ms, %.1f iterations per request" % (

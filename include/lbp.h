@@ -355,11 +355,13 @@ int lbp_server_cancel(lbp_server *s, uint64_t req_id);
 int lbp_server_poll(lbp_server *s, lbp_completion *out, int32_t max, int32_t *n_out);
 /* Waits until every accepted request has finished (LBP_E_STATE on timeout). */
 int lbp_server_drain(lbp_server *s, double timeout_s);
-/* out[15] = {accepted, finished, completed, rejected for the budget, failed,
+/* out[18] = {accepted, finished, completed, rejected for the budget, failed,
  * cancelled, rounds, resident now, queued now, max resident, arena peak bytes,
  * worker busy microseconds, of which in rounds (launch + wait), preparation
- * microseconds summed over the preparation threads, preparation threads}. */
-int lbp_server_stats(lbp_server *s, int64_t out[15]);
+ * microseconds summed over the preparation threads, preparation threads,
+ * worker microseconds in admissions, in enqueueing rounds (launch lists and
+ * kernels), in read-outs of finished requests}. */
+int lbp_server_stats(lbp_server *s, int64_t out[18]);
 /* Stops the worker (queued and resident requests are dropped) and frees
  * everything. */
 void lbp_server_destroy(lbp_server *s);

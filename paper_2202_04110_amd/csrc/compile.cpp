@@ -60,7 +60,7 @@ bool pair_fast(bool dense, int32_t arity, const int32_t *ns) {
 
 }  // namespace
 
-int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
+int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err, bool scan_potentials) {
     if (!d) return bad(err, "graph description is NULL");
     const int64_t V = d->num_vars, F = d->num_factors, NT = d->num_cfg_tables;
     if (V < 0 || F < 0 || NT < 0) return bad(err, "negative num_vars, num_factors or num_cfg_tables");
@@ -96,7 +96,7 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
         return bad(err, "logpot_off must start at 0 and be non-decreasing");
     const int64_t Tn = d->logpot_off[F];
     if (Tn > 0 && !d->log_potentials) return bad(err, "log_potentials is NULL");
-    {
+    if (scan_potentials) {
         const int64_t i = first_nonfinite(d->log_potentials, Tn);
         if (i >= 0) return bad(err, at("log_potentials", i) + " is not finite");
     }
@@ -203,7 +203,9 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err) {
 
 int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
     int64_t sz[6];
-    int rc = validate_desc(d, sz, err);
+    // the potentials are checked for NaN and infinity while they are copied
+    // into their panels (every one of them is), not in a pass of their own
+    int rc = validate_desc(d, sz, err, false);
     if (rc != LBP_OK) return rc;
     L->V = sz[0]; L->VS = sz[1]; L->F = sz[2]; L->E = sz[3]; L->ES = sz[4]; L->Tn = sz[5];
     const int64_t V = L->V, F = L->F, E = L->E;
@@ -336,12 +338,24 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
     // of their first variable (then by index): a tile's factors then touch
     // few variable tiles, which keeps belief reads local.  Tile membership
     // does not change any factor's arithmetic.
+    // (a stable counting sort on the block index when the class is large
+    // against the number of blocks, a comparison sort otherwise: same order)
+    const int64_t nblk = (V + kLanes - 1) / kLanes;
+    std::vector<int32_t> blk_start, sorted;
     for (size_t c = 0; c < class_key.size(); ++c) {
         if (std::get<0>(class_key[c]) == TK_LOGW) continue;
         std::vector<int32_t> &fl = class_facs[c];
-        std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) {
-            return d->edge_var[d->factor_edge_off[x]] / kLanes < d->edge_var[d->factor_edge_off[y]] / kLanes;
-        });
+        auto key = [&](int32_t f) { return d->edge_var[d->factor_edge_off[f]] / kLanes; };
+        if ((int64_t)fl.size() >= nblk / 4) {
+            blk_start.assign(nblk + 1, 0);
+            for (int32_t f : fl) ++blk_start[key(f) + 1];
+            for (int64_t b = 0; b < nblk; ++b) blk_start[b + 1] += blk_start[b];
+            sorted.resize(fl.size());
+            for (int32_t f : fl) sorted[blk_start[key(f)]++] = f;
+            fl.swap(sorted);
+        } else {
+            std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
+        }
     }
     for (size_t c = 0; c < class_key.size(); ++c) {
         const int32_t kind = std::get<0>(class_key[c]);
@@ -588,15 +602,34 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
     std::fill(L->theta_panel.begin() + b_zero, L->theta_panel.end(), 0.0f);
     L->phi_panel.resize(L->P);
     if (P == 0) std::fill(L->phi_panel.begin(), L->phi_panel.end(), 0.0f);
+    // each tile's panel is the transpose of its factors' tables: blocks of 16
+    // lanes, so every configuration row is written 64 bytes at a time
+    uint32_t nonfinite = 0;
     for (size_t t = 0; t < L->ftile.size(); ++t) {
         const FTile &ft = L->ftile[t];
         if (ft.kind != TK_PAIR && ft.kind != TK_GEN) continue;
         const int32_t ncfg = ft.kind == TK_PAIR ? ft.a * ft.b : L->gcls[ft.a].ncfg;
         const int32_t *lf = tile_fac.data() + t * kLanes;
-        float *row = L->phi_panel.data() + ft.phi_off;
-        for (int32_t c = 0; c < ncfg; ++c, row += kLanes)
-            for (int32_t l = 0; l < kLanes; ++l)
-                row[l] = lf[l] >= 0 ? d->log_potentials[L->lp_off[lf[l]] + c] : 0.0f;
+        float *panel = L->phi_panel.data() + ft.phi_off;
+        for (int32_t l0 = 0; l0 < kLanes; l0 += 16) {
+            const float *src[16];
+            for (int32_t l = 0; l < 16; ++l)
+                src[l] = lf[l0 + l] >= 0 ? d->log_potentials + L->lp_off[lf[l0 + l]] : nullptr;
+            for (int32_t c = 0; c < ncfg; ++c) {
+                float *row = panel + (int64_t)c * kLanes + l0;
+                for (int32_t l = 0; l < 16; ++l) {
+                    const float x = src[l] ? src[l][c] : 0.0f;
+                    uint32_t u;
+                    std::memcpy(&u, &x, sizeof u);
+                    nonfinite |= (uint32_t)((u & 0x7f800000u) == 0x7f800000u);
+                    row[l] = x;
+                }
+            }
+        }
+    }
+    if (nonfinite) {
+        const int64_t i = first_nonfinite(d->log_potentials, L->Tn);
+        return bad(err, at("log_potentials", i) + " is not finite");
     }
     return LBP_OK;
 }

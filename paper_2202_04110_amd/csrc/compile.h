@@ -88,7 +88,9 @@ struct HostLayout {
 };
 
 // Returns LBP_OK or an LBP_E_* code with a message in *err.
-int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err);
+// scan_potentials = false leaves the NaN/infinity check of the log-potentials
+// to the caller (compile_desc does it while filling the potential panels).
+int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err, bool scan_potentials = true);
 int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err);
 // Host replay of every kernel's addresses against the layout's array sizes.
 int check_layout(const HostLayout &L, std::string *err);

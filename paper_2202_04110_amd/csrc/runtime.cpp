@@ -293,7 +293,7 @@ void graph_fill_image(const HostLayout &L, char *image) {
 }
 
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
-                 const char *image) {
+                 const char *image, bool wait) {
     lbp_graph *g = nullptr;
     char *own_image = nullptr;  // built here when the caller brings none
     try {
@@ -314,6 +314,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         g->dbytes = gp.total;
         auto ptr = [&](size_t i) { return (void *)(g->dmem + gp.p[i].off); };
         if (!image) {
+            wait = true;  // the image built here is freed before returning
             own_image = (char *)panel_alloc(gp.data_end);
             if (!own_image) throw std::bad_alloc();
             graph_fill_image(L, own_image);
@@ -366,8 +367,9 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
             if (e == hipSuccess) e = hipMemcpyAsync(g->fused, fv, sizeof(fv), hipMemcpyHostToDevice, st);
         }
         describe_lists(gp.ll, (char *)ptr(gp.items), &g->vl, &g->fl);
-        // the host image and the descriptors must outlive the copies
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        // the host image and the descriptors must outlive the copies (the
+        // descriptors live in g; without wait, the caller keeps the image)
+        if (e == hipSuccess && (wait || gp.fused)) e = hipStreamSynchronize(st);
         panel_free(own_image);
         own_image = nullptr;
         if (e != hipSuccess) {

@@ -104,6 +104,7 @@ struct Request {
     float residual = -1.0f;   // last residual measured (0 before the first check)
     size_t conv_bytes = 0;    // previous messages, partial maxima, residual
     char *conv = nullptr;
+    uint64_t up_gen = 0;      // upload number (executor's count) while its upload may be in flight
     std::vector<float> grad_q;
     HostLayout L;
     size_t bytes = 0, graph_bytes = 0, adj_bytes = 0;
@@ -134,10 +135,16 @@ public:
     virtual int admit(Request &r) = 0;
     virtual int round(const std::vector<Request *> &active, int32_t steps) = 0;
     virtual int wait() = 0;
-    virtual int finish(Request &r) = 0;
+    // Read-out of finished requests: finish_begin for each (slot: its index
+    // in this batch, < max_slots), one finish_wait, then finish_end for each.
+    virtual int finish_begin(Request &r, int32_t slot) = 0;
+    virtual int finish_wait() = 0;
+    virtual int finish_end(Request &r, int32_t slot) = 0;
     // after wait(): the residual of every request with check_now
     virtual void residuals(const std::vector<Request *> &active) = 0;
     virtual void release(Request &r) = 0;
+    // after wait(): frees the upload images that are no longer needed
+    virtual void images_done(const std::vector<Request *> &) {}
     virtual int alloc_outputs(Request &r) = 0;
     virtual void free_outputs(Request &r) = 0;
     // whether prep threads should pack each request's upload image
@@ -149,7 +156,9 @@ public:
     int admit(Request &) override { return LBP_OK; }
     int round(const std::vector<Request *> &, int32_t) override { return LBP_OK; }
     int wait() override { return LBP_OK; }
-    int finish(Request &) override { return LBP_OK; }
+    int finish_begin(Request &, int32_t) override { return LBP_OK; }
+    int finish_wait() override { return LBP_OK; }
+    int finish_end(Request &, int32_t) override { return LBP_OK; }
     // the bookkeeping executor's messages stay zero, so they never change
     void residuals(const std::vector<Request *> &active) override {
         for (Request *r : active)
@@ -180,10 +189,10 @@ public:
         if (copy_) (void)hipStreamSynchronize(copy_);
         if (stage_) (void)hipFree(stage_);
         if (base_) (void)hipFree(base_);
-        for (auto &kv : pool_)
-            for (void *p : kv.second) (void)hipHostFree(p);
         if (res_host_) (void)hipHostFree(res_host_);
         if (jobs_host_) (void)hipHostFree(jobs_host_);
+        if (flags_host_) (void)hipHostFree(flags_host_);
+        if (up_ev_) (void)hipEventDestroy(up_ev_);
         if (jobs_dev_) (void)hipFree(jobs_dev_);
         if (ev_) (void)hipEventDestroy(ev_);
         if (compute_) (void)hipStreamDestroy(compute_);
@@ -197,6 +206,12 @@ public:
         HIP_TRY(hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking));
         HIP_TRY(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&up_ev_, hipEventDisableTiming));
+        if (hipHostMalloc((void **)&flags_host_, sizeof(int32_t) * (size_t)max_slots) != hipSuccess) {
+            (void)hipGetLastError();
+            flags_host_ = nullptr;
+            return set_error(LBP_E_OOM, "pinned read-out flags");
+        }
         // convergence checks: one job and one residual per resident request,
         // staged in pinned memory and read back after each round
         const size_t jb = align256(sizeof(ConvJob) * (size_t)max_slots);
@@ -222,11 +237,22 @@ public:
 
     bool wants_image() const override { return true; }
 
+    // Forward requests upload without waiting: the image stays with the
+    // request, the compute stream waits for the copy stream before the next
+    // round (or read-out) and the image is freed once that has completed.
+    // Backward requests (their adjoint buffers are prepared here) wait.
     int admit(Request &r) override {
         char *mem = base_ + r.off;
-        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get());
-        r.image.reset();  // uploaded (graph_create waits for its copies)
+        const bool async = !r.backward;
+        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get(), !async);
         if (rc != LBP_OK) return rc;
+        if (async) {
+            r.up_gen = ++up_gen_;
+            HIP_TRY(hipEventRecord(up_ev_, copy_));
+        } else {
+            up_done_ = up_gen_;  // the copy stream has drained
+            r.image.reset();
+        }
         r.g->last_T = r.T;
         if (r.tol >= 0.0f) r.conv = mem + Arena::round(r.graph_bytes);
         if (r.backward) {
@@ -242,6 +268,10 @@ public:
     }
 
     int round(const std::vector<Request *> &active, int32_t steps) override {
+        if (up_gen_ > up_done_) {
+            HIP_TRY(hipStreamWaitEvent(compute_, up_ev_, 0));
+            round_gen_ = up_gen_;
+        }
         std::vector<uint64_t> ids;
         for (Request *r : active) ids.push_back(r->id);
         if (ids != ids_) {
@@ -294,7 +324,13 @@ public:
 
     int wait() override {
         HIP_TRY(hipEventSynchronize(ev_));
+        up_done_ = std::max(up_done_, round_gen_);
         return LBP_OK;
+    }
+
+    // the image of a request whose upload is known to have completed
+    void drop_image(Request &r) {
+        if (r.image && r.up_gen <= up_done_) r.image.reset();
     }
 
     void residuals(const std::vector<Request *> &active) override {
@@ -302,7 +338,11 @@ public:
             if (r->check_now) r->residual = res_host_[r->res_slot];
     }
 
-    int finish(Request &r) override {
+    int finish_begin(Request &r, int32_t slot) override {
+        if (r.up_gen > up_done_) {  // not covered by a round yet (zero iterations)
+            HIP_TRY(hipStreamWaitEvent(compute_, up_ev_, 0));
+            round_gen_ = up_gen_;
+        }
         int rc = graph_readout(r.g, r.q, 1, r.map, false, compute_);
         if (rc != LBP_OK) return rc;
         if (r.backward) {
@@ -311,16 +351,39 @@ public:
             if (rc != LBP_OK) return rc;
             HIP_TRY(hipMemcpyAsync(r.gphi, r.gphi_dev, sizeof(float) * r.L.Tn, hipMemcpyDeviceToHost, compute_));
         }
-        int32_t flag = 0;
-        HIP_TRY(hipMemcpyAsync(&flag, r.g->host.flag, sizeof(int32_t), hipMemcpyDeviceToHost, compute_));
+        flags_host_[slot] = 0;
+        HIP_TRY(hipMemcpyAsync(flags_host_ + slot, r.g->host.flag, sizeof(int32_t), hipMemcpyDeviceToHost, compute_));
+        return LBP_OK;
+    }
+
+    int finish_wait() override {
         HIP_TRY(hipStreamSynchronize(compute_));
-        return flag ? set_error(LBP_E_NONFINITE, "beliefs contain NaN or infinity") : LBP_OK;
+        up_done_ = std::max(up_done_, round_gen_);
+        return LBP_OK;
+    }
+
+    int finish_end(Request &r, int32_t slot) override {
+        drop_image(r);
+        return flags_host_[slot] ? set_error(LBP_E_NONFINITE, "beliefs contain NaN or infinity") : LBP_OK;
     }
 
     void release(Request &r) override {
+        if (r.image) {
+            // an upload that no round or read-out has waited for yet: the
+            // arena memory and the image are reused only after it completes
+            if (r.up_gen > up_done_) {
+                (void)hipStreamSynchronize(copy_);
+                up_done_ = up_gen_;
+            }
+            r.image.reset();
+        }
         graph_destroy(r.g);  // the arena owns the memory
         r.g = nullptr;
         ids_.clear();        // the resident set changes
+    }
+
+    void images_done(const std::vector<Request *> &resident) override {
+        for (Request *r : resident) drop_image(*r);
     }
 
     int alloc_outputs(Request &r) override {
@@ -345,7 +408,20 @@ public:
     }
 
 private:
-    // Pinned host buffers, kept per power-of-two size class and reused.
+    // Pinned host buffers for results, per power-of-two size class, shared
+    // by every server of the process and reused (page-locking is slow, so a
+    // new server starts with the buffers earlier ones returned).  At most
+    // kIdleCap bytes wait idle; the pool lives until the process ends.
+    static constexpr size_t kIdleCap = size_t(512) << 20;
+    struct OutPool {
+        std::mutex mu;
+        std::map<size_t, std::vector<void *>> free_lists;
+        size_t idle = 0;
+    };
+    static OutPool &out_pool() {
+        static OutPool *p = new OutPool;
+        return *p;
+    }
     static size_t size_class(size_t bytes) {
         size_t c = 4096;
         while (c < bytes) c <<= 1;
@@ -353,12 +429,14 @@ private:
     }
     void *pinned_get(size_t bytes) {
         const size_t c = size_class(bytes);
+        OutPool &P = out_pool();
         {
-            std::lock_guard<std::mutex> lk(pool_mu_);
-            auto &v = pool_[c];
+            std::lock_guard<std::mutex> lk(P.mu);
+            auto &v = P.free_lists[c];
             if (!v.empty()) {
                 void *p = v.back();
                 v.pop_back();
+                P.idle -= c;
                 return p;
             }
         }
@@ -371,8 +449,17 @@ private:
     }
     void pinned_put(void *p, size_t bytes) {
         if (!p) return;
-        std::lock_guard<std::mutex> lk(pool_mu_);
-        pool_[size_class(bytes)].push_back(p);
+        const size_t c = size_class(bytes);
+        OutPool &P = out_pool();
+        {
+            std::lock_guard<std::mutex> lk(P.mu);
+            if (P.idle + c <= kIdleCap) {
+                P.free_lists[c].push_back(p);
+                P.idle += c;
+                return;
+            }
+        }
+        (void)hipHostFree(p);
     }
 
     // Active graphs sharing (damping, temperature) launch together.
@@ -441,9 +528,12 @@ private:
     size_t stage_bytes_ = 0;
     std::vector<uint64_t> ids_;
     std::vector<Part> parts_;
-    std::mutex pool_mu_;
-    std::map<size_t, std::vector<void *>> pool_;
     float *res_host_ = nullptr;   // pinned, one residual per active slot
+    int32_t *flags_host_ = nullptr;  // pinned, one read-out flag per finishing request
+    hipEvent_t up_ev_ = nullptr;     // recorded on the copy stream after each upload
+    uint64_t up_gen_ = 0;            // uploads issued
+    uint64_t up_done_ = 0;           // uploads known to have completed
+    uint64_t round_gen_ = 0;         // uploads the compute stream was last made to wait for
     ConvJob *jobs_host_ = nullptr; // pinned staging of the round's checks
     ConvJob *jobs_dev_ = nullptr;  // device copy, followed by res_dev_
     float *res_dev_ = nullptr;
@@ -479,6 +569,9 @@ struct lbp_server {
     double busy_s = 0.0;   // worker: rounds, admissions, read-outs
     double prep_s = 0.0;   // prep threads: compile and check, summed
     double round_s = 0.0;  // worker: launching rounds and waiting for them
+    double admit_s = 0.0;  // worker: admissions (arena, outputs, upload enqueue)
+    double launch_s = 0.0; // worker: enqueueing rounds (launch lists, kernels)
+    double finish_s = 0.0; // worker: read-outs of finished requests, with their wait
 
     double clock() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
@@ -557,6 +650,13 @@ struct lbp_server {
     }
 
     void admit() {
+        const double t0 = clock();
+        admit_loop();
+        std::lock_guard<std::mutex> lk(mu);
+        admit_s += clock() - t0;
+    }
+
+    void admit_loop() {
         while (!pending.empty() && (int32_t)resident.size() < max_slots) {
             Request *r = pending.front();
             int prep;
@@ -663,6 +763,10 @@ struct lbp_server {
             const double tr = clock();
             if (!active.empty()) {
                 int rc = exec->round(active, s);
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    launch_s += clock() - tr;
+                }
                 if (rc == LBP_OK) admit();  // uploads on the copy stream overlap the round
                 if (rc == LBP_OK) rc = exec->wait();
                 {
@@ -678,6 +782,7 @@ struct lbp_server {
                     continue;
                 }
                 exec->residuals(active);
+                exec->images_done(resident);
                 for (Request *r : active) {
                     r->done += s;
                     if (r->check_now && r->residual < r->tol) r->settled = true;
@@ -685,16 +790,25 @@ struct lbp_server {
                 std::lock_guard<std::mutex> lk(mu);
                 ++n_rounds;
             }
-            for (size_t i = 0; i < resident.size();) {
-                Request *r = resident[i];
-                if (r->done >= r->iters || r->settled) {
-                    int rc = exec->finish(*r);
+            // finished requests: all read-outs queued, one wait, then each
+            // leaves (its memory is reused only after the wait)
+            std::vector<Request *> fin;
+            for (Request *r : resident)
+                if (r->done >= r->iters || r->settled) fin.push_back(r);
+            if (!fin.empty()) {
+                const double tf = clock();
+                std::vector<int> rcs(fin.size(), LBP_OK);
+                for (size_t i = 0; i < fin.size(); ++i) rcs[i] = exec->finish_begin(*fin[i], (int32_t)i);
+                const int wrc = exec->finish_wait();
+                for (size_t i = 0; i < fin.size(); ++i) {
+                    Request *r = fin[i];
+                    int rc = rcs[i] != LBP_OK ? rcs[i] : wrc != LBP_OK ? wrc : exec->finish_end(*r, (int32_t)i);
                     drop_resident(r);
-                    resident.erase(resident.begin() + i);
+                    resident.erase(std::find(resident.begin(), resident.end(), r));
                     complete(r, rc);
-                } else {
-                    ++i;
                 }
+                std::lock_guard<std::mutex> lk(mu);
+                finish_s += clock() - tf;
             }
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -904,7 +1018,7 @@ int lbp_server_drain(lbp_server *s, double timeout_s) {
     return ok ? LBP_OK : set_error(LBP_E_STATE, "drain timed out");
 }
 
-int lbp_server_stats(lbp_server *s, int64_t out[15]) {
+int lbp_server_stats(lbp_server *s, int64_t out[18]) {
     if (!s || !out) return set_error(LBP_E_INVALID, "server or out is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     out[0] = s->n_submitted;
@@ -922,6 +1036,9 @@ int lbp_server_stats(lbp_server *s, int64_t out[15]) {
     out[12] = (int64_t)(s->round_s * 1e6);
     out[13] = (int64_t)(s->prep_s * 1e6);
     out[14] = (int64_t)s->preps.size();
+    out[15] = (int64_t)(s->admit_s * 1e6);
+    out[16] = (int64_t)(s->launch_s * 1e6);
+    out[17] = (int64_t)(s->finish_s * 1e6);
     return LBP_OK;
 }
 

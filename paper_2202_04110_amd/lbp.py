@@ -433,7 +433,7 @@ class Sampler:
 
 SERVER_STATS = ("accepted", "finished", "completed", "rejected", "failed", "cancelled", "rounds",
                 "resident", "queued", "max_resident", "arena_peak_bytes", "busy_us", "round_us", "prep_us",
-                "prep_threads")
+                "prep_threads", "admit_us", "launch_us", "finish_us")
 
 
 class Server:

@@ -108,7 +108,7 @@ int main() {
             cancelled += buf[j].status == LBP_E_STATE;
         }
     }
-    int64_t st[15] = {0};
+    int64_t st[18] = {0};
     lbp_server_stats(srv, st);
     lbp_server_destroy(srv);
     // concurrent host-only validation and layout checks

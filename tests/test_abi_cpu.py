@@ -172,3 +172,20 @@ def test_layout_bounds(lbp, name):
     mk = dict(_layout_cases())[name]
     info = lbp.check_layout(mk())
     assert info["M"] > 0 and info["VB"] > 0
+
+
+def test_compile_reports_first_nonfinite_potential(lbp):
+    """Compilation checks the log-potentials while it copies them into their
+    panels: the first non-finite entry is named, whatever the tile order."""
+    g = W.random_factor_graph(11, num_vars=40, tree=False, extra_factors=30, max_arity=3, explicit_frac=0.4)
+    n = g.num_logpots
+    assert n > 20
+    for idx in (n - 1, n // 2, 3):
+        h = g.copy()
+        h.log_potentials[idx] = np.nan
+        h.log_potentials[n - 1] = -np.inf if idx != n - 1 else np.nan
+        with pytest.raises(lbp.LBPError) as ei:
+            lbp.check_layout(h)
+        assert ei.value.code == lbp.LBP_E_INVALID
+        assert "log_potentials[%d]" % idx in str(ei.value)
+    lbp.check_layout(g)  # the clean graph compiles

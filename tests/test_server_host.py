@@ -42,6 +42,7 @@ def test_budget_and_slots_respected(lbp):
     for r in recs.values():
         assert r["t_arrival"] <= r["t_ready"] <= r["t_admit"] <= r["t_done"]
     assert st["prep_threads"] >= 1 and st["prep_us"] > 0 and st["round_us"] <= st["busy_us"]
+    assert st["launch_us"] <= st["round_us"] and st["finish_us"] <= st["busy_us"] and st["admit_us"] > 0
     # zero-filled outputs of the right sizes from the bookkeeping executor
     assert recs[3]["beliefs"].shape == (specs[3].num_var_states,)
     assert recs[3]["map"].shape == (specs[3].num_vars,)
