@@ -57,6 +57,19 @@ hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool max
 // Read-out of a single graph (gs[0]).
 hipError_t launch_readout(const DevGraph *gs, int nvtiles, bool maxp, const TParams &P, float *q, int normalized,
                           int32_t *map, hipStream_t st);
+// Read-out of one graph inside a multi-graph launch: its normalised beliefs
+// (VS floats, flat order) and MAP (V ints) go to q and map, which may be
+// page-locked host memory; *flag is set to 1 on a non-finite belief (the
+// caller clears it first).  The beliefs B must be current.
+struct ReadJob {
+    const DevGraph *g;
+    float *q;
+    int32_t *map;
+    int32_t *flag;
+    TParams P;
+    int32_t ntiles, maxp;
+};
+hipError_t launch_readout_multi(const ReadJob *jobs, int n, int max_tiles, hipStream_t st);
 hipError_t launch_msgs_out(const DevGraph *gs, int E, float *out, hipStream_t st);
 hipError_t launch_msgs_in(const DevGraph *gs, int E, const float *in, hipStream_t st);
 hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStream_t st);

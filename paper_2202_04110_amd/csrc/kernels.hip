@@ -1189,14 +1189,13 @@ __global__ void k_evidence_out(const DevGraph *__restrict__ gs, const float *__r
 // read-out and flat-order exchange
 // --------------------------------------------------------------------------
 // q[v,s] = B[v,s] - LSE_T(B[v,:]) (or B), MAP = lowest-index argmax.
+// Variable tile w of G; flag_host (may be null) is also set on a non-finite
+// belief.
 template <bool MAXP>
-__global__ __launch_bounds__(256) void k_readout(const DevGraph *__restrict__ gs, int ntiles, TParams P,
-                                                 float *__restrict__ qout, int normalized,
-                                                 int32_t *__restrict__ mapout) {
-    const int w = wave_index(4);
-    if (w >= ntiles) return;
+__device__ __forceinline__ void readout_tile(const DevGraph &G, int w, const TParams &P, float *__restrict__ qout,
+                                             int normalized, int32_t *__restrict__ mapout,
+                                             int32_t *__restrict__ flag_host) {
     const int lane = lane_id();
-    const DevGraph &G = gs[0];
     const int v = w * kLanes + lane;
     if (v >= G.V) return;
     const VTile vt = G.vtile[w];
@@ -1213,7 +1212,10 @@ __global__ __launch_bounds__(256) void k_readout(const DevGraph *__restrict__ gs
             best = s;
         }
     }
-    if (!finite) G.flag[0] = 1;
+    if (!finite) {
+        G.flag[0] = 1;
+        if (flag_host) flag_host[0] = 1;
+    }
     if (mapout) mapout[v] = best;
     if (qout) {
         float z = 0.0f;
@@ -1229,6 +1231,26 @@ __global__ __launch_bounds__(256) void k_readout(const DevGraph *__restrict__ gs
         float *q = qout + G.vs_off[v];
         for (int s = 0; s < n; ++s) q[s] = b[s * kLanes] - z;
     }
+}
+
+template <bool MAXP>
+__global__ __launch_bounds__(256) void k_readout(const DevGraph *__restrict__ gs, int ntiles, TParams P,
+                                                 float *__restrict__ qout, int normalized,
+                                                 int32_t *__restrict__ mapout) {
+    const int w = wave_index(4);
+    if (w >= ntiles) return;
+    readout_tile<MAXP>(gs[0], w, P, qout, normalized, mapout, nullptr);
+}
+
+// Read-outs of several graphs in one launch: blockIdx.y = job, each job's
+// normalised beliefs and MAP written straight to its (page-locked host)
+// outputs, and its flag word set on a non-finite belief.
+__global__ __launch_bounds__(256) void k_readout_multi(const ReadJob *__restrict__ jobs) {
+    const ReadJob J = jobs[blockIdx.y];
+    const int w = wave_index(4);
+    if (w >= J.ntiles) return;
+    if (J.maxp) readout_tile<true>(*J.g, w, J.P, J.q, 1, J.map, J.flag);
+    else readout_tile<false>(*J.g, w, J.P, J.q, 1, J.map, J.flag);
 }
 
 __global__ void k_msgs_out(const DevGraph *__restrict__ gs, float *__restrict__ out) {
@@ -1476,6 +1498,12 @@ hipError_t launch_readout(const DevGraph *gs, int nvtiles, bool maxp, const TPar
     dim3 grid(blocks_for(nvtiles, 4)), block(256);
     if (maxp) hipLaunchKernelGGL((k_readout<true>), grid, block, 0, st, gs, nvtiles, P, q, normalized, map);
     else hipLaunchKernelGGL((k_readout<false>), grid, block, 0, st, gs, nvtiles, P, q, normalized, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout_multi(const ReadJob *jobs, int n, int max_tiles, hipStream_t st) {
+    if (n <= 0 || max_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_readout_multi, dim3(blocks_for(max_tiles, 4), n), dim3(256), 0, st, jobs);
     return hipGetLastError();
 }
 

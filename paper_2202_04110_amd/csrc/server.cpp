@@ -192,6 +192,7 @@ public:
         if (res_host_) (void)hipHostFree(res_host_);
         if (jobs_host_) (void)hipHostFree(jobs_host_);
         if (flags_host_) (void)hipHostFree(flags_host_);
+        if (read_host_) (void)hipHostFree(read_host_);
         if (up_ev_) (void)hipEventDestroy(up_ev_);
         if (jobs_dev_) (void)hipFree(jobs_dev_);
         if (ev_) (void)hipEventDestroy(ev_);
@@ -207,21 +208,30 @@ public:
         HIP_TRY(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&up_ev_, hipEventDisableTiming));
-        if (hipHostMalloc((void **)&flags_host_, sizeof(int32_t) * (size_t)max_slots) != hipSuccess) {
+        if (hipHostMalloc((void **)&flags_host_, sizeof(int32_t) * (size_t)max_slots) != hipSuccess ||
+            hipHostMalloc((void **)&read_host_, sizeof(ReadJob) * (size_t)max_slots) != hipSuccess) {
             (void)hipGetLastError();
-            flags_host_ = nullptr;
-            return set_error(LBP_E_OOM, "pinned read-out flags");
+            return set_error(LBP_E_OOM, "pinned read-out buffers");
+        }
+        // read-outs write the result buffers from the device through their
+        // host addresses: page-locked memory must be mapped at the same address
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, flags_host_, 0) != hipSuccess || dp != (void *)flags_host_) {
+            (void)hipGetLastError();
+            return set_error(LBP_E_UNSUPPORTED, "page-locked host memory is not mapped at its host address");
         }
         // convergence checks: one job and one residual per resident request,
         // staged in pinned memory and read back after each round
         const size_t jb = align256(sizeof(ConvJob) * (size_t)max_slots);
+        const size_t rb = align256(sizeof(float) * (size_t)max_slots);
         if (hipHostMalloc((void **)&res_host_, sizeof(float) * (size_t)max_slots) != hipSuccess ||
             hipHostMalloc((void **)&jobs_host_, sizeof(ConvJob) * (size_t)max_slots) != hipSuccess ||
-            hipMalloc((void **)&jobs_dev_, jb + sizeof(float) * (size_t)max_slots) != hipSuccess) {
+            hipMalloc((void **)&jobs_dev_, jb + rb + sizeof(ReadJob) * (size_t)max_slots) != hipSuccess) {
             (void)hipGetLastError();
-            return set_error(LBP_E_OOM, "convergence-check buffers");
+            return set_error(LBP_E_OOM, "convergence-check and read-out buffers");
         }
         res_dev_ = (float *)((char *)jobs_dev_ + jb);
+        read_dev_ = (ReadJob *)((char *)jobs_dev_ + jb + rb);
         ctx_.stream = compute_;
         hipError_t e = hipMalloc((void **)&base_, std::max<size_t>(budget, 256));
         if (e != hipSuccess) {
@@ -338,28 +348,54 @@ public:
             if (r->check_now) r->residual = res_host_[r->res_slot];
     }
 
+    // A batch of read-outs: each graph's beliefs from its messages (its own
+    // belief launches), then one launch that writes every request's
+    // normalised beliefs and MAP straight into its page-locked result
+    // buffers, then the reverse sweeps of backward requests, then one wait.
     int finish_begin(Request &r, int32_t slot) override {
         if (r.up_gen > up_done_) {  // not covered by a round yet (zero iterations)
             HIP_TRY(hipStreamWaitEvent(compute_, up_ev_, 0));
             round_gen_ = up_gen_;
         }
-        int rc = graph_readout(r.g, r.q, 1, r.map, false, compute_);
-        if (rc != LBP_OK) return rc;
-        if (r.backward) {
-            adjoint_finish_record(r.g);
-            rc = adjoint_backward(r.g, r.gq_dev, r.gphi_dev, nullptr, compute_);
-            if (rc != LBP_OK) return rc;
-            HIP_TRY(hipMemcpyAsync(r.gphi, r.gphi_dev, sizeof(float) * r.L.Tn, hipMemcpyDeviceToHost, compute_));
-        }
+        const TParams P = make_params(0.5f, r.T);
+        HIP_TRY(launch_iteration(r.g->dgraph, r.g->vl, r.g->fl, P, r.T == 0.0f, compute_, 1));
         flags_host_[slot] = 0;
-        HIP_TRY(hipMemcpyAsync(flags_host_ + slot, r.g->host.flag, sizeof(int32_t), hipMemcpyDeviceToHost, compute_));
+        ReadJob &J = read_host_[fin_.size()];  // jobs packed in the order they are queued
+        J.g = r.g->dgraph;
+        J.q = r.q;
+        J.map = r.map;
+        J.flag = flags_host_ + slot;
+        J.P = P;
+        J.ntiles = r.g->nvt;
+        J.maxp = r.T == 0.0f;
+        fin_.push_back(&r);
         return LBP_OK;
     }
 
     int finish_wait() override {
+        const int n = (int)fin_.size();
+        int max_tiles = 0;
+        for (int i = 0; i < n; ++i) max_tiles = std::max(max_tiles, read_host_[i].ntiles);
+        int rc = LBP_OK;
+        if (n > 0) {
+            hipError_t e = hipMemcpyAsync(read_dev_, read_host_, sizeof(ReadJob) * n, hipMemcpyHostToDevice, compute_);
+            if (e == hipSuccess) e = launch_readout_multi(read_dev_, n, max_tiles, compute_);
+            if (e != hipSuccess) rc = hip_error(e, "read-out launch");
+        }
+        for (Request *r : fin_)
+            if (rc == LBP_OK && r->backward) {
+                adjoint_finish_record(r->g);
+                rc = adjoint_backward(r->g, r->gq_dev, r->gphi_dev, nullptr, compute_);
+                if (rc == LBP_OK) {
+                    hipError_t e = hipMemcpyAsync(r->gphi, r->gphi_dev, sizeof(float) * r->L.Tn,
+                                                  hipMemcpyDeviceToHost, compute_);
+                    if (e != hipSuccess) rc = hip_error(e, "gradient read-out");
+                }
+            }
+        fin_.clear();
         HIP_TRY(hipStreamSynchronize(compute_));
         up_done_ = std::max(up_done_, round_gen_);
-        return LBP_OK;
+        return rc;
     }
 
     int finish_end(Request &r, int32_t slot) override {
@@ -530,6 +566,9 @@ private:
     std::vector<Part> parts_;
     float *res_host_ = nullptr;   // pinned, one residual per active slot
     int32_t *flags_host_ = nullptr;  // pinned, one read-out flag per finishing request
+    ReadJob *read_host_ = nullptr;   // pinned staging of a read-out batch
+    ReadJob *read_dev_ = nullptr;    // its device copy (after res_dev_)
+    std::vector<Request *> fin_;     // the batch being read out
     hipEvent_t up_ev_ = nullptr;     // recorded on the copy stream after each upload
     uint64_t up_gen_ = 0;            // uploads issued
     uint64_t up_done_ = 0;           // uploads known to have completed
