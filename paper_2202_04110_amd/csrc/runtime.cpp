@@ -370,6 +370,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         // the host image and the descriptors must outlive the copies (the
         // descriptors live in g; without wait, the caller keeps the image)
         if (e == hipSuccess && (wait || gp.fused)) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) (void)hipStreamSynchronize(st);  // no copy may still read an image
         panel_free(own_image);
         own_image = nullptr;
         if (e != hipSuccess) {
