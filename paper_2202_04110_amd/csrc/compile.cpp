@@ -201,7 +201,7 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err, b
     return LBP_OK;
 }
 
-int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
+int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool fill) {
     int64_t sz[6];
     // the potentials are checked for NaN and infinity while they are copied
     // into their panels (every one of them is), not in a pass of their own
@@ -588,33 +588,48 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
         if (fg.kind != TK_PAIR || fg.a != fg.b) L->fusable = false;
 
     // -------------------------------------------------------------- values
-    // Panels are written front to back, every element once (padding zero).
+    if (!fill) {
+        L->tile_fac.swap(tile_fac);  // fill_panels needs it later
+        return LBP_OK;
+    }
     L->theta_panel.resize(L->VB);
+    L->phi_panel.resize(L->P);
+    L->tile_fac.swap(tile_fac);
+    rc = fill_panels(d, *L, L->theta_panel.data(), L->phi_panel.data(), err);
+    std::vector<int32_t>().swap(L->tile_fac);
+    return rc;
+}
+
+int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, float *phi, std::string *err) {
+    // Panels are written front to back, every element once (padding zero).
+    const int64_t V = L.V;
+    const int64_t nvt = (int64_t)L.vtile.size();
+    int64_t filled = 0;
     for (int64_t t = 0; t < nvt; ++t) {
-        const VTile &vt = L->vtile[t];
-        float *row = L->theta_panel.data() + vt.b_off;
+        const VTile &vt = L.vtile[t];
+        float *row = theta + vt.b_off;
         for (int32_t s = 0; s < vt.n; ++s, row += kLanes)
             for (int32_t l = 0; l < kLanes; ++l) {
                 const int64_t v = t * kLanes + l;
-                row[l] = (d->evidence && v < V && s < L->vn[v]) ? d->evidence[L->vs_off[v] + s] : 0.0f;
+                row[l] = (d->evidence && v < V && s < L.vn[v]) ? d->evidence[L.vs_off[v] + s] : 0.0f;
             }
+        filled = std::max<int64_t>(filled, vt.b_off + (int64_t)vt.n * kLanes);
     }
-    std::fill(L->theta_panel.begin() + b_zero, L->theta_panel.end(), 0.0f);
-    L->phi_panel.resize(L->P);
-    if (P == 0) std::fill(L->phi_panel.begin(), L->phi_panel.end(), 0.0f);
+    std::fill(theta + filled, theta + L.VB, 0.0f);  // the spare zero panel
     // each tile's panel is the transpose of its factors' tables: blocks of 16
-    // lanes, so every configuration row is written 64 bytes at a time
+    // lanes, so every configuration row is written 64 bytes at a time; the
+    // values are checked for NaN and infinity on the way
     uint32_t nonfinite = 0;
-    for (size_t t = 0; t < L->ftile.size(); ++t) {
-        const FTile &ft = L->ftile[t];
+    for (size_t t = 0; t < L.ftile.size(); ++t) {
+        const FTile &ft = L.ftile[t];
         if (ft.kind != TK_PAIR && ft.kind != TK_GEN) continue;
-        const int32_t ncfg = ft.kind == TK_PAIR ? ft.a * ft.b : L->gcls[ft.a].ncfg;
-        const int32_t *lf = tile_fac.data() + t * kLanes;
-        float *panel = L->phi_panel.data() + ft.phi_off;
+        const int32_t ncfg = ft.kind == TK_PAIR ? ft.a * ft.b : L.gcls[ft.a].ncfg;
+        const int32_t *lf = L.tile_fac.data() + t * kLanes;
+        float *panel = phi + ft.phi_off;
         for (int32_t l0 = 0; l0 < kLanes; l0 += 16) {
             const float *src[16];
             for (int32_t l = 0; l < 16; ++l)
-                src[l] = lf[l0 + l] >= 0 ? d->log_potentials + L->lp_off[lf[l0 + l]] : nullptr;
+                src[l] = lf[l0 + l] >= 0 ? d->log_potentials + L.lp_off[lf[l0 + l]] : nullptr;
             for (int32_t c = 0; c < ncfg; ++c) {
                 float *row = panel + (int64_t)c * kLanes + l0;
                 for (int32_t l = 0; l < 16; ++l) {
@@ -628,7 +643,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err) {
         }
     }
     if (nonfinite) {
-        const int64_t i = first_nonfinite(d->log_potentials, L->Tn);
+        const int64_t i = first_nonfinite(d->log_potentials, L.Tn);
         return bad(err, at("log_potentials", i) + " is not finite");
     }
     return LBP_OK;

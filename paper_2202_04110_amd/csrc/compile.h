@@ -82,7 +82,9 @@ struct HostLayout {
     std::vector<int64_t> es_off, vs_off;
     std::vector<int32_t> vn, fac_phi;
     std::vector<int64_t> lp_off;
-    PanelBuf theta_panel, phi_panel;  // every element written by compile_desc
+    PanelBuf theta_panel, phi_panel;  // every element written by compile_desc (or fill_panels)
+    std::vector<int32_t> tile_fac;    // factor of each (tile, lane) with a potential panel, -1 otherwise
+                                      // (kept only when compile_desc leaves the panels to fill_panels)
     std::vector<FGroup> fgroups;
     std::vector<VGroup> vgroups;
 };
@@ -91,7 +93,13 @@ struct HostLayout {
 // scan_potentials = false leaves the NaN/infinity check of the log-potentials
 // to the caller (compile_desc does it while filling the potential panels).
 int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err, bool scan_potentials = true);
-int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err);
+// fill = false: the layout without its evidence and potential panels, which
+// fill_panels then writes wherever the caller wants them (an upload image).
+int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool fill = true);
+// Writes the evidence panel (L.VB floats) and the potential panel (L.P
+// floats) of a layout compiled from `d`, checking the potentials for NaN and
+// infinity (LBP_E_INVALID naming the first).
+int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, float *phi, std::string *err);
 // Host replay of every kernel's addresses against the layout's array sizes.
 int check_layout(const HostLayout &L, std::string *err);
 

@@ -242,8 +242,9 @@ struct GraphPieces {
             total += align256(std::max<size_t>(bytes, 4));
             return p.size() - 1;
         };
-        th = add(L.theta_panel.data(), sizeof(float) * L.VB);
-        phi = add(L.phi_panel.data(), sizeof(float) * L.P);
+        // panels not compiled into the layout are written in place later
+        th = add(L.theta_panel.size() == (size_t)L.VB ? L.theta_panel.data() : nullptr, sizeof(float) * L.VB);
+        phi = add(L.phi_panel.size() == (size_t)L.P ? L.phi_panel.data() : nullptr, sizeof(float) * L.P);
         ft = add(L.ftile.data(), sizeof(FTile) * L.ftile.size());
         fvb = add(L.fvb.data(), sizeof(int32_t) * L.fvb.size());
         fvar = add(L.fvar.data(), sizeof(int32_t) * L.fvar.size());
@@ -285,11 +286,16 @@ size_t graph_device_bytes(const HostLayout &L, bool with_fused) { return GraphPi
 
 size_t graph_image_bytes(const HostLayout &L) { return GraphPieces(L, false).data_end; }
 
-void graph_fill_image(const HostLayout &L, char *image) {
+int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d, std::string *err) {
     GraphPieces gp(L, false);
     for (const Piece &p : gp.p)
         if (p.src && p.bytes) std::memcpy(image + p.off, p.src, p.bytes);
     pack_lists(gp.ll, image + gp.p[gp.items].off);
+    if (L.theta_panel.size() == (size_t)L.VB && L.phi_panel.size() == (size_t)L.P) return LBP_OK;
+    // panels left to fill_panels: written here, in place
+    std::string e;
+    if (!d) return set_error(LBP_E_INVALID, "graph image: the layout has no panels and no description was given");
+    return fill_panels(d, L, (float *)(image + gp.p[gp.th].off), (float *)(image + gp.p[gp.phi].off), err ? err : &e);
 }
 
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
@@ -317,7 +323,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
             wait = true;  // the image built here is freed before returning
             own_image = (char *)panel_alloc(gp.data_end);
             if (!own_image) throw std::bad_alloc();
-            graph_fill_image(L, own_image);
+            graph_fill_image(L, own_image);  // compiled with its panels
             image = own_image;
         }
         // one copy of every host piece (a single DMA when the image is

@@ -168,7 +168,9 @@ size_t graph_device_bytes(const HostLayout &L, bool with_fused);
 // packed in device order (graph_image_bytes(L) bytes, written by
 // graph_fill_image), uploaded with one copy.
 size_t graph_image_bytes(const HostLayout &L);
-void graph_fill_image(const HostLayout &L, char *image);
+// Writes the image.  A layout compiled without its panels (compile_desc with
+// fill = false) has them written here from `d`, with fill_panels' checks.
+int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d = nullptr, std::string *err = nullptr);
 // Creates a graph from a compiled (and checked) layout.  mem: a 256-aligned
 // region of graph_device_bytes(L, with_fused) bytes the caller owns, or
 // nullptr to allocate.  image: the layout's host image, or nullptr to build

@@ -641,7 +641,9 @@ struct lbp_server {
             const double tp = clock();
             try {
                 std::string err;
-                rc = compile_desc(&r->desc->d, &r->L, &err);  // validates first
+                // validates first; the panels go straight into the upload
+                // image below when the executor wants one
+                rc = compile_desc(&r->desc->d, &r->L, &err, !exec->wants_image());
                 if (rc == LBP_OK) rc = check_layout(r->L, &err);
                 if (rc == LBP_OK) {
                     r->graph_bytes = graph_device_bytes(r->L, false);
@@ -659,13 +661,13 @@ struct lbp_server {
                     if (r->bytes > arena.capacity()) rc = LBP_E_BUDGET;
                 }
                 if (rc == LBP_OK && exec->wants_image()) {
-                    // pack the upload here, off the worker thread; the host
-                    // panels are then no longer needed
+                    // pack the upload here, off the worker thread, with the
+                    // evidence and potential panels written in place
                     r->image.reset((char *)panel_alloc(graph_image_bytes(r->L)));
                     if (!r->image) throw std::bad_alloc();
-                    graph_fill_image(r->L, r->image.get());
-                    PanelBuf().swap(r->L.phi_panel);
-                    PanelBuf().swap(r->L.theta_panel);
+                    rc = graph_fill_image(r->L, r->image.get(), &r->desc->d, &err);
+                    std::vector<int32_t>().swap(r->L.tile_fac);
+                    if (rc != LBP_OK) r->image.reset();
                 }
             } catch (const std::bad_alloc &) {
                 rc = LBP_E_OOM;

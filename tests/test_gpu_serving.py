@@ -97,6 +97,34 @@ def test_cancel_resident_request(lbp, ctx):
     assert res[2]["status"] == 0
 
 
+def test_invalid_values_and_zero_iterations(lbp, ctx):
+    """Requests whose potentials or evidence hold NaN/infinity complete with
+    LBP_E_INVALID (the potentials are checked as the upload image is
+    written), zero-iteration requests are read out from zero messages, and
+    the requests around them are unaffected."""
+    good = W.potts_grid(20, 3, 31)
+    bad_lp = W.potts_grid(20, 3, 32)
+    bad_lp.log_potentials[len(bad_lp.log_potentials) // 2] = np.nan
+    bad_ev = W.potts_grid(12, 3, 33)
+    bad_ev.evidence[7] = np.inf
+    srv = lbp.Server(ctx, budget_bytes=64 << 20, max_slots=4, steps_per_round=5)
+    srv.submit(good, 30, 0.5, 1.0, req_id=1)
+    srv.submit(bad_lp, 30, 0.5, 1.0, req_id=2)
+    srv.submit(bad_ev, 30, 0.5, 1.0, req_id=3)
+    srv.submit(good, 0, 0.5, 1.0, req_id=4)
+    srv.submit(good, 30, 0.5, 0.0, req_id=5)
+    srv.drain(60)
+    res = {r["req_id"]: r for r in srv.poll()}
+    srv.close()
+    assert res[2]["status"] == lbp.LBP_E_INVALID and res[2]["beliefs"] is None
+    assert res[3]["status"] == lbp.LBP_E_INVALID
+    for rid, iters, T in ((1, 30, 1.0), (4, 0, 1.0), (5, 30, 0.0)):
+        q, mp, _ = lone(lbp, ctx, good, iters, 0.5, T)
+        assert res[rid]["status"] == 0 and res[rid]["iters"] == iters
+        np.testing.assert_array_equal(res[rid]["beliefs"], q)
+        np.testing.assert_array_equal(res[rid]["map"], mp)
+
+
 def test_early_exit_requests_equal_lone_run_until(lbp, ctx):
     """Requests with a tolerance (lbp_server_submit_until) served together
     with fixed-iteration requests: each stops at the same iteration, with
