@@ -314,6 +314,47 @@ def test_potts512_full_size(lbp, ctx):
     mo = og.run(1, 0.5, 1.0, m0=m.astype(np.float64), threads=NT)
     g.run_bp(1, 0.5, 1.0)
     assert np.abs(g.get_messages() - mo).max() <= TOL_STEP
+    # the launch configuration the benchmark times (shipped shapes: fused
+    # iterations) gives bitwise the two-phase messages after 200 iterations
+    from paper_2202_04110_amd import tune
+    f = lbp.Graph(ctx, spec)
+    tune.apply_or_tune(f, 0.5, 1.0, path=os.devnull, packaged=True)
+    assert f.fused_in_use
+    f.run_bp(200, 0.5, 1.0)
+    np.testing.assert_array_equal(f.get_messages(), m)
+    np.testing.assert_array_equal(f.get_beliefs(), q)
+    f.free()
+    g.free()
+
+
+def test_potts2048_full_size(lbp, ctx):
+    """Potts 2048x2048x5 (beyond the last-level cache) in the launch
+    configuration the benchmark times (shipped shapes: fused iterations with
+    the tables loaded before the gathers): every message after 2 iterations
+    from zero against the oracle, the row invariant and normalised beliefs
+    after 200, and one step from the GPU's final state against the oracle."""
+    from paper_2202_04110_amd import tune
+    spec = W.potts_grid(2048, 5, 2)
+    g = lbp.Graph(ctx, spec)
+    tune.apply_or_tune(g, 0.5, 1.0, path=os.devnull, packaged=True)
+    assert g.fused_in_use
+    assert [l["fused_variant"] & 2 for l in g.launches() if l["phase"] == 1] == [2]
+    og = OracleGraph(spec)
+    g.run_bp(2, 0.5, 1.0)
+    mo = og.run(2, 0.5, 1.0, threads=NT)
+    assert np.abs(g.get_messages() - mo).max() <= TOL_STEP
+    del mo
+    g.run_bp(198, 0.5, 1.0)
+    m = g.get_messages()
+    off = spec.edge_state_off()
+    assert np.all(np.maximum.reduceat(m, off[:-1]) == 0.0)
+    q = g.get_beliefs()
+    lse = np.log(np.exp(q.astype(np.float64)).reshape(-1, 5).sum(1))
+    assert np.abs(lse).max() < 1e-5
+    mo = og.run(1, 0.5, 1.0, m0=m.astype(np.float64), threads=NT)
+    g.run_bp(1, 0.5, 1.0)
+    assert np.abs(g.get_messages() - mo).max() <= TOL_STEP
+    g.free()
 
 
 # ------------------------------------------------------- state semantics
