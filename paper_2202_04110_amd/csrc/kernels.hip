@@ -266,19 +266,22 @@ __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int la
     const int k = h.e_begin + lane;
     const int a = k < h.e_end ? G.hedge[k] : -1;
     for (int s0 = 0; s0 < h.n; s0 += SC) {
+        // lane j's evidence term, loaded with the edge rows rather than
+        // after the sums
+        const bool own = lane < SC && s0 + lane < h.n;
+        const float th = own ? G.theta[h.b_addr + (s0 + lane) * kLanes] : 0.0f;
         float x[SC];
 #pragma unroll
         for (int j = 0; j < SC; ++j) x[j] = (a >= 0 && s0 + j < h.n) ? G.m[a + (s0 + j) * kLanes] : 0.0f;
 #pragma unroll
         for (int j = 0; j < SC; ++j)
             if (s0 + j < h.n) x[j] = wave_sum(x[j]);  // uniform condition
-        if (lane < SC && s0 + lane < h.n) {
+        if (own) {
             float v = 0.0f;
 #pragma unroll
             for (int j = 0; j < SC; ++j)
                 if (j == lane) v = x[j];
-            const int b = h.b_addr + (s0 + lane) * kLanes;
-            G.B[b] = G.theta[b] + v;
+            G.B[h.b_addr + (s0 + lane) * kLanes] = th + v;
         }
     }
 }
@@ -295,6 +298,9 @@ __device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int t
     const int lane = tid & 63, wave = tid >> 6;
     for (int s0 = 0; s0 < h.n; s0 += SC) {
         const int ns = min(SC, h.n - s0);  // uniform
+        // thread tid's evidence term, loaded with the edge rows rather than
+        // after the reduction
+        const float th = tid < ns ? G.theta[h.b_addr + (s0 + tid) * kLanes] : 0.0f;
         float part[SC];
 #pragma unroll
         for (int j = 0; j < SC; ++j) part[j] = 0.0f;
@@ -328,8 +334,7 @@ __device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int t
             float v = red[tid][0];
 #pragma unroll
             for (int w = 1; w < kHighWaves; ++w) v += red[tid][w];
-            const int b = h.b_addr + (s0 + tid) * kLanes;
-            G.B[b] = G.theta[b] + v;
+            G.B[h.b_addr + (s0 + tid) * kLanes] = th + v;
         }
         __syncthreads();
     }

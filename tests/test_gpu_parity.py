@@ -630,3 +630,26 @@ def test_run_until_converged(lbp, ctx):
     f.use_fused(True)
     assert f.run_bp_until(300, 0.5, 1.0, tol) == (done, r)
     np.testing.assert_array_equal(f.get_messages(), ref.get_messages())
+
+
+@pytest.mark.parametrize("name", ["rbm", "rbm_t005", "deconv", "ising32", "triplet256"])
+def test_bench_launch_configuration_bitwise(lbp, ctx, name):
+    """Each benchmark workload at full size in the launch configuration the
+    benchmark times (shipped launch shapes, fused iterations where the table
+    says so) gives bitwise the messages, beliefs and MAP of the default
+    configuration, whose parity with the oracle the tests above check."""
+    import bench
+    from paper_2202_04110_amd import tune
+    build, iters, d, T, _ = bench.WORKLOADS[name]
+    spec = build(W)
+    n = min(iters, 60)
+    ref = lbp.Graph(ctx, spec)
+    ref.run_bp(n, d, T)
+    g = lbp.Graph(ctx, spec)
+    tune.apply_or_tune(g, d, T, path=os.devnull, packaged=True)
+    g.run_bp(n, d, T)
+    np.testing.assert_array_equal(g.get_messages(), ref.get_messages())
+    np.testing.assert_array_equal(g.get_beliefs(), ref.get_beliefs())
+    np.testing.assert_array_equal(g.decode_map(), ref.decode_map())
+    g.free()
+    ref.free()
