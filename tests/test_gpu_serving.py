@@ -97,6 +97,33 @@ def test_cancel_resident_request(lbp, ctx):
     assert res[2]["status"] == 0
 
 
+def test_cancel_during_upload(lbp, ctx):
+    """Requests cancelled right after submission (while they are being
+    prepared, queued or uploaded) complete with LBP_E_STATE; their memory is
+    reused only after any upload in flight has finished, so the requests
+    admitted after them give the lone-run results."""
+    big = [W.potts_grid(160, 6, 40 + i) for i in range(6)]
+    small = W.potts_grid(24, 4, 50)
+    srv = lbp.Server(ctx, budget_bytes=96 << 20, max_slots=3, steps_per_round=5)
+    for i, spec in enumerate(big):
+        srv.submit(spec, 40, 0.5, 1.0, req_id=i)
+        srv.cancel(i)
+    for j in range(4):
+        srv.submit(small, 20 + 5 * j, 0.5, 1.0, req_id=100 + j)
+    srv.drain(120)
+    res = {r["req_id"]: r for r in srv.poll(64)}
+    st = srv.stats()
+    srv.close()
+    assert len(res) == len(big) + 4
+    assert all(res[i]["status"] in (lbp.LBP_E_STATE, 0) for i in range(len(big)))
+    assert st["cancelled"] >= 1
+    for j in range(4):
+        q, mp, _ = lone(lbp, ctx, small, 20 + 5 * j, 0.5, 1.0)
+        assert res[100 + j]["status"] == 0
+        np.testing.assert_array_equal(res[100 + j]["beliefs"], q)
+        np.testing.assert_array_equal(res[100 + j]["map"], mp)
+
+
 def test_invalid_values_and_zero_iterations(lbp, ctx):
     """Requests whose potentials or evidence hold NaN/infinity complete with
     LBP_E_INVALID (the potentials are checked as the upload image is
