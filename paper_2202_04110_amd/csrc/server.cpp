@@ -30,6 +30,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -105,6 +106,8 @@ struct Request {
     size_t conv_bytes = 0;    // previous messages, partial maxima, residual
     char *conv = nullptr;
     uint64_t up_gen = 0;      // upload number (executor's count) while its upload may be in flight
+    bool in_backward = false; // read out; its reverse sweep runs on the executor's finisher thread
+    int back_status = LBP_OK;
     std::vector<float> grad_q;
     HostLayout L;
     size_t bytes = 0, graph_bytes = 0, adj_bytes = 0;
@@ -145,6 +148,15 @@ public:
     virtual void release(Request &r) = 0;
     // after wait(): frees the upload images that are no longer needed
     virtual void images_done(const std::vector<Request *> &) {}
+    // Reverse sweeps off the worker thread: after its read-out, a backward
+    // request may be handed to a finisher (start_backward returns true; the
+    // request stays resident); take_backward returns the finished ones, with
+    // back_status set; `wake` is called from the finisher when one is done;
+    // drain_backward waits until every handed-over sweep has finished.
+    virtual bool start_backward(Request &) { return false; }
+    virtual void take_backward(std::vector<Request *> &) {}
+    virtual void set_wake(std::function<void()>) {}
+    virtual void drain_backward() {}
     virtual int alloc_outputs(Request &r) = 0;
     virtual void free_outputs(Request &r) = 0;
     // whether prep threads should pack each request's upload image
@@ -184,7 +196,17 @@ public:
 class GpuExecutor : public Executor {
 public:
     ~GpuExecutor() override {
+        if (fin_th_.joinable()) {
+            {
+                std::lock_guard<std::mutex> lk(fmu_);
+                fstop_ = true;
+            }
+            fcv_.notify_all();
+            fin_th_.join();
+        }
         (void)hipSetDevice(ctx_.device);
+        if (back_) (void)hipStreamSynchronize(back_);
+        if (back_) (void)hipStreamDestroy(back_);
         if (compute_) (void)hipStreamSynchronize(compute_);
         if (copy_) (void)hipStreamSynchronize(copy_);
         if (stage_) (void)hipFree(stage_);
@@ -206,6 +228,7 @@ public:
         HIP_TRY(hipSetDevice(device));
         HIP_TRY(hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking));
         HIP_TRY(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&back_, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&up_ev_, hipEventDisableTiming));
         if (hipHostMalloc((void **)&flags_host_, sizeof(int32_t) * (size_t)max_slots) != hipSuccess ||
@@ -238,6 +261,11 @@ public:
             (void)hipGetLastError();
             base_ = nullptr;
             return set_error(LBP_E_OOM, "server arena of " + std::to_string(budget) + " bytes");
+        }
+        try {
+            fin_th_ = std::thread([this] { finisher(); });
+        } catch (const std::system_error &) {
+            return set_error(LBP_E_OOM, "could not start the finisher thread");
         }
         return LBP_OK;
     }
@@ -351,7 +379,7 @@ public:
     // A batch of read-outs: each graph's beliefs from its messages (its own
     // belief launches), then one launch that writes every request's
     // normalised beliefs and MAP straight into its page-locked result
-    // buffers, then the reverse sweeps of backward requests, then one wait.
+    // buffers, then one wait.  Backward requests then go to the finisher.
     int finish_begin(Request &r, int32_t slot) override {
         if (r.up_gen > up_done_) {  // not covered by a round yet (zero iterations)
             HIP_TRY(hipStreamWaitEvent(compute_, up_ev_, 0));
@@ -382,16 +410,6 @@ public:
             if (e == hipSuccess) e = launch_readout_multi(read_dev_, n, max_tiles, compute_);
             if (e != hipSuccess) rc = hip_error(e, "read-out launch");
         }
-        for (Request *r : fin_)
-            if (rc == LBP_OK && r->backward) {
-                adjoint_finish_record(r->g);
-                rc = adjoint_backward(r->g, r->gq_dev, r->gphi_dev, nullptr, compute_);
-                if (rc == LBP_OK) {
-                    hipError_t e = hipMemcpyAsync(r->gphi, r->gphi_dev, sizeof(float) * r->L.Tn,
-                                                  hipMemcpyDeviceToHost, compute_);
-                    if (e != hipSuccess) rc = hip_error(e, "gradient read-out");
-                }
-            }
         fin_.clear();
         HIP_TRY(hipStreamSynchronize(compute_));
         up_done_ = std::max(up_done_, round_gen_);
@@ -401,6 +419,32 @@ public:
     int finish_end(Request &r, int32_t slot) override {
         drop_image(r);
         return flags_host_[slot] ? set_error(LBP_E_NONFINITE, "beliefs contain NaN or infinity") : LBP_OK;
+    }
+
+    bool start_backward(Request &r) override {
+        {
+            std::lock_guard<std::mutex> lk(fmu_);
+            bq_.push_back(&r);
+            ++fpending_;
+        }
+        fcv_.notify_one();
+        return true;
+    }
+
+    void take_backward(std::vector<Request *> &out) override {
+        std::lock_guard<std::mutex> lk(fmu_);
+        out.insert(out.end(), bdone_.begin(), bdone_.end());
+        bdone_.clear();
+    }
+
+    void set_wake(std::function<void()> w) override {
+        std::lock_guard<std::mutex> lk(fmu_);
+        wake_ = std::move(w);
+    }
+
+    void drain_backward() override {
+        std::unique_lock<std::mutex> lk(fmu_);
+        fdone_cv_.wait(lk, [&] { return fpending_ == 0; });
     }
 
     void release(Request &r) override {
@@ -444,6 +488,41 @@ public:
     }
 
 private:
+    // The finisher: reverse sweeps of read-out backward requests on their own
+    // stream, so they overlap the worker's rounds.  A request's graph is not
+    // touched by the worker while it is here (it is resident but not active).
+    void finisher() {
+        (void)hipSetDevice(ctx_.device);
+        for (;;) {
+            Request *r = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(fmu_);
+                fcv_.wait(lk, [&] { return fstop_ || !bq_.empty(); });
+                if (bq_.empty()) return;  // stopping with nothing queued
+                r = bq_.front();
+                bq_.pop_front();
+            }
+            adjoint_finish_record(r->g);
+            int rc = adjoint_backward(r->g, r->gq_dev, r->gphi_dev, nullptr, back_);
+            if (rc == LBP_OK) {
+                hipError_t e = hipMemcpyAsync(r->gphi, r->gphi_dev, sizeof(float) * r->L.Tn, hipMemcpyDeviceToHost,
+                                              back_);
+                if (e == hipSuccess) e = hipStreamSynchronize(back_);
+                if (e != hipSuccess) rc = hip_error(e, "gradient read-out");
+            }
+            r->back_status = rc;
+            std::function<void()> wake;
+            {
+                std::lock_guard<std::mutex> lk(fmu_);
+                bdone_.push_back(r);
+                --fpending_;
+                wake = wake_;
+            }
+            fdone_cv_.notify_all();
+            if (wake) wake();
+        }
+    }
+
     // Pinned host buffers for results, per power-of-two size class, shared
     // by every server of the process and reused (page-locking is slow, so a
     // new server starts with the buffers earlier ones returned).  At most
@@ -569,6 +648,15 @@ private:
     ReadJob *read_host_ = nullptr;   // pinned staging of a read-out batch
     ReadJob *read_dev_ = nullptr;    // its device copy (after res_dev_)
     std::vector<Request *> fin_;     // the batch being read out
+    hipStream_t back_ = nullptr;     // the finisher's stream
+    std::thread fin_th_;
+    std::mutex fmu_;
+    std::condition_variable fcv_, fdone_cv_;
+    std::deque<Request *> bq_;       // fmu_: waiting for their reverse sweep
+    std::vector<Request *> bdone_;   // fmu_: swept, for the worker to complete
+    int fpending_ = 0;               // fmu_: handed over and not yet swept
+    bool fstop_ = false;             // fmu_
+    std::function<void()> wake_;
     hipEvent_t up_ev_ = nullptr;     // recorded on the copy stream after each upload
     uint64_t up_gen_ = 0;            // uploads issued
     uint64_t up_done_ = 0;           // uploads known to have completed
@@ -598,6 +686,8 @@ struct lbp_server {
     std::vector<Request *> handed_out; // caller thread: freed at the next poll
     std::deque<Request *> pending;     // worker only
     std::vector<Request *> resident;   // worker only
+    int64_t n_in_backward = 0;         // worker only: resident requests with the finisher
+    int back_ready = 0;                // mu: finisher completions not yet taken
     bool stop = false;                 // mu
     std::thread th;
     Clock::time_point t0 = Clock::now();
@@ -761,10 +851,11 @@ struct lbp_server {
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv.wait(lk, [&] {
-                    return stop || !incoming.empty() || !resident.empty() || !cancels.empty() ||
-                           (!pending.empty() && pending.front()->prep != 0);
+                    return stop || !incoming.empty() || (int64_t)resident.size() > n_in_backward ||
+                           !cancels.empty() || back_ready > 0 || (!pending.empty() && pending.front()->prep != 0);
                 });
                 if (stop) break;
+                back_ready = 0;
                 while (!incoming.empty()) {
                     pending.push_back(incoming.front());
                     incoming.pop_front();
@@ -777,9 +868,22 @@ struct lbp_server {
                 }
                 cancels.clear();
             }
-            // cancelled resident requests leave at this round boundary
+            // requests whose reverse sweep has finished leave
+            {
+                std::vector<Request *> swept;
+                exec->take_backward(swept);
+                for (Request *r : swept) {
+                    r->in_backward = false;
+                    --n_in_backward;
+                    drop_resident(r);
+                    resident.erase(std::find(resident.begin(), resident.end(), r));
+                    complete(r, r->back_status);
+                }
+            }
+            // cancelled resident requests leave at this round boundary (those
+            // with the finisher complete when their sweep does)
             for (size_t i = 0; i < resident.size();) {
-                if (resident[i]->cancel) {
+                if (resident[i]->cancel && !resident[i]->in_backward) {
                     Request *r = resident[i];
                     drop_resident(r);
                     resident.erase(resident.begin() + i);
@@ -835,7 +939,7 @@ struct lbp_server {
             // leaves (its memory is reused only after the wait)
             std::vector<Request *> fin;
             for (Request *r : resident)
-                if (r->done >= r->iters || r->settled) fin.push_back(r);
+                if ((r->done >= r->iters || r->settled) && !r->in_backward) fin.push_back(r);
             if (!fin.empty()) {
                 const double tf = clock();
                 std::vector<int> rcs(fin.size(), LBP_OK);
@@ -844,6 +948,11 @@ struct lbp_server {
                 for (size_t i = 0; i < fin.size(); ++i) {
                     Request *r = fin[i];
                     int rc = rcs[i] != LBP_OK ? rcs[i] : wrc != LBP_OK ? wrc : exec->finish_end(*r, (int32_t)i);
+                    if (rc == LBP_OK && r->backward && exec->start_backward(*r)) {
+                        r->in_backward = true;  // stays resident until its sweep is done
+                        ++n_in_backward;
+                        continue;
+                    }
                     drop_resident(r);
                     resident.erase(std::find(resident.begin(), resident.end(), r));
                     complete(r, rc);
@@ -857,7 +966,18 @@ struct lbp_server {
             }
             update_stats();
         }
-        // shutting down: everything left is cancelled
+        // shutting down: sweeps under way finish, everything else is cancelled
+        exec->drain_backward();
+        {
+            std::vector<Request *> swept;
+            exec->take_backward(swept);
+            for (Request *r : swept) {
+                r->in_backward = false;
+                drop_resident(r);
+                resident.erase(std::find(resident.begin(), resident.end(), r));
+                complete(r, r->back_status);
+            }
+        }
         for (Request *r : resident) {
             drop_resident(r);
             complete(r, LBP_E_STATE);
@@ -890,6 +1010,11 @@ int server_create(lbp_ctx *ctx, int64_t budget, int32_t max_slots, int32_t steps
             s->exec.reset(new HostExecutor);
         }
         lbp_server *raw = s.get();
+        s->exec->set_wake([raw] {
+            std::lock_guard<std::mutex> lk(raw->mu);
+            ++raw->back_ready;
+            raw->cv.notify_one();
+        });
         s->th = std::thread([raw] { raw->run(); });
         // preparation threads: half the CPUs this process may run on, at
         // most 8 (more contend for host memory bandwidth and run slower)
@@ -1094,6 +1219,7 @@ void lbp_server_destroy(lbp_server *s) {
     if (s->th.joinable()) s->th.join();
     for (std::thread &t : s->preps)
         if (t.joinable()) t.join();
+    s->exec->set_wake(nullptr);  // the worker is gone; nothing is left to wake
     for (Request *r : s->handed_out) {
         s->exec->free_outputs(*r);
         delete r;
