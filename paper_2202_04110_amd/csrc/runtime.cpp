@@ -266,11 +266,11 @@ struct GraphPieces {
         add_to_lists(ll, 0, s, &mids, &highs);
         finish_lists(ll, mids, highs);
         items = add(nullptr, lists_bytes(ll));  // packed by pack_lists
+        dg = add(nullptr, sizeof(DevGraph));    // written into the image by graph_create
         data_end = total;  // everything above is copied from the host image, everything below starts zero
         m = add(nullptr, sizeof(float) * L.M);
         B = add(nullptr, sizeof(float) * L.VB);
         fl = add(nullptr, sizeof(int32_t) * 4);
-        dg = add(nullptr, sizeof(DevGraph));
         q = add(nullptr, sizeof(float) * L.VS);
         map = add(nullptr, sizeof(int32_t) * L.V);
         if (fused) {
@@ -299,7 +299,7 @@ int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d, 
 }
 
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
-                 const char *image, bool wait) {
+                 char *image, bool wait) {
     lbp_graph *g = nullptr;
     char *own_image = nullptr;  // built here when the caller brings none
     try {
@@ -326,10 +326,6 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
             graph_fill_image(L, own_image);  // compiled with its panels
             image = own_image;
         }
-        // one copy of every host piece (a single DMA when the image is
-        // page-locked), one fill for messages, beliefs, flag and scratch
-        hipError_t e = hipMemcpyAsync(g->dmem, image, gp.data_end, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemsetAsync(g->dmem + gp.data_end, 0, gp.total - gp.data_end, st);
         DevGraph &h = g->host;
         h.m = (float *)ptr(gp.m);
         h.mo = h.m;
@@ -360,7 +356,12 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         g->dgraph = (DevGraph *)ptr(gp.dg);
         g->q_tmp = (float *)ptr(gp.q);
         g->map_tmp = (int32_t *)ptr(gp.map);
-        if (e == hipSuccess) e = hipMemcpyAsync(g->dgraph, &g->host, sizeof(DevGraph), hipMemcpyHostToDevice, st);
+        // the descriptor travels in the image: one copy of every host piece
+        // (a single DMA when the image is page-locked), one fill for
+        // messages, beliefs, flag and scratch
+        std::memcpy(image + gp.p[gp.dg].off, &g->host, sizeof(DevGraph));
+        hipError_t e = hipMemcpyAsync(g->dmem, image, gp.data_end, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(g->dmem + gp.data_end, 0, gp.total - gp.data_end, st);
         DevGraph fv[2];
         if (gp.fused) {
             float *m2 = (float *)ptr(gp.m2);

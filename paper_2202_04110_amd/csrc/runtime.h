@@ -174,11 +174,12 @@ int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d =
 // Creates a graph from a compiled (and checked) layout.  mem: a 256-aligned
 // region of graph_device_bytes(L, with_fused) bytes the caller owns, or
 // nullptr to allocate.  image: the layout's host image, or nullptr to build
-// one here.  Copies run on `st`, and the call waits for them unless wait is
+// one here (the graph's device descriptor is written into it).  Copies run
+// on `st`, and the call waits for them unless wait is
 // false and the caller brings the image: then the image must outlive the
 // copies and work on other streams must wait for `st` before using the graph.
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
-                 const char *image = nullptr, bool wait = true);
+                 char *image = nullptr, bool wait = true);
 void graph_destroy(lbp_graph *g);
 
 // Read-out (beliefs and/or MAP) on `st`; host outputs are copied with
