@@ -653,3 +653,41 @@ def test_bench_launch_configuration_bitwise(lbp, ctx, name):
     np.testing.assert_array_equal(g.decode_map(), ref.decode_map())
     g.free()
     ref.free()
+
+
+def test_rbm_map_quality_gpu(lbp, ctx):
+    """The paper's small-RBM protocol on the HIP path: 20 RBMs of 15 + 15
+    binary units, 200 max-product iterations at damping 0.5, exact MAP by
+    enumeration.  Where the oracle's run has converged (final residual at
+    most 1e-6; loopy max-product need not converge, and then FP32 and FP64
+    trajectories part), the GPU's MAP equals the oracle's on every variable
+    with a clear top-2 margin; over all 20 it recovers the exact MAP about as
+    often as the oracle (a statistic; the paper reports 17 of 20 on RBMs of an
+    unstated distribution)."""
+    import brute
+    hits_gpu = hits_oracle = converged = 0
+    for r in range(20):
+        spec = W.random_rbm_small(1000 + r)
+        g = lbp.Graph(ctx, spec)
+        g.run_bp(200, 0.5, 0.0)
+        xg = g.decode_map()
+        g.free()
+        og = OracleGraph(spec)
+        mo, res = og.run(200, 0.5, 0.0, residuals=True)
+        _, qo, xo = og.beliefs(mo, 0.0)
+        off = spec.var_state_off()
+        if res[-1] <= 1e-6:
+            converged += 1
+            for v in range(spec.num_vars):
+                row = np.sort(qo[off[v]:off[v + 1]])
+                if row[-1] - row[-2] > MARGIN:
+                    assert xg[v] == xo[v], (r, v)
+        w = spec.log_potentials.reshape(-1, 4)[:, 3].astype(np.float64).reshape(15, 15)
+        b = spec.evidence.reshape(-1, 2)[:, 1].astype(np.float64)
+        _, best = brute.rbm_exact_map(15, 15, w, b[:15], b[15:])
+        hits_gpu += int(abs(og.score(xg.astype(np.int32)) - best) < 1e-9)
+        hits_oracle += int(abs(og.score(xo.astype(np.int32)) - best) < 1e-9)
+    print("exact MAP recovered on %d/20 RBMs (oracle %d/20); oracle converged on %d/20"
+          % (hits_gpu, hits_oracle, converged))
+    # runs that do not converge may end on different assignments either way
+    assert converged >= 5 and hits_gpu >= 5 and abs(hits_gpu - hits_oracle) <= 20 - converged + 1
