@@ -93,6 +93,28 @@ def measured_traffic(workload, kernel, shape):
     return k.get("bytes_per_launch")
 
 
+def plain_copy_gbps(mib=1024, reps=10):
+    """Read + write GB/s of a plain device-to-device copy of `mib` MiB (the
+    runtime's copy kernel), timed with HIP events: the bandwidth an ordinary
+    streaming kernel reaches on this machine, beside the nominal peak."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.empty(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(spec, iters_full, damping, temperature, budget_s=12.0):
     """The FP64 oracle on the host's cores, timed on a bounded number of
     iterations of the same graph; scaled to edge-state updates per second."""
@@ -110,10 +132,23 @@ def cpu_baseline(spec, iters_full, damping, temperature, budget_s=12.0):
     m = og.run(iters, damping, temperature, threads=cores)
     dt = og.last_seconds
     del m
+    # the same oracle on one core, on a shorter sample
+    iters1 = int(max(1, min(iters_full, 0.3 * budget_s / max(t1 * cores, 1e-6))))
+    m = og.run(iters1, damping, temperature, threads=1)
+    dt1 = og.last_seconds
+    del m
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": spec.num_edge_states * iters / dt, "unit": "edge-state updates/s", "cores": cores,
             "kind": "oracle",
             "sample": "%d of %d iterations of the same graph, FP64, OpenMP over variables and factors, "
-                      "%.2f s" % (iters, iters_full, dt)}
+                      "%.2f s" % (iters, iters_full, dt),
+            "one_core": {"value": spec.num_edge_states * iters1 / dt1, "sample": "%d iterations, %.2f s" % (iters1, dt1)},
+            "host_cpu": model, "host_cpus_visible": os.cpu_count()}
 
 
 def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
@@ -336,6 +371,7 @@ def main():
         tkey, shape = "variable", (vl[0]["wpb"], vl[0]["swizzle"]) if len(vl) == 1 else (None, None)
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, tkey, shape)
+    copy_gbps = plain_copy_gbps()
     out = {
         "metric": "edge-state message updates/sec",
         "value": value,
@@ -354,7 +390,9 @@ def main():
                    "temperature": T},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-                     "algorithmic_bytes_per_launch": kbytes, "avg_launch_ms": kms},
+                     "algorithmic_bytes_per_launch": kbytes, "avg_launch_ms": kms,
+                     "plain_copy_gbps": copy_gbps,
+                     "frac_of_plain_copy": achieved / copy_gbps if copy_gbps else None},
         "phases_ms": {"variable": t_var, "factor": t_fac, "two_phase_iteration": t_it, "fused_iteration": t_fused},
         "iteration_gbps": bm["iter_bytes"] / (t_it * 1e-3) / 1e9,
         "solve_gbps": bm["iter_bytes"] * iters / (ms_step * 1e-3) / 1e9,
