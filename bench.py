@@ -276,6 +276,45 @@ def sampling_leg(lbp, W, ctx, S, iters=1000, reps=3):
             "speedup_over_sequential": S * t1 / ts}
 
 
+def batch_leg(lbp, W, ctx, n, iters=50, reps=5, seed=5):
+    """n graphs of the served mix (Potts, side 16..256 log-uniform, 2..8
+    states, sum-product T=1, damping 0.5, `iters` iterations) advanced
+    together in one batch: two-phase iterations, fused iterations, and the
+    same graphs solved one after another."""
+    import torch
+
+    reqs = W.served_requests(n, seed=seed, backward_count=0)
+    specs = [W.request_graph(r) for r in reqs]
+    gs = [lbp.Graph(ctx, s) for s in specs]
+    b = lbp.Batch(ctx, gs)
+    es = sum(int(s.num_edge_states) for s in specs)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def lone():
+        for g in gs:
+            g.run_bp(iters, 0.5, 1.0)
+
+    t_lone = timed(lone)
+    t_two = timed(lambda: b.run_bp(iters, 0.5, 1.0))
+    b.use_fused(True)
+    t_fused = timed(lambda: b.run_bp(iters, 0.5, 1.0))
+    b.free()
+    for g in gs:
+        g.free()
+    return {"graphs": n, "iters": iters, "edge_states": es,
+            "one_after_another_ms": t_lone * 1e3, "batch_two_phase_ms": t_two * 1e3, "batch_fused_ms": t_fused * 1e3,
+            "edge_state_updates_per_s": {"one_after_another": es * iters / t_lone, "batch_two_phase": es * iters / t_two,
+                                         "batch_fused": es * iters / t_fused}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +330,8 @@ def main():
                     help="comma-separated HBM budgets of the served stream, in MiB")
     ap.add_argument("--samples", type=int, default=0, metavar="S",
                     help="also time S perturb-and-MAP samples of the deconvolution graph in shared launches")
+    ap.add_argument("--batch", type=int, default=0, metavar="N",
+                    help="batch leg: N served-mix graphs in one batch, two-phase and fused iterations")
     ap.add_argument("--gradient", action="store_true",
                     help="also time a recorded solve plus its reverse sweep against the forward solve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -410,6 +451,8 @@ def main():
         out["gradient"] = gradient_leg(lbp, W, ctx)
     if args.samples:
         out["sampling"] = sampling_leg(lbp, W, ctx, args.samples)
+    if args.batch:
+        out["batch"] = batch_leg(lbp, W, ctx, args.batch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, iters, d, T)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

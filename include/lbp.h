@@ -253,6 +253,11 @@ int lbp_run_bp_backward(lbp_graph *g, const float *grad_q, float *grad_logpot, f
 int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
                      lbp_batch **out);
 int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature);
+/* Fused iterations for a batch whose graphs all have them (see
+ * lbp_graph_use_fused): pairs of iterations run as single launches over
+ * every graph, with bitwise the same results.  LBP_E_INVALID if a graph has
+ * none.  Off by default. */
+int lbp_batch_use_fused(lbp_batch *b, int enable);
 void lbp_batch_free(lbp_batch *b);
 
 /*

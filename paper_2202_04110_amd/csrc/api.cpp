@@ -606,7 +606,7 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
         std::vector<WorkItem> mids, highs;
         for (int32_t gi = 0; gi < num_graphs; ++gi) add_to_lists(ll, gi, graphs[gi]->shape, &mids, &highs);
         finish_lists(ll, mids, highs);
-        const size_t gbytes = align256(sizeof(DevGraph) * std::max(1, num_graphs));
+        const size_t gbytes = align256(sizeof(DevGraph) * 3 * std::max(1, num_graphs));
         const size_t total = gbytes + lists_bytes(ll);
         b = new lbp_batch;
         b->ctx = ctx;
@@ -617,12 +617,28 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
             delete b;
             return fail(LBP_E_OOM, "batch allocation failed");
         }
+        // descriptors, then (when every graph has a fused form) each graph's
+        // m -> m2 view and then each graph's m2 -> m view
         std::vector<DevGraph> hg;
         for (int32_t gi = 0; gi < num_graphs; ++gi) hg.push_back(graphs[gi]->host);
+        bool fusable = num_graphs > 0;
+        for (int32_t gi = 0; gi < num_graphs; ++gi) fusable = fusable && graphs[gi]->m2;
+        if (fusable) {
+            for (int32_t gi = 0; gi < num_graphs; ++gi) {
+                hg.push_back(graphs[gi]->host);
+                hg.back().mo = graphs[gi]->m2;
+            }
+            for (int32_t gi = 0; gi < num_graphs; ++gi) {
+                hg.push_back(graphs[gi]->host);
+                hg.back().m = graphs[gi]->m2;
+                hg.back().mo = graphs[gi]->host.m;
+            }
+        }
         b->dgraphs = (DevGraph *)b->dmem;
+        b->fviews = fusable ? b->dgraphs + num_graphs : nullptr;
         hipStream_t st = ctx->stream;
         if (num_graphs)
-            e = hipMemcpyAsync(b->dgraphs, hg.data(), sizeof(DevGraph) * num_graphs, hipMemcpyHostToDevice, st);
+            e = hipMemcpyAsync(b->dgraphs, hg.data(), sizeof(DevGraph) * hg.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = upload_lists(ll, b->dmem + gbytes, st, &b->vl, &b->fl);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
@@ -646,7 +662,8 @@ int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature)
     std::string why;
     if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
     HIP_TRY(hipSetDevice(b->ctx->device));
-    hipError_t e = run_loop(b->ctx, b->loops, b->dgraphs, nullptr, b->vl, b->fl, iters, damping, temperature);
+    hipError_t e = run_loop(b->ctx, b->loops, b->dgraphs, b->use_fused ? b->fviews : nullptr, b->vl, b->fl, iters,
+                            damping, temperature, (int32_t)b->graphs.size());
     if (e != hipSuccess) return hip_error(e, "batch iteration launch");
     for (lbp_graph *g : b->graphs) {
         g->last_T = temperature;
@@ -752,6 +769,16 @@ void lbp_sampler_free(lbp_sampler *sp) {
     destroy_loops(sp->loops);
     (void)hipFree(sp->dmem);
     delete sp;
+}
+
+int lbp_batch_use_fused(lbp_batch *b, int enable) {
+    if (!b) return fail(LBP_E_INVALID, "batch is NULL");
+    if (enable && !b->fviews) return fail(LBP_E_INVALID, "not every graph of the batch has a fused iteration");
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    destroy_loops(b->loops);
+    b->use_fused = enable != 0;
+    return LBP_OK;
 }
 
 void lbp_batch_free(lbp_batch *b) {

@@ -157,14 +157,15 @@ hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, c
 }
 
 hipError_t launch_loop(const DevGraph *gs, const DevGraph *fused, const std::vector<Launch> &vl,
-                       const std::vector<Launch> &fl, int32_t iters, const TParams &P, bool maxp, hipStream_t st) {
+                       const std::vector<Launch> &fl, int32_t iters, const TParams &P, bool maxp, hipStream_t st,
+                       int32_t fused_stride) {
     hipError_t e = hipSuccess;
     int32_t it = 0;
     if (fused)
         for (; it + 1 < iters && e == hipSuccess; it += 2)
             for (int h = 0; h < 2 && e == hipSuccess; ++h)
                 for (const Launch &L : fl) {
-                    e = launch_pair(fused + h, L.items, L.n, L.a, L.b, maxp, P, L.fshape, st, true);
+                    e = launch_pair(fused + h * fused_stride, L.items, L.n, L.a, L.b, maxp, P, L.fshape, st, true);
                     if (e != hipSuccess) break;
                 }
     for (; it < iters && e == hipSuccess; ++it) e = launch_iteration(gs, vl, fl, P, maxp, st);
@@ -182,12 +183,13 @@ void destroy_loops(std::vector<CachedLoop> &v) {
 }
 
 hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const DevGraph *fused,
-                    const std::vector<Launch> &vl, const std::vector<Launch> &fl, int32_t iters, float d, float T) {
+                    const std::vector<Launch> &vl, const std::vector<Launch> &fl, int32_t iters, float d, float T,
+                    int32_t fused_stride) {
     const TParams P = make_params(d, T);
     const bool maxp = T == 0.0f;
     const size_t per_iter = vl.size() + fl.size();
     if (!ctx->use_graphs || iters < 2 || per_iter == 0)
-        return launch_loop(gs, fused, vl, fl, iters, P, maxp, ctx->stream);
+        return launch_loop(gs, fused, vl, fl, iters, P, maxp, ctx->stream, fused_stride);
     for (const CachedLoop &c : cache)
         if (c.iters == iters && c.d == d && c.T == T) return hipGraphLaunch(c.exec, ctx->stream);
     if (!ctx->capture) {
@@ -196,7 +198,7 @@ hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph
     }
     hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = launch_loop(gs, fused, vl, fl, iters, P, maxp, ctx->capture);
+    hipError_t le = launch_loop(gs, fused, vl, fl, iters, P, maxp, ctx->capture, fused_stride);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -371,6 +373,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
             fv[1].m = m2;
             fv[1].mo = g->host.m;
             g->fused = (DevGraph *)ptr(gp.fdg);
+            g->m2 = m2;
             if (e == hipSuccess) e = hipMemcpyAsync(g->fused, fv, sizeof(fv), hipMemcpyHostToDevice, st);
         }
         describe_lists(gp.ll, (char *)ptr(gp.items), &g->vl, &g->fl);

@@ -66,12 +66,14 @@ hipError_t upload_lists(const LaunchLists &ll, char *mem, hipStream_t st, std::v
 
 hipError_t launch_iteration(const DevGraph *gs, const std::vector<Launch> &vl, const std::vector<Launch> &fl,
                             const TParams &P, bool maxp, hipStream_t st, int phases = 3);
-// `iters` iterations of a fusable graph: pairs of fused iterations through
-// the second message buffer (fused[0]: m -> m2, fused[1]: m2 -> m), then one
-// two-phase in-place iteration on gs if iters is odd, so the messages end in
-// the graph's own buffer.  Bitwise the same as two-phase iterations.
+// `iters` iterations of fusable graphs: pairs of fused iterations through
+// the second message buffers (fused[g]: graph g's m -> m2 view,
+// fused[stride + g]: its m2 -> m view; stride = the number of graphs), then
+// one two-phase in-place iteration on gs if iters is odd, so the messages end
+// in each graph's own buffer.  Bitwise the same as two-phase iterations.
 hipError_t launch_loop(const DevGraph *gs, const DevGraph *fused, const std::vector<Launch> &vl,
-                       const std::vector<Launch> &fl, int32_t iters, const TParams &P, bool maxp, hipStream_t st);
+                       const std::vector<Launch> &fl, int32_t iters, const TParams &P, bool maxp, hipStream_t st,
+                       int32_t fused_stride = 1);
 
 // A captured fixed-iteration loop, replayed with hipGraphLaunch.
 struct CachedLoop {
@@ -107,6 +109,7 @@ struct lbp_graph {
     lbp::DevGraph host{};             // device pointers, host copy
     lbp::DevGraph *dgraph = nullptr;  // device copy
     lbp::DevGraph *fused = nullptr;   // device [2]: fused views over the two message buffers, or null
+    float *m2 = nullptr;              // the second message buffer of a fusable graph (device), or null
     bool use_fused = false;           // lbp_run_bp runs fused iterations (chosen by the autotuner)
     float *q_tmp = nullptr;           // VS
     int32_t *map_tmp = nullptr;       // V
@@ -137,6 +140,8 @@ struct lbp_batch {
     std::vector<lbp_graph *> graphs;
     char *dmem = nullptr;
     lbp::DevGraph *dgraphs = nullptr;
+    lbp::DevGraph *fviews = nullptr;  // device [2 * graphs]: every graph's fused views, when all are fusable
+    bool use_fused = false;
     std::vector<lbp::Launch> vl, fl;
     std::vector<lbp::CachedLoop> loops;
 };
@@ -159,7 +164,8 @@ namespace lbp {
 // launching each kernel.
 // fused: the graph's fused views (nullptr for two-phase iterations).
 hipError_t run_loop(lbp_ctx *ctx, std::vector<CachedLoop> &cache, const DevGraph *gs, const DevGraph *fused,
-                    const std::vector<Launch> &vl, const std::vector<Launch> &fl, int32_t iters, float d, float T);
+                    const std::vector<Launch> &vl, const std::vector<Launch> &fl, int32_t iters, float d, float T,
+                    int32_t fused_stride = 1);
 
 // Device bytes an uploaded layout occupies (with_fused: plus the second
 // message buffer and views of the fused iteration, if the layout allows it).

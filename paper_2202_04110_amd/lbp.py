@@ -84,6 +84,7 @@ _sig("lbp_run_bp_record", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_int
 _sig("lbp_run_bp_backward", C.c_int, [_P, _P, _P, _P])
 _sig("lbp_batch_create", C.c_int, [_P, _P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_batch_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
+_sig("lbp_batch_use_fused", C.c_int, [_P, C.c_int])
 _sig("lbp_batch_free", None, [_P])
 _sig("lbp_run_bp_until", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32,
                                    C.POINTER(C.c_int32), C.POINTER(C.c_float)])
@@ -380,6 +381,10 @@ class Batch:
 
     def run_bp(self, iters: int, damping: float, temperature: float):
         check(_lib.lbp_batch_run(self.h, int(iters), float(damping), float(temperature)))
+
+    def use_fused(self, enable: bool):
+        """Fused iterations over every graph (all must be fusable)."""
+        check(_lib.lbp_batch_use_fused(self.h, int(bool(enable))))
 
     def free(self):
         if getattr(self, "h", None):

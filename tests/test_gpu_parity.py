@@ -579,6 +579,44 @@ def test_fused_iterations_match_two_phase(lbp, ctx):
         mg.use_fused(True)
 
 
+def test_fused_batches_match_lone_runs(lbp, ctx):
+    """A batch of fusable graphs of different sizes and state counts runs
+    fused iterations over all of them (pairs of iterations in single
+    launches through each graph's second buffer): bitwise the messages,
+    beliefs and MAP of each graph run alone, for even and odd counts; a batch
+    with a graph that has no fused form refuses them."""
+    specs = [W.potts_grid(33, 3, 201), W.potts_grid(50, 5, 202), W.ising_grid(40, 203),
+             W.potts_grid(20, 8, 204), W.random_pairwise(205, 2000, 6000, 4)]
+    for T in (1.0, 0.0):
+        gs = [lbp.Graph(ctx, s) for s in specs]
+        b = lbp.Batch(ctx, gs)
+        b.use_fused(True)
+        for iters in (1, 2, 7, 10):
+            for g in gs:
+                g.reset_messages()
+            b.run_bp(iters, 0.5, T)
+            for s, g in zip(specs, gs):
+                lone = lbp.Graph(ctx, s)
+                lone.run_bp(iters, 0.5, T)
+                np.testing.assert_array_equal(g.get_messages(), lone.get_messages())
+                if iters == 7:
+                    np.testing.assert_array_equal(g.get_beliefs(), lone.get_beliefs())
+                    np.testing.assert_array_equal(g.decode_map(), lone.decode_map())
+                lone.free()
+        b.use_fused(False)
+        b.free()
+        for g in gs:
+            g.free()
+    mg = lbp.Graph(ctx, mixed_graph(104))
+    pg = lbp.Graph(ctx, W.potts_grid(10, 3, 206))
+    b = lbp.Batch(ctx, [pg, mg])
+    with pytest.raises(lbp.LBPError):
+        b.use_fused(True)
+    b.free()
+    mg.free()
+    pg.free()
+
+
 def test_binding_imported_before_torch():
     """The binding loads torch before the library, so both share one HIP
     runtime whatever the caller imported first."""
