@@ -605,7 +605,7 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
         LaunchLists ll;
         std::vector<WorkItem> mids, highs;
         for (int32_t gi = 0; gi < num_graphs; ++gi) add_to_lists(ll, gi, graphs[gi]->shape, &mids, &highs);
-        finish_lists(ll, mids, highs);
+        finish_lists(ll, mids, highs, true);
         const size_t gbytes = align256(sizeof(DevGraph) * 3 * std::max(1, num_graphs));
         const size_t total = gbytes + lists_bytes(ll);
         b = new lbp_batch;

@@ -490,6 +490,30 @@ __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, c
     pair_tile<NA, NB, EXACT, MAXP, FUSED, EARLY>(G, ft, lane_id(), P);
 }
 
+// Square pairwise tiles of several state counts (2..8) in one launch: each
+// wavefront branches on its tile's state count (uniform across the
+// wavefront) to that count's exact tile code, so a tile gets the same bits as
+// in its own class's launch.
+template <bool MAXP, bool FUSED, bool EARLY>
+__global__ __launch_bounds__(256) void k_pair_mix(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
+                                                  int nitems, TParams P, int swz) {
+    const int w = wave_item(swz);
+    if (w >= nitems) return;
+    const WorkItem it = items[w];
+    const DevGraph &G = gs[it.g];
+    const FTile ft = G.ftile[it.t];
+    const int lane = lane_id();
+    switch (__builtin_amdgcn_readfirstlane(ft.a)) {
+    case 2: pair_tile<2, 2, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    case 3: pair_tile<3, 3, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    case 4: pair_tile<4, 4, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    case 5: pair_tile<5, 5, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    case 6: pair_tile<6, 6, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    case 7: pair_tile<7, 7, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    default: pair_tile<8, 8, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    }
+}
+
 // --------------------------------------------------------------------------
 // factor phase: OR / AND, closed forms (PGMax Sec. "Package features":
 // logical factors with updates linear in their arity)
@@ -1430,6 +1454,10 @@ static void pair_dispatch(const DevGraph *gs, const WorkItem *items, int n, int 
         }
     }
 #undef PAIR_CASE
+    if (na == 0) {
+        hipLaunchKernelGGL((k_pair_mix<MAXP, FUSED, EARLY>), grid, block, 0, st, gs, items, n, P, z);
+        return;
+    }
     if (!FUSED)
         hipLaunchKernelGGL((k_pair<kPairStatesMax, kPairStatesMax, false, MAXP, false, false>), grid, block, 0, st,
                            gs, items, n, P, z);
@@ -1438,7 +1466,9 @@ static void pair_dispatch(const DevGraph *gs, const WorkItem *items, int n, int 
 hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, bool maxp,
                        const TParams &P, const LaunchShape &S, hipStream_t st, bool fused) {
     if (n <= 0) return hipSuccess;
-    if (fused && (na != nb || na < 2 || na > kPairStatesMax)) return hipErrorInvalidValue;
+    // na = nb = 0: a mixed launch of square tiles of 2..kPairStatesMax states
+    if (na != nb && (na == 0 || nb == 0)) return hipErrorInvalidValue;
+    if (fused && na != 0 && (na != nb || na < 2 || na > kPairStatesMax)) return hipErrorInvalidValue;
     if (fused && S.early) {
         if (maxp) pair_dispatch<true, true, true>(gs, items, n, na, nb, P, S, st);
         else pair_dispatch<false, true, true>(gs, items, n, na, nb, P, S, st);
@@ -1569,6 +1599,7 @@ hipError_t launch_logpot_in(const DevGraph *gs, int F, const float *in, hipStrea
 hipError_t launch_pair_adj(const DevGraph *gs, const WorkItem *items, int n, int na, int nb, const TParams &P,
                            const AdjBufs &J, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (na <= 0 || nb <= 0) return hipErrorInvalidValue;  // mixed launches are forward only
     dim3 grid(blocks_for(n, 4)), block(256);
     if (na == nb && na >= 2 && na <= 8) {
         switch (na) {

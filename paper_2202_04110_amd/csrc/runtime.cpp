@@ -70,7 +70,51 @@ void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<
     }
 }
 
-void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs) {
+namespace {
+void merge_lists(LaunchLists &ll) {
+    std::vector<size_t> sq;
+    for (size_t i = 0; i < ll.fshape.size(); ++i) {
+        const FGroup &f = ll.fshape[i];
+        if (f.kind == TK_PAIR && f.a == f.b && f.a >= 2 && f.a <= kPairStatesMax) sq.push_back(i);
+    }
+    if (sq.size() > 1) {
+        std::vector<FGroup> shape;
+        std::vector<std::vector<WorkItem>> items;
+        FGroup mixed;
+        mixed.kind = TK_PAIR;
+        mixed.a = mixed.b = 0;
+        shape.push_back(mixed);
+        items.emplace_back();
+        size_t k = 0;
+        for (size_t i = 0; i < ll.fshape.size(); ++i) {
+            if (k < sq.size() && sq[k] == i) {
+                items[0].insert(items[0].end(), ll.fitems[i].begin(), ll.fitems[i].end());
+                ++k;
+            } else {
+                shape.push_back(ll.fshape[i]);
+                items.push_back(std::move(ll.fitems[i]));
+            }
+        }
+        ll.fshape = std::move(shape);
+        ll.fitems = std::move(items);
+    }
+    bool small = ll.vbucket.size() > 1;
+    int32_t top = 0;
+    for (int32_t b : ll.vbucket) {
+        small = small && b <= 8;
+        top = std::max(top, b);
+    }
+    if (small) {
+        std::vector<WorkItem> all;
+        for (const auto &v : ll.vitems) all.insert(all.end(), v.begin(), v.end());
+        ll.vbucket.assign(1, top);
+        ll.vitems.assign(1, std::move(all));
+    }
+}
+}  // namespace
+
+void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs, bool merge) {
+    if (merge) merge_lists(ll);
     if (mids.empty() && highs.empty()) return;
     if (ll.vbucket.empty()) {
         ll.vbucket.push_back(2);

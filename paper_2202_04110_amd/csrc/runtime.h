@@ -53,7 +53,12 @@ struct LaunchLists {
 struct GraphShape;  // below
 void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<WorkItem> *mids,
                   std::vector<WorkItem> *highs);
-void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs);
+// merge (lists of several graphs): square pairwise launches of 2..8 states
+// become one mixed launch (a = b = 0; each wavefront takes its tile's own
+// state count), and variable launches of buckets up to 8 become one launch
+// of the largest bucket, so graphs of different state counts share launches.
+// The arithmetic of each element is unchanged.
+void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs, bool merge = false);
 // Device bytes of the lists' work items (one 256-aligned piece per launch).
 size_t lists_bytes(const LaunchLists &ll);
 // Launch descriptors of lists whose items sit at device address `mem`.

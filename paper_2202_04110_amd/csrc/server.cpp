@@ -607,7 +607,7 @@ private:
             for (Request *r : active)
                 if (r->d == parts_[i].d && r->T == parts_[i].T)
                     add_to_lists(parts_[i].ll, gi++, r->g->shape, &mids[i], &highs[i]);
-            finish_lists(parts_[i].ll, mids[i], highs[i]);
+            finish_lists(parts_[i].ll, mids[i], highs[i], true);
             total += align256(sizeof(DevGraph) * parts_[i].hgs.size()) + lists_bytes(parts_[i].ll);
         }
         if (total > stage_bytes_) {
