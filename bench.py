@@ -279,8 +279,8 @@ def sampling_leg(lbp, W, ctx, S, iters=1000, reps=3):
 def batch_leg(lbp, W, ctx, n, iters=50, reps=5, seed=5):
     """n graphs of the served mix (Potts, side 16..256 log-uniform, 2..8
     states, sum-product T=1, damping 0.5, `iters` iterations) advanced
-    together in one batch: two-phase iterations, fused iterations, and the
-    same graphs solved one after another."""
+    together in one batch: two-phase iterations, fused iterations, after
+    lbp_batch_autotune, and the same graphs solved one after another."""
     import torch
 
     reqs = W.served_requests(n, seed=seed, backward_count=0)
@@ -306,13 +306,16 @@ def batch_leg(lbp, W, ctx, n, iters=50, reps=5, seed=5):
     t_two = timed(lambda: b.run_bp(iters, 0.5, 1.0))
     b.use_fused(True)
     t_fused = timed(lambda: b.run_bp(iters, 0.5, 1.0))
+    tuned_fused = b.autotune(0.5, 1.0, reps=10)
+    t_tuned = timed(lambda: b.run_bp(iters, 0.5, 1.0))
     b.free()
     for g in gs:
         g.free()
     return {"graphs": n, "iters": iters, "edge_states": es,
             "one_after_another_ms": t_lone * 1e3, "batch_two_phase_ms": t_two * 1e3, "batch_fused_ms": t_fused * 1e3,
+            "batch_autotuned_ms": t_tuned * 1e3, "autotune_chose_fused": tuned_fused,
             "edge_state_updates_per_s": {"one_after_another": es * iters / t_lone, "batch_two_phase": es * iters / t_two,
-                                         "batch_fused": es * iters / t_fused}}
+                                         "batch_fused": es * iters / t_fused, "batch_autotuned": es * iters / t_tuned}}
 
 
 def main():

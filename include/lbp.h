@@ -249,6 +249,9 @@ int lbp_run_bp_backward(lbp_graph *g, const float *grad_q, float *grad_logpot, f
  * context and advances all of them in shared kernel launches; each graph's
  * arithmetic is the same as when it runs alone, so results are bitwise
  * identical.  The batch does not own its graphs, which must outlive it.
+ * Square pairwise factors of 2..8 states share one launch whatever their
+ * state count, and so do the variables of up to 8 states, so graphs of
+ * different state counts still advance in two launches per iteration.
  */
 int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
                      lbp_batch **out);
@@ -258,6 +261,13 @@ int lbp_batch_run(lbp_batch *b, int32_t iters, float damping, float temperature)
  * every graph, with bitwise the same results.  LBP_E_INVALID if a graph has
  * none.  Off by default. */
 int lbp_batch_use_fused(lbp_batch *b, int enable);
+/* Times the batch's launch shapes as lbp_autotune does for a graph (reps
+ * timed launches per candidate) and keeps the fastest; when every graph has
+ * fused iterations, also tunes their shapes and switches the batch to fused
+ * or two-phase iterations, whichever is faster (*fused_out, if not NULL: 1 if
+ * fused).  Every graph's messages are restored before return.  Shapes never
+ * change results.  Synchronises the context's stream. */
+int lbp_batch_autotune(lbp_batch *b, float damping, float temperature, int32_t reps, int32_t *fused_out);
 void lbp_batch_free(lbp_batch *b);
 
 /*

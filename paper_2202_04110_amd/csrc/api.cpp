@@ -413,6 +413,51 @@ int tune_launches(const DevGraph *gs, std::vector<Launch> &vl, std::vector<Launc
     return LBP_OK;
 }
 
+// The fused launches' own shapes (waves per block x variant), then fused or
+// two-phase iterations, whichever is faster: *use_fused.  gs / fused /
+// stride as for launch_loop.  Moves the messages (the caller restores them).
+int tune_fused(const DevGraph *gs, const DevGraph *fused, int32_t stride, const std::vector<Launch> &vl,
+               std::vector<Launch> &fl, float d, float T, int reps, hipStream_t st, bool *use_fused) {
+    const TParams P = make_params(d, T);
+    const bool maxp = T == 0.0f;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    auto time_loop = [&](const DevGraph *fz, float *ms) {
+        hipError_t x = launch_loop(gs, fz, vl, fl, 2, P, maxp, st, stride);  // warm-up
+        if (x == hipSuccess) x = hipEventRecord(a, st);
+        if (x == hipSuccess) x = launch_loop(gs, fz, vl, fl, 2 * reps, P, maxp, st, stride);
+        if (x == hipSuccess) x = hipEventRecord(b, st);
+        if (x == hipSuccess) x = hipEventSynchronize(b);
+        if (x == hipSuccess) x = hipEventElapsedTime(ms, a, b);
+        return x;
+    };
+    for (Launch &L : fl) {
+        LaunchShape best = L.fshape;
+        float best_t = 1e30f;
+        for (int w : {1, 2, 4})
+            for (int v : {0, 1, 2, 3}) {
+                if (e != hipSuccess) break;
+                L.fshape = LaunchShape{w, v & 1, v >> 1};
+                float ms = 0.0f;
+                e = time_loop(fused, &ms);
+                if (e == hipSuccess && ms < best_t) {
+                    best_t = ms;
+                    best = L.fshape;
+                }
+            }
+        L.fshape = best;
+    }
+    float t2 = 0.0f, tf = 0.0f;
+    if (e == hipSuccess) e = time_loop(nullptr, &t2);
+    if (e == hipSuccess) e = time_loop(fused, &tf);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_error(e, "autotune fused");
+    *use_fused = tf < t2;
+    return LBP_OK;
+}
+
 }  // namespace
 
 int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out) {
@@ -501,47 +546,8 @@ int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, f
     e = hipMemcpyAsync(save, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
     int rc = e == hipSuccess ? tune_launches(g->dgraph, g->vl, g->fl, damping, temperature, reps, st, best_ms_out)
                              : hip_error(e, "autotune backup");
-    if (rc == LBP_OK && g->fused) {
-        // the fused variant's own shapes, then fused or two-phase iterations,
-        // whichever is faster on this graph
-        const TParams P = make_params(damping, temperature);
-        const bool maxp = temperature == 0.0f;
-        hipEvent_t a = nullptr, b = nullptr;
-        e = hipEventCreate(&a);
-        if (e == hipSuccess) e = hipEventCreate(&b);
-        auto time_loop = [&](const DevGraph *fz, float *ms) {
-            hipError_t x = launch_loop(g->dgraph, fz, g->vl, g->fl, 2, P, maxp, st);  // warm-up
-            if (x == hipSuccess) x = hipEventRecord(a, st);
-            if (x == hipSuccess) x = launch_loop(g->dgraph, fz, g->vl, g->fl, 2 * reps, P, maxp, st);
-            if (x == hipSuccess) x = hipEventRecord(b, st);
-            if (x == hipSuccess) x = hipEventSynchronize(b);
-            if (x == hipSuccess) x = hipEventElapsedTime(ms, a, b);
-            return x;
-        };
-        for (Launch &L : g->fl) {
-            LaunchShape best = L.fshape;
-            float best_t = 1e30f;
-            for (int w : {1, 2, 4})
-                for (int v : {0, 1, 2, 3}) {
-                    if (e != hipSuccess) break;
-                    L.fshape = LaunchShape{w, v & 1, v >> 1};
-                    float ms = 0.0f;
-                    e = time_loop(g->fused, &ms);
-                    if (e == hipSuccess && ms < best_t) {
-                        best_t = ms;
-                        best = L.fshape;
-                    }
-                }
-            L.fshape = best;
-        }
-        float t2 = 0.0f, tf = 0.0f;
-        if (e == hipSuccess) e = time_loop(nullptr, &t2);
-        if (e == hipSuccess) e = time_loop(g->fused, &tf);
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-        if (e != hipSuccess) rc = hip_error(e, "autotune fused");
-        else g->use_fused = tf < t2;
-    }
+    if (rc == LBP_OK && g->fused)
+        rc = tune_fused(g->dgraph, g->fused, 1, g->vl, g->fl, damping, temperature, reps, st, &g->use_fused);
     e = hipMemcpyAsync(g->host.m, save, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(save);
@@ -769,6 +775,50 @@ void lbp_sampler_free(lbp_sampler *sp) {
     destroy_loops(sp->loops);
     (void)hipFree(sp->dmem);
     delete sp;
+}
+
+int lbp_batch_autotune(lbp_batch *b, float damping, float temperature, int32_t reps, int32_t *fused_out) {
+    if (!b) return fail(LBP_E_INVALID, "batch is NULL");
+    std::string why;
+    if (!valid_params(0, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
+    if (reps < 1) return fail(LBP_E_INVALID, "reps must be >= 1");
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    // the timed launches update every graph's messages: keep and restore them
+    int64_t total = 0;
+    for (lbp_graph *g : b->graphs) total += g->M;
+    float *save = nullptr;
+    hipError_t e = hipMalloc((void **)&save, sizeof(float) * (size_t)std::max<int64_t>(1, total));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBP_E_OOM, "autotune message backup");
+    }
+    int64_t off = 0;
+    for (lbp_graph *g : b->graphs) {
+        if (e == hipSuccess && g->M)
+            e = hipMemcpyAsync(save + off, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
+        off += g->M;
+    }
+    int rc = e == hipSuccess ? tune_launches(b->dgraphs, b->vl, b->fl, damping, temperature, reps, st, nullptr)
+                             : hip_error(e, "autotune backup");
+    if (rc == LBP_OK && b->fviews)
+        rc = tune_fused(b->dgraphs, b->fviews, (int32_t)b->graphs.size(), b->vl, b->fl, damping, temperature, reps,
+                        st, &b->use_fused);
+    off = 0;
+    e = hipSuccess;
+    for (lbp_graph *g : b->graphs) {
+        if (e == hipSuccess && g->M)
+            e = hipMemcpyAsync(g->host.m, save + off, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
+        off += g->M;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    else (void)hipStreamSynchronize(st);
+    (void)hipFree(save);
+    destroy_loops(b->loops);
+    if (rc != LBP_OK) return rc;
+    if (e != hipSuccess) return hip_error(e, "autotune restore");
+    if (fused_out) *fused_out = b->use_fused;
+    return LBP_OK;
 }
 
 int lbp_batch_use_fused(lbp_batch *b, int enable) {

@@ -85,6 +85,7 @@ _sig("lbp_run_bp_backward", C.c_int, [_P, _P, _P, _P])
 _sig("lbp_batch_create", C.c_int, [_P, _P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_batch_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float])
 _sig("lbp_batch_use_fused", C.c_int, [_P, C.c_int])
+_sig("lbp_batch_autotune", C.c_int, [_P, C.c_float, C.c_float, C.c_int32, C.POINTER(C.c_int32)])
 _sig("lbp_batch_free", None, [_P])
 _sig("lbp_run_bp_until", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32,
                                    C.POINTER(C.c_int32), C.POINTER(C.c_float)])
@@ -385,6 +386,13 @@ class Batch:
     def use_fused(self, enable: bool):
         """Fused iterations over every graph (all must be fusable)."""
         check(_lib.lbp_batch_use_fused(self.h, int(bool(enable))))
+
+    def autotune(self, damping: float, temperature: float, reps: int = 20) -> bool:
+        """Tunes the batch's launch shapes (and fused vs two-phase iterations
+        when every graph has them); returns whether fused iterations won."""
+        fused = C.c_int32(0)
+        check(_lib.lbp_batch_autotune(self.h, float(damping), float(temperature), int(reps), C.byref(fused)))
+        return bool(fused.value)
 
     def free(self):
         if getattr(self, "h", None):

@@ -142,6 +142,8 @@ def test_null_handles_are_rejected(lbp):
                L.lbp_sampler_create(None, 4, C.byref(out)),
                L.lbp_sampler_run(None, 1, 0.5, 0.0, None, None, None),
                L.lbp_batch_run(None, 1, 0.5, 1.0),
+               L.lbp_batch_use_fused(None, 1),
+               L.lbp_batch_autotune(None, 0.5, 1.0, 3, C.byref(n)),
                L.lbp_graph_num_launches(None, C.byref(n)),
                L.lbp_graph_use_fused(None, 1),
                L.lbp_reset_messages(None),

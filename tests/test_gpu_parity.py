@@ -617,6 +617,49 @@ def test_fused_batches_match_lone_runs(lbp, ctx):
     pg.free()
 
 
+def test_batch_autotune_keeps_results(lbp, ctx):
+    """lbp_batch_autotune restores every graph's messages bitwise, and the
+    batch then still gives each graph's lone results bitwise, whichever shapes
+    and iteration form it chose; a batch with a graph that has no fused form
+    stays two-phase."""
+    specs = [W.potts_grid(33, 3, 211), W.potts_grid(50, 5, 212), W.ising_grid(40, 213),
+             W.potts_grid(20, 8, 214), W.random_pairwise(215, 2000, 6000, 4)]
+    gs = [lbp.Graph(ctx, s) for s in specs]
+    b = lbp.Batch(ctx, gs)
+    b.run_bp(3, 0.5, 1.0)
+    before = [g.get_messages() for g in gs]
+    fused = b.autotune(0.5, 1.0, reps=3)
+    assert isinstance(fused, bool)
+    for g, m in zip(gs, before):
+        np.testing.assert_array_equal(g.get_messages(), m)
+    for T in (1.0, 0.0):
+        for iters in (4, 9):
+            for g in gs:
+                g.reset_messages()
+            b.run_bp(iters, 0.5, T)
+            for s, g in zip(specs, gs):
+                lone = lbp.Graph(ctx, s)
+                lone.run_bp(iters, 0.5, T)
+                np.testing.assert_array_equal(g.get_messages(), lone.get_messages())
+                lone.free()
+    b.free()
+    for g in gs:
+        g.free()
+    mg = lbp.Graph(ctx, mixed_graph(105))
+    pg = lbp.Graph(ctx, W.potts_grid(10, 3, 216))
+    b = lbp.Batch(ctx, [pg, mg])
+    assert b.autotune(0.5, 0.0, reps=2) is False
+    b.run_bp(6, 0.5, 0.0)
+    for s, g in ((W.potts_grid(10, 3, 216), pg), (mixed_graph(105), mg)):
+        lone = lbp.Graph(ctx, s)
+        lone.run_bp(6, 0.5, 0.0)
+        np.testing.assert_array_equal(g.get_messages(), lone.get_messages())
+        lone.free()
+    b.free()
+    mg.free()
+    pg.free()
+
+
 def test_binding_imported_before_torch():
     """The binding loads torch before the library, so both share one HIP
     runtime whatever the caller imported first."""
