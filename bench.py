@@ -318,6 +318,42 @@ def batch_leg(lbp, W, ctx, n, iters=50, reps=5, seed=5):
                                          "batch_fused": es * iters / t_fused, "batch_autotuned": es * iters / t_tuned}}
 
 
+def paper_rbm_leg(lbp, W, ctx, runs=10):
+    """The paper's timing protocol on MAP inference: fully connected binary
+    RBMs of 40, 60, ..., 200 units (half visible, half hidden), max-product,
+    200 iterations, damping 0.5, each time the mean of `runs` solves.  A solve
+    is reset messages + 200 iterations + MAP decode copied to the host, with
+    the graph resident in HBM; the second figure also uploads the graph (and
+    captures its loop) every time."""
+    import torch
+
+    out = {}
+    for units in range(40, 201, 20):
+        spec = W.rbm(units // 2, units // 2, seed=units)
+        g = lbp.Graph(ctx, spec)
+        g.run_bp(200, 0.5, 0.0)
+        g.decode_map()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            g.reset_messages()
+            g.run_bp(200, 0.5, 0.0)
+            g.decode_map()
+        t_res = (time.perf_counter() - t0) / runs
+        g.free()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            h = lbp.Graph(ctx, spec)
+            h.run_bp(200, 0.5, 0.0)
+            h.decode_map()
+            h.free()
+        t_up = (time.perf_counter() - t0) / runs
+        es = int(spec.num_edge_states)
+        out[str(units)] = {"edge_states": es, "solve_ms": t_res * 1e3, "upload_and_solve_ms": t_up * 1e3,
+                           "edge_state_updates_per_s": es * 200 / t_res}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +371,8 @@ def main():
                     help="also time S perturb-and-MAP samples of the deconvolution graph in shared launches")
     ap.add_argument("--batch", type=int, default=0, metavar="N",
                     help="batch leg: N served-mix graphs in one batch, two-phase and fused iterations")
+    ap.add_argument("--paper-rbm", action="store_true",
+                    help="the paper's MAP timing protocol: RBMs of 40..200 units, 200 max-product iterations")
     ap.add_argument("--gradient", action="store_true",
                     help="also time a recorded solve plus its reverse sweep against the forward solve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -456,6 +494,8 @@ def main():
         out["sampling"] = sampling_leg(lbp, W, ctx, args.samples)
     if args.batch:
         out["batch"] = batch_leg(lbp, W, ctx, args.batch)
+    if args.paper_rbm:
+        out["paper_rbm"] = paper_rbm_leg(lbp, W, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, iters, d, T)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
