@@ -512,7 +512,8 @@ size_t adjoint_bytes(int64_t M, int64_t VB, int64_t P, int32_t iters, int32_t ck
     return AdjLayout((size_t)M, (size_t)VB, (size_t)P, nseg, k).total;
 }
 
-int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_every, char *mem, hipStream_t st) {
+int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_every, char *mem, hipStream_t st,
+                    std::vector<DevGraph> *staging) {
     auto &J = g->adj;
     J.valid = false;
     int32_t k, nseg;
@@ -557,7 +558,9 @@ int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_
     HIP_TRY(hipMemsetAsync(J.seg, 0, sizeof(float) * M * k, st));
     HIP_TRY(hipMemsetAsync(J.nbar, 0, sizeof(float) * M, st));
     HIP_TRY(hipMemsetAsync(J.zeros, 0, sizeof(float) * VB, st));
-    std::vector<DevGraph> views(k + 2, g->host);
+    std::vector<DevGraph> local;
+    std::vector<DevGraph> &views = staging ? *staging : local;
+    views.assign(k + 2, g->host);
     for (int32_t j = 0; j < k; ++j) {
         views[j].m = J.seg + M * j;
         views[j].mo = J.seg + M * std::min(j + 1, k - 1);
@@ -569,7 +572,7 @@ int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_
     views[k + 1].theta = J.zeros;
     views[k + 1].B = J.Bbar;
     HIP_TRY(hipMemcpyAsync(J.views, views.data(), sizeof(DevGraph) * (k + 2), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));  // the host staging of the views must outlive its copy
+    if (!staging) HIP_TRY(hipStreamSynchronize(st));  // the local staging must outlive its copy
     J.iters = iters;
     J.k = k;
     J.nseg = nseg;

@@ -201,8 +201,12 @@ int graph_readout(lbp_graph *g, float *q, int normalized, int32_t *map, bool out
 size_t adjoint_bytes(int64_t M, int64_t VB, int64_t P, int32_t iters, int32_t ckpt_every);
 // Sets up the workspace (mem: adjoint_bytes(...) bytes owned by the caller,
 // or nullptr to allocate) and the views for a record of (iters, d, T, k);
-// marks the record invalid until adjoint_finish_record.
-int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_every, char *mem, hipStream_t st);
+// marks the record invalid until adjoint_finish_record.  The views are
+// staged in `staging` when given (host memory the caller keeps until the
+// copies queued on st have completed; nothing waits here), else in a local
+// buffer and st is synchronised.
+int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_every, char *mem, hipStream_t st,
+                    std::vector<DevGraph> *staging = nullptr);
 // Copies the current messages into checkpoint `seg` on `st`.
 int adjoint_checkpoint(lbp_graph *g, int32_t seg, hipStream_t st);
 void adjoint_finish_record(lbp_graph *g);

@@ -109,6 +109,7 @@ struct Request {
     bool in_backward = false; // read out; its reverse sweep runs on the executor's finisher thread
     int back_status = LBP_OK;
     std::vector<float> grad_q;
+    std::vector<DevGraph> adj_views;  // host staging of the reverse sweep's views (copied at admission)
     HostLayout L;
     size_t bytes = 0, graph_bytes = 0, adj_bytes = 0;
     size_t off = Arena::kNone;
@@ -279,29 +280,28 @@ public:
     // request, the compute stream waits for the copy stream before the next
     // round (or read-out) and the image is freed once that has completed.
     // Backward requests (their adjoint buffers are prepared here) wait.
+    // Queues the request's uploads on the copy stream and waits for none of
+    // them: the graph image, and for a backward request the reverse sweep's
+    // views and its loss vector, all from host memory the request keeps
+    // (the image until a round or read-out has waited for this upload, the
+    // rest until the request ends; release waits for an upload still in
+    // flight).  One event after them all carries the upload generation.
     int admit(Request &r) override {
         char *mem = base_ + r.off;
-        const bool async = !r.backward;
-        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get(), !async);
+        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get(), false);
         if (rc != LBP_OK) return rc;
-        if (async) {
-            r.up_gen = ++up_gen_;
-            HIP_TRY(hipEventRecord(up_ev_, copy_));
-        } else {
-            up_done_ = up_gen_;  // the copy stream has drained
-            r.image.reset();
-        }
+        r.up_gen = ++up_gen_;  // from here on release waits for the copy stream
         r.g->last_T = r.T;
         if (r.tol >= 0.0f) r.conv = mem + Arena::round(r.graph_bytes);
         if (r.backward) {
             char *am = mem + Arena::round(r.graph_bytes);
-            rc = adjoint_prepare(r.g, r.iters, r.d, r.T, r.k, am, copy_);
+            rc = adjoint_prepare(r.g, r.iters, r.d, r.T, r.k, am, copy_, &r.adj_views);
             if (rc != LBP_OK) return rc;
             r.gq_dev = (float *)(am + Arena::round(r.adj_bytes));
             r.gphi_dev = (float *)((char *)r.gq_dev + Arena::round(sizeof(float) * r.L.VS));
             HIP_TRY(hipMemcpyAsync(r.gq_dev, r.grad_q.data(), sizeof(float) * r.L.VS, hipMemcpyHostToDevice, copy_));
-            HIP_TRY(hipStreamSynchronize(copy_));
         }
+        HIP_TRY(hipEventRecord(up_ev_, copy_));
         return LBP_OK;
     }
 
