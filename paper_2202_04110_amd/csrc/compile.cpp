@@ -618,8 +618,16 @@ int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, floa
     std::fill(theta + filled, theta + L.VB, 0.0f);  // the spare zero panel
     // each tile's panel is the transpose of its factors' tables: blocks of 16
     // lanes, so every configuration row is written 64 bytes at a time; the
-    // values are checked for NaN and infinity on the way
+    // values are checked for NaN and infinity on the way.  Where all 16 lanes
+    // hold a factor, 4 configurations of each are read at once (16-byte
+    // loads) and written out as 4 rows.
     uint32_t nonfinite = 0;
+    auto flag = [](const float *x) {
+        uint32_t u[16], acc = 0;
+        std::memcpy(u, x, sizeof u);
+        for (int32_t l = 0; l < 16; ++l) acc |= (uint32_t)((u[l] & 0x7f800000u) == 0x7f800000u);
+        return acc;
+    };
     for (size_t t = 0; t < L.ftile.size(); ++t) {
         const FTile &ft = L.ftile[t];
         if (ft.kind != TK_PAIR && ft.kind != TK_GEN) continue;
@@ -628,17 +636,28 @@ int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, floa
         float *panel = phi + ft.phi_off;
         for (int32_t l0 = 0; l0 < kLanes; l0 += 16) {
             const float *src[16];
-            for (int32_t l = 0; l < 16; ++l)
+            bool full = true;
+            for (int32_t l = 0; l < 16; ++l) {
                 src[l] = lf[l0 + l] >= 0 ? d->log_potentials + L.lp_off[lf[l0 + l]] : nullptr;
-            for (int32_t c = 0; c < ncfg; ++c) {
-                float *row = panel + (int64_t)c * kLanes + l0;
-                for (int32_t l = 0; l < 16; ++l) {
-                    const float x = src[l] ? src[l][c] : 0.0f;
-                    uint32_t u;
-                    std::memcpy(&u, &x, sizeof u);
-                    nonfinite |= (uint32_t)((u & 0x7f800000u) == 0x7f800000u);
-                    row[l] = x;
+                full = full && src[l];
+            }
+            int32_t c = 0;
+            if (full)
+                for (; c + 4 <= ncfg; c += 4) {
+                    alignas(16) float in[16][4];
+                    for (int32_t l = 0; l < 16; ++l) std::memcpy(in[l], src[l] + c, sizeof in[l]);
+                    for (int32_t j = 0; j < 4; ++j) {
+                        alignas(16) float row[16];
+                        for (int32_t l = 0; l < 16; ++l) row[l] = in[l][j];
+                        nonfinite |= flag(row);
+                        std::memcpy(panel + (int64_t)(c + j) * kLanes + l0, row, sizeof row);
+                    }
                 }
+            for (; c < ncfg; ++c) {
+                alignas(16) float row[16];
+                for (int32_t l = 0; l < 16; ++l) row[l] = src[l] ? src[l][c] : 0.0f;
+                nonfinite |= flag(row);
+                std::memcpy(panel + (int64_t)c * kLanes + l0, row, sizeof row);
             }
         }
     }
