@@ -417,6 +417,22 @@ int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, f
  * measures faster.  Off by default.  out = {available, in use}. */
 int lbp_graph_use_fused(lbp_graph *g, int enable);
 int lbp_graph_fused_state(const lbp_graph *g, int32_t out[2]);
+/* Resident solver (Sec. "Package features": the same parallel damped
+ * updates): a graph whose messages and beliefs fit in one workgroup's LDS
+ * (the device's limit; index arrays, evidence and tables join them while
+ * they fit), whose
+ * variables have at most 64 edges and whose factors are all pairwise or
+ * OR/AND of at most 256 edges is solved by lbp_run_bp in one workgroup that
+ * keeps messages and beliefs in on-chip memory for all iterations, with the
+ * same per-element arithmetic as launched iterations (bitwise identical
+ * results).  One workgroup works through the tiles that launched iterations
+ * spread over the whole device, so it pays only for the smallest graphs:
+ * off by default, lbp_autotune switches it on when it measures faster.
+ * Enabling it where it does not apply is LBP_E_INVALID.  Other entry points
+ * (batches, lbp_run_bp_until, records) always launch.  out = {applies, in
+ * use}. */
+int lbp_graph_use_resident(lbp_graph *g, int enable);
+int lbp_graph_resident_state(const lbp_graph *g, int32_t out[2]);
 
 /* Diagnostic timing: runs `reps` launches of one phase of an iteration on the
  * current messages and returns the mean time per launch (per iteration for

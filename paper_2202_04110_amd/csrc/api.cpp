@@ -213,10 +213,36 @@ int lbp_run_bp(lbp_graph *g, int32_t iters, float damping, float temperature) {
     if (!valid_params(iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
     HIP_TRY(hipSetDevice(g->ctx->device));
     ++g->version;
-    hipError_t e = run_loop(g->ctx, g->loops, g->dgraph, g->use_fused ? g->fused : nullptr, g->vl, g->fl, iters,
-                            damping, temperature);
+    hipError_t e = hipErrorInvalidValue;
+    if (g->use_resident) {
+        e = launch_solve_resident(g->dgraph, g->plan, iters, temperature == 0.0f, make_params(damping, temperature),
+                                  g->ctx->stream);
+        if (e != hipSuccess) {
+            // refused at launch (LDS size or configuration): launched
+            // iterations from here on, for this graph
+            (void)hipGetLastError();
+            g->use_resident = g->resident_ok = false;
+        }
+    }
+    if (!g->use_resident)
+        e = run_loop(g->ctx, g->loops, g->dgraph, g->use_fused ? g->fused : nullptr, g->vl, g->fl, iters, damping,
+                     temperature);
     if (e != hipSuccess) return hip_error(e, "iteration launch");
     g->last_T = temperature;
+    return LBP_OK;
+}
+
+int lbp_graph_use_resident(lbp_graph *g, int enable) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    if (enable && !g->resident_ok) return fail(LBP_E_INVALID, "the graph does not fit the resident solver");
+    g->use_resident = enable != 0;
+    return LBP_OK;
+}
+
+int lbp_graph_resident_state(const lbp_graph *g, int32_t out[2]) {
+    if (!g || !out) return fail(LBP_E_INVALID, "graph or out is NULL");
+    out[0] = g->resident_ok;
+    out[1] = g->use_resident;
     return LBP_OK;
 }
 
@@ -548,6 +574,40 @@ int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, f
                              : hip_error(e, "autotune backup");
     if (rc == LBP_OK && g->fused)
         rc = tune_fused(g->dgraph, g->fused, 1, g->vl, g->fl, damping, temperature, reps, st, &g->use_fused);
+    if (rc == LBP_OK && g->resident_ok) {
+        // the resident solver against the launched iterations chosen above
+        const TParams P = make_params(damping, temperature);
+        const bool maxp = temperature == 0.0f;
+        hipEvent_t a = nullptr, b = nullptr;
+        float tl = 0.0f, tr = 0.0f;
+        hipError_t x = hipEventCreate(&a);
+        if (x == hipSuccess) x = hipEventCreate(&b);
+        if (x == hipSuccess) x = launch_solve_resident(g->dgraph, g->plan, 2, maxp, P, st);  // warm-up
+        if (x == hipSuccess) x = hipEventRecord(a, st);
+        if (x == hipSuccess) x = launch_solve_resident(g->dgraph, g->plan, 2 * reps, maxp, P, st);
+        if (x == hipSuccess) x = hipEventRecord(b, st);
+        if (x == hipSuccess) x = hipEventSynchronize(b);
+        if (x == hipSuccess) x = hipEventElapsedTime(&tr, a, b);
+        // launched iterations as lbp_run_bp runs them: a captured loop,
+        // captured on the first call and replayed on the timed one
+        const DevGraph *fz = g->use_fused ? g->fused : nullptr;
+        if (x == hipSuccess) x = run_loop(g->ctx, g->loops, g->dgraph, fz, g->vl, g->fl, 2 * reps, damping, temperature);
+        if (x == hipSuccess) x = hipEventRecord(a, st);
+        if (x == hipSuccess) x = run_loop(g->ctx, g->loops, g->dgraph, fz, g->vl, g->fl, 2 * reps, damping, temperature);
+        if (x == hipSuccess) x = hipEventRecord(b, st);
+        if (x == hipSuccess) x = hipEventSynchronize(b);
+        if (x == hipSuccess) x = hipEventElapsedTime(&tl, a, b);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        if (x == hipSuccess) {
+            g->use_resident = tr < tl;
+        } else {
+            // the resident solver was refused (LDS size or configuration)
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(st);
+            g->use_resident = g->resident_ok = false;
+        }
+    }
     e = hipMemcpyAsync(g->host.m, save, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(save);

@@ -17,6 +17,29 @@ struct TParams {
 
 TParams make_params(float damping, float temperature);
 
+// A graph's launch list for the resident solver (passed by value): variable
+// launches first (a: state bucket; n low tiles then n_mid wavefront items),
+// then factor launches (kind, a, b as launched; n items).
+struct SolveLaunch {
+    int32_t kind, a, b, n, n_mid, pad;
+    const WorkItem *items;
+};
+constexpr int kSolveLaunchesMax = 12;
+// Graph arrays the resident solver may hold in LDS, in placement order:
+// messages and beliefs always, then (each while it fits) the index arrays
+// and tile descriptors that start every tile's load chain, the evidence, the
+// potential tables.
+enum SolveArray : int32_t {
+    SA_M, SA_B, SA_VEDGE, SA_FVB, SA_HEDGE, SA_VNS, SA_VTILE, SA_FTILE, SA_HVAR, SA_THETA, SA_PHI, SA_COUNT
+};
+struct SolvePlan {
+    int32_t nv = 0, nf = 0;
+    int32_t words[SA_COUNT] = {};  // size of each array in 4-byte words
+    uint32_t lds_mask = 0;         // arrays copied into LDS
+    int32_t lds_words = 0;         // their total
+    SolveLaunch l[kSolveLaunchesMax];
+};
+
 // Launch shape of a wavefront-per-item kernel: wavefronts per block (1, 2 or
 // 4), whether blocks are remapped so each XCD takes a contiguous range, and
 // (fused pairwise launches only) whether tables are loaded before the belief
@@ -55,6 +78,15 @@ hipError_t launch_logical(const DevGraph *gs, const WorkItem *items, int n, bool
 hipError_t launch_gen(const DevGraph *gs, const WorkItem *items, int n, bool maxp, const TParams &P, int lds_code,
                       hipStream_t st);
 // Read-out of a single graph (gs[0]).
+// `iters` iterations of one small graph in a single workgroup holding the
+// arrays of plan.lds_mask in LDS (plan.lds_words words, which must include
+// the messages and beliefs); no block-per-variable items, pairwise and lane
+// logical factor launches only (hipErrorInvalidValue otherwise).  Bitwise the
+// same as launched two-phase iterations.
+hipError_t launch_solve_resident(const DevGraph *g, const SolvePlan &plan, int32_t iters, bool maxp, const TParams &P,
+                                 hipStream_t st);
+// Largest LDS allocation of one workgroup on `device`, in bytes (0 if unknown).
+int32_t solve_lds_limit(int device);
 hipError_t launch_readout(const DevGraph *gs, int nvtiles, bool maxp, const TParams &P, float *q, int normalized,
                           int32_t *map, hipStream_t st);
 // Read-out of one graph inside a multi-graph launch: its normalised beliefs

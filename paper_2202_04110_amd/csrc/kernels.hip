@@ -735,6 +735,115 @@ __global__ __launch_bounds__(256) void k_logical_wide(const DevGraph *__restrict
 }
 
 // --------------------------------------------------------------------------
+// resident solver: a small graph in one workgroup
+// --------------------------------------------------------------------------
+// The graph's messages and beliefs are copied into LDS; each iteration runs
+// the variable launches' items and then the factor launches' items, one
+// wavefront per item with the launched path's tile code, the two phases
+// separated by workgroup barriers.  The tile code reads and writes through a
+// copy of the graph descriptor whose message and belief arrays are the LDS
+// copies, so every element gets the same arithmetic as in launched
+// iterations; the messages are copied back at the end.
+constexpr int kSolveThreads = 512;
+
+template <bool MAXP>
+__device__ __forceinline__ void pair_any(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+    if (ft.a == ft.b) switch (ft.a) {
+        case 2: pair_tile<2, 2, true, MAXP, false, false>(G, ft, lane, P); return;
+        case 3: pair_tile<3, 3, true, MAXP, false, false>(G, ft, lane, P); return;
+        case 4: pair_tile<4, 4, true, MAXP, false, false>(G, ft, lane, P); return;
+        case 5: pair_tile<5, 5, true, MAXP, false, false>(G, ft, lane, P); return;
+        case 6: pair_tile<6, 6, true, MAXP, false, false>(G, ft, lane, P); return;
+        case 7: pair_tile<7, 7, true, MAXP, false, false>(G, ft, lane, P); return;
+        case 8: pair_tile<8, 8, true, MAXP, false, false>(G, ft, lane, P); return;
+        default: break;
+        }
+    pair_tile<kPairStatesMax, kPairStatesMax, false, MAXP, false, false>(G, ft, lane, P);
+}
+
+// Address of graph array `a` in G (as 4-byte words).
+__device__ __forceinline__ const uint32_t *solve_src(const DevGraph &G, int a) {
+    switch (a) {
+    case SA_M: return (const uint32_t *)G.m;
+    case SA_B: return (const uint32_t *)G.B;
+    case SA_VEDGE: return (const uint32_t *)G.vedge;
+    case SA_FVB: return (const uint32_t *)G.fvb;
+    case SA_HEDGE: return (const uint32_t *)G.hedge;
+    case SA_VNS: return (const uint32_t *)G.vns;
+    case SA_VTILE: return (const uint32_t *)G.vtile;
+    case SA_FTILE: return (const uint32_t *)G.ftile;
+    case SA_HVAR: return (const uint32_t *)G.hvar;
+    case SA_THETA: return (const uint32_t *)G.theta;
+    default: return (const uint32_t *)G.phi;
+    }
+}
+
+__device__ __forceinline__ void solve_repoint(DevGraph &G, int a, uint32_t *p) {
+    switch (a) {
+    case SA_M: G.m = (float *)p; G.mo = (float *)p; break;
+    case SA_B: G.B = (float *)p; break;
+    case SA_VEDGE: G.vedge = (const int32_t *)p; break;
+    case SA_FVB: G.fvb = (const int32_t *)p; break;
+    case SA_HEDGE: G.hedge = (const int32_t *)p; break;
+    case SA_VNS: G.vns = (const int32_t *)p; break;
+    case SA_VTILE: G.vtile = (const VTile *)p; break;
+    case SA_FTILE: G.ftile = (const FTile *)p; break;
+    case SA_HVAR: G.hvar = (const HVar *)p; break;
+    case SA_THETA: G.theta = (float *)p; break;
+    default: G.phi = (float *)p; break;
+    }
+}
+
+template <bool MAXP>
+__global__ __launch_bounds__(kSolveThreads) void k_solve_resident(const DevGraph *__restrict__ gs, SolvePlan plan,
+                                                                  int iters, TParams P) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    const DevGraph &Gg = gs[0];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = kSolveThreads / 64;
+    DevGraph G = Gg;
+    uint32_t *at = lds;
+#pragma unroll
+    for (int a = 0; a < SA_COUNT; ++a) {  // unrolled: each field chosen at compile time
+        if (!(plan.lds_mask >> a & 1u)) continue;
+        const uint32_t *src = solve_src(Gg, a);
+        for (int i = tid; i < plan.words[a]; i += kSolveThreads) at[i] = src[i];
+        solve_repoint(G, a, at);
+        at += plan.words[a];
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        for (int li = 0; li < plan.nv; ++li) {
+            const SolveLaunch L = plan.l[li];
+            for (int w = wave; w < L.n + L.n_mid; w += nwaves) {
+                const int t = L.items[w].t;
+                if (w >= L.n) {
+                    belief_mid_var(G, t, lane);
+                    continue;
+                }
+                switch (L.a) {
+                case 2: belief_low_tile<2>(G, t, lane); break;
+                case 4: belief_low_tile<4>(G, t, lane); break;
+                case 8: belief_low_tile<8>(G, t, lane); break;
+                default: belief_low_tile<16>(G, t, lane); break;
+                }
+            }
+        }
+        __syncthreads();
+        for (int li = plan.nv; li < plan.nv + plan.nf; ++li) {
+            const SolveLaunch L = plan.l[li];
+            for (int w = wave; w < L.n; w += nwaves) {
+                const FTile ft = G.ftile[L.items[w].t];
+                if (L.kind == TK_PAIR) pair_any<MAXP>(G, ft, lane, P);
+                else if (ft.kind == TK_LOGL) logl_tile<MAXP>(G, ft, lane, P);
+                else logw_tile<4, MAXP>(G, ft, lane, P);
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < plan.words[SA_M]; i += kSolveThreads) Gg.m[i] = G.m[i];
+}
+
+// --------------------------------------------------------------------------
 // factor phase: generic enumeration factors (explicit configuration tables or
 // dense tables of arity != 2 / larger state counts).  One wavefront per
 // block, one lane per factor; the class's configuration table is staged in
@@ -1479,6 +1588,39 @@ hipError_t launch_pair(const DevGraph *gs, const WorkItem *items, int n, int na,
         if (maxp) pair_dispatch<true, false, false>(gs, items, n, na, nb, P, S, st);
         else pair_dispatch<false, false, false>(gs, items, n, na, nb, P, S, st);
     }
+    return hipGetLastError();
+}
+
+int32_t solve_lds_limit(int device) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return v;
+}
+
+hipError_t launch_solve_resident(const DevGraph *g, const SolvePlan &plan, int32_t iters, bool maxp, const TParams &P,
+                                 hipStream_t st) {
+    if (iters <= 0) return hipSuccess;
+    const uint32_t need = (1u << SA_M) | (1u << SA_B);
+    int64_t words = 0;
+    for (int a = 0; a < SA_COUNT; ++a)
+        if (plan.lds_mask >> a & 1u) words += plan.words[a];
+    if ((plan.lds_mask & need) != need || plan.lds_mask >> SA_COUNT || words != plan.lds_words || plan.nv < 0 ||
+        plan.nf < 0 || plan.nv + plan.nf > kSolveLaunchesMax)
+        return hipErrorInvalidValue;
+    for (int i = 0; i < plan.nv + plan.nf; ++i) {
+        const SolveLaunch &L = plan.l[i];
+        if (L.n < 0 || L.n_mid < 0 || (L.n + L.n_mid > 0 && !L.items)) return hipErrorInvalidValue;
+        if (i < plan.nv ? L.kind != -1 : (L.kind != TK_PAIR && L.kind != TK_LOGL)) return hipErrorInvalidValue;
+    }
+    const size_t lds = sizeof(uint32_t) * (size_t)words;
+    const void *fn = maxp ? (const void *)k_solve_resident<true> : (const void *)k_solve_resident<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (maxp) hipLaunchKernelGGL((k_solve_resident<true>), dim3(1), dim3(kSolveThreads), lds, st, g, plan, iters, P);
+    else hipLaunchKernelGGL((k_solve_resident<false>), dim3(1), dim3(kSolveThreads), lds, st, g, plan, iters, P);
     return hipGetLastError();
 }
 

@@ -438,6 +438,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         g->V = L.V; g->VS = L.VS; g->F = L.F; g->E = L.E; g->ES = L.ES; g->Tn = L.Tn;
         g->M = L.M; g->VB = L.VB; g->P = L.P;
         g->nvt = (int32_t)L.vtile.size();
+        g->resident_ok = make_solve_plan(g->vl, g->fl, L, solve_lds_limit(ctx->device) / 4, &g->plan);
         *out = g;
         return LBP_OK;
     } catch (const std::bad_alloc &) {
@@ -448,6 +449,36 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         }
         return set_error(LBP_E_OOM, "host allocation failed");
     }
+}
+
+bool make_solve_plan(const std::vector<Launch> &vl, const std::vector<Launch> &fl, const HostLayout &L,
+                     int64_t limit_words, SolvePlan *plan) {
+    static_assert(sizeof(VTile) == 16 && sizeof(FTile) == 32 && sizeof(HVar) == 16, "4-byte-word structs");
+    const int64_t w[SA_COUNT] = {L.M, L.VB, (int64_t)L.vedge.size(), (int64_t)L.fvb.size(), (int64_t)L.hedge.size(),
+                                 (int64_t)L.vns.size(), 4 * (int64_t)L.vtile.size(), 8 * (int64_t)L.ftile.size(),
+                                 4 * (int64_t)L.hvar.size(), L.VB, L.P};
+    if (L.M <= 0 || L.VB <= 0 || w[SA_M] + w[SA_B] > limit_words || vl.size() + fl.size() > (size_t)kSolveLaunchesMax)
+        return false;
+    SolvePlan p;
+    int64_t used = 0;
+    for (int a = 0; a < SA_COUNT; ++a) {
+        p.words[a] = (int32_t)w[a];
+        if (used + w[a] <= limit_words) {
+            p.lds_mask |= 1u << a;
+            used += w[a];
+        }
+    }
+    p.lds_words = (int32_t)used;
+    for (const Launch &x : vl) {
+        if (x.n_high != 0) return false;
+        p.l[p.nv++] = SolveLaunch{-1, x.a, 0, x.n, x.n_mid, 0, x.items};
+    }
+    for (const Launch &x : fl) {
+        if (x.kind != TK_PAIR && x.kind != TK_LOGL) return false;
+        p.l[p.nv + p.nf++] = SolveLaunch{x.kind, x.a, x.b, x.n, 0, 0, x.items};
+    }
+    *plan = p;
+    return true;
 }
 
 void graph_destroy(lbp_graph *g) {

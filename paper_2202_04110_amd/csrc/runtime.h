@@ -116,6 +116,9 @@ struct lbp_graph {
     lbp::DevGraph *fused = nullptr;   // device [2]: fused views over the two message buffers, or null
     float *m2 = nullptr;              // the second message buffer of a fusable graph (device), or null
     bool use_fused = false;           // lbp_run_bp runs fused iterations (chosen by the autotuner)
+    bool resident_ok = false;         // small enough for the resident solver (plan below)
+    bool use_resident = false;        // lbp_run_bp runs the resident solver (chosen by the autotuner)
+    lbp::SolvePlan plan;
     float *q_tmp = nullptr;           // VS
     int32_t *map_tmp = nullptr;       // V
     std::vector<lbp::Launch> vl, fl;  // the graph's own launches
@@ -192,6 +195,12 @@ int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d =
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
                  char *image = nullptr, bool wait = true);
 void graph_destroy(lbp_graph *g);
+// The resident solver's plan of a graph's launch lists, if the graph fits it
+// (messages and beliefs within limit_words 4-byte words of LDS, no
+// block-per-variable items, pairwise and lane logical factor launches only);
+// the other arrays are placed in LDS in SolveArray order while they fit.
+bool make_solve_plan(const std::vector<Launch> &vl, const std::vector<Launch> &fl, const HostLayout &L,
+                     int64_t limit_words, SolvePlan *plan);
 
 // Read-out (beliefs and/or MAP) on `st`; host outputs are copied with
 // hipMemcpyAsync and are complete once `st` is synchronised.

@@ -120,6 +120,8 @@ _sig("lbp_graph_get_launch", C.c_int, [_P, C.c_int32, _P])
 _sig("lbp_graph_set_launch", C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32])
 _sig("lbp_graph_set_fused_launch", C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32])
 _sig("lbp_autotune", C.c_int, [_P, C.c_float, C.c_float, C.c_int32, _P])
+_sig("lbp_graph_use_resident", C.c_int, [_P, C.c_int])
+_sig("lbp_graph_resident_state", C.c_int, [_P, _P])
 _sig("lbp_graph_use_fused", C.c_int, [_P, C.c_int])
 _sig("lbp_graph_fused_state", C.c_int, [_P, _P])
 _sig("lbp_time_phase", C.c_int, [_P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.POINTER(C.c_float)])
@@ -352,6 +354,18 @@ class Graph:
         st = np.zeros(2, np.int32)
         check(_lib.lbp_graph_fused_state(self.h, _ptr(st)))
         return bool(st[1])
+
+    def use_resident(self, enable: bool):
+        """lbp_run_bp in one workgroup with messages in LDS (bitwise the
+        same); off by default, chosen by autotune when faster."""
+        check(_lib.lbp_graph_use_resident(self.h, int(bool(enable))))
+
+    @property
+    def resident_state(self):
+        """(applies, in use) of the resident solver."""
+        st = np.zeros(2, np.int32)
+        check(_lib.lbp_graph_resident_state(self.h, _ptr(st)))
+        return bool(st[0]), bool(st[1])
 
     def set_launch(self, i: int, wpb: int, swizzle: int):
         check(_lib.lbp_graph_set_launch(self.h, int(i), int(wpb), int(swizzle)))

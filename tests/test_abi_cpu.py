@@ -146,6 +146,8 @@ def test_null_handles_are_rejected(lbp):
                L.lbp_batch_autotune(None, 0.5, 1.0, 3, C.byref(n)),
                L.lbp_graph_num_launches(None, C.byref(n)),
                L.lbp_graph_use_fused(None, 1),
+               L.lbp_graph_use_resident(None, 1),
+               L.lbp_graph_resident_state(None, None),
                L.lbp_reset_messages(None),
                L.lbp_run_bp_record(None, 5, 0.5, 1.0, 2),
                L.lbp_graph_set_fused_launch(None, 0, 4, 2),

@@ -660,6 +660,52 @@ def test_batch_autotune_keeps_results(lbp, ctx):
     pg.free()
 
 
+def test_resident_solver_matches_launched(lbp, ctx):
+    """The resident solver (one workgroup, messages and beliefs in LDS) gives
+    bitwise the messages, beliefs and MAP of launched iterations, for lane and
+    wavefront-per-variable paths, pairwise classes of several state counts and
+    lane logical factors; the oracle agrees within the belief tolerance;
+    graphs it does not fit refuse it; after lbp_autotune, whatever it chose,
+    results are unchanged.  (The oracle comparison is made where the
+    oracle's run has converged.)"""
+    cases = [(W.chain(401, 500, 4), 60, 1.0), (W.single_logical(402, W.OR, 40), 30, 1.0),
+             (W.single_logical(403, W.AND, 6), 30, 0.0), (W.potts_grid(16, 8, 404), 40, 1.0),
+             (W.ising_grid(32, 405), 50, 0.0), (W.rbm(20, 20, 406), 40, 0.0),
+             (W.disjoint_union([W.potts_grid(9, 3, 407), W.single_logical(408, W.OR, 5)]), 40, 0.7)]
+    for spec, iters, T in cases:
+        g = lbp.Graph(ctx, spec)
+        applies, in_use = g.resident_state
+        assert applies and not in_use, spec.name
+        out = {}
+        for mode in (False, True):
+            g.use_resident(mode)
+            assert g.resident_state == (True, mode)
+            g.reset_messages()
+            g.run_bp(iters, 0.5, T)
+            out[mode] = (g.get_messages(), g.get_beliefs(), g.decode_map())
+        for a, b in zip(out[False], out[True]):
+            np.testing.assert_array_equal(a, b)
+        og = OracleGraph(spec)
+        mo, res = og.run(iters, 0.5, T, residuals=True)
+        if res[-1] <= 1e-6:  # loopy max-product need not converge; then only the bitwise check applies
+            _, qo, _ = og.beliefs(mo, T)
+            assert np.abs(out[True][1] - qo).max() <= TOL_Q, spec.name
+        g.autotune(0.5, T, reps=3)
+        g.reset_messages()
+        g.run_bp(iters, 0.5, T)
+        np.testing.assert_array_equal(g.get_messages(), out[False][0])
+        g.free()
+    for spec in (W.deconv(seed=4, K=2, tw=3, sd=5, img=6), W.rbm(100, 100, 409), W.single_enum(410, [3, 4, 2])):
+        g = lbp.Graph(ctx, spec)
+        if not g.resident_state[0]:
+            with pytest.raises(lbp.LBPError):
+                g.use_resident(True)
+        g.free()
+    big = lbp.Graph(ctx, W.potts_grid(128, 5, 411))
+    assert big.resident_state == (False, False)
+    big.free()
+
+
 def test_binding_imported_before_torch():
     """The binding loads torch before the library, so both share one HIP
     runtime whatever the caller imported first."""
