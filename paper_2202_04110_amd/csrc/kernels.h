@@ -36,9 +36,10 @@ struct SolvePlan {
     int32_t nv = 0, nf = 0;
     int32_t words[SA_COUNT] = {};  // size of each array in 4-byte words
     uint32_t lds_mask = 0;         // arrays copied into LDS
-    int32_t lds_words = 0;         // their total
+    int32_t lds_words = 0;         // their total, each rounded up to 4 words (16-byte aligned placements)
     SolveLaunch l[kSolveLaunchesMax];
 };
+__host__ __device__ constexpr int64_t solve_words_aligned(int64_t w) { return (w + 3) & ~int64_t(3); }
 
 // Launch shape of a wavefront-per-item kernel: wavefronts per block (1, 2 or
 // 4), whether blocks are remapped so each XCD takes a contiguous range, and

@@ -808,7 +808,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_resident(const DevGraph
         const uint32_t *src = solve_src(Gg, a);
         for (int i = tid; i < plan.words[a]; i += kSolveThreads) at[i] = src[i];
         solve_repoint(G, a, at);
-        at += plan.words[a];
+        at += solve_words_aligned(plan.words[a]);
     }
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
@@ -1606,7 +1606,7 @@ hipError_t launch_solve_resident(const DevGraph *g, const SolvePlan &plan, int32
     const uint32_t need = (1u << SA_M) | (1u << SA_B);
     int64_t words = 0;
     for (int a = 0; a < SA_COUNT; ++a)
-        if (plan.lds_mask >> a & 1u) words += plan.words[a];
+        if (plan.lds_mask >> a & 1u) words += solve_words_aligned(plan.words[a]);
     if ((plan.lds_mask & need) != need || plan.lds_mask >> SA_COUNT || words != plan.lds_words || plan.nv < 0 ||
         plan.nf < 0 || plan.nv + plan.nf > kSolveLaunchesMax)
         return hipErrorInvalidValue;

@@ -457,15 +457,16 @@ bool make_solve_plan(const std::vector<Launch> &vl, const std::vector<Launch> &f
     const int64_t w[SA_COUNT] = {L.M, L.VB, (int64_t)L.vedge.size(), (int64_t)L.fvb.size(), (int64_t)L.hedge.size(),
                                  (int64_t)L.vns.size(), 4 * (int64_t)L.vtile.size(), 8 * (int64_t)L.ftile.size(),
                                  4 * (int64_t)L.hvar.size(), L.VB, L.P};
-    if (L.M <= 0 || L.VB <= 0 || w[SA_M] + w[SA_B] > limit_words || vl.size() + fl.size() > (size_t)kSolveLaunchesMax)
+    if (L.M <= 0 || L.VB <= 0 || solve_words_aligned(w[SA_M]) + solve_words_aligned(w[SA_B]) > limit_words ||
+        vl.size() + fl.size() > (size_t)kSolveLaunchesMax)
         return false;
     SolvePlan p;
     int64_t used = 0;
     for (int a = 0; a < SA_COUNT; ++a) {
         p.words[a] = (int32_t)w[a];
-        if (used + w[a] <= limit_words) {
+        if (used + solve_words_aligned(w[a]) <= limit_words) {
             p.lds_mask |= 1u << a;
-            used += w[a];
+            used += solve_words_aligned(w[a]);
         }
     }
     p.lds_words = (int32_t)used;
