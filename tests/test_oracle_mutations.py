@@ -66,6 +66,8 @@ MUTATIONS = {
     "adjoint_vtof_sign": (
         "gm[g->es_off[e] + s] -= gn[g->es_off[e] + s];",
         "gm[g->es_off[e] + s] += gn[g->es_off[e] + s];"),
+    "residual_always_zero": ("double a = fabs(mn[i] - m[i]);", "double a = 0.0;"),
+    "residual_of_state_not_change": ("double a = fabs(mn[i] - m[i]);", "double a = fabs(mn[i]);"),
 }
 
 
@@ -92,6 +94,7 @@ def _checks(P):
         ("adjoint_fd_T", lambda: P.test_adjoint_vs_finite_differences(False, 0.5)),
         ("adjoint_fd_d", lambda: P.test_adjoint_fd_damping(0.3)),
         ("adjoint_tree", P.test_adjoint_tree_closed_form),
+        ("resid0", lambda: P.test_residual_history_matches_separate_runs(0.0)),
     ]
 
 

@@ -314,3 +314,44 @@ def test_rbm_map_quality_statistic():
         hits += int(abs(sc - best) < 1e-9)
     print("exact MAP recovered on %d/20 RBMs" % hits)
     assert hits >= 5
+
+
+# ------------------------------------------------- run bookkeeping
+@pytest.mark.parametrize("T", [0.0, 1.0])
+def test_residual_history_matches_separate_runs(T):
+    """og_run's residual history is the largest change of the message array
+    from one iterate to the next: resid[t] = max |m_{t+1} - m_t|, where m_t
+    and m_{t+1} come from two independent runs of t and t + 1 iterations from
+    zero (the runs are deterministic, so the identity is exact)."""
+    g = W.random_factor_graph(8, num_vars=40, tree=False, extra_factors=30, max_arity=3,
+                              logical_frac=0.3, explicit_frac=0.3, max_states=4)
+    og = OracleGraph(g)
+    K = 12
+    _, res = og.run(K, 0.5, T, residuals=True)
+    prev = og.zero_messages()
+    for t in range(K):
+        cur = og.run(t + 1, 0.5, T)
+        assert res[t] == np.abs(cur - prev).max(), t
+        prev = cur
+    # loopy max-product moves: the history is not trivially zero
+    assert res[0] > 0 and res[-1] > 0
+
+
+@pytest.mark.parametrize("case", ["mixed", "deconv"])
+def test_threaded_runs_bitwise_single_thread(case):
+    """Every output element of an iteration is owned by one loop iteration and
+    computed in a fixed order, so runs over 8 threads are bitwise the runs on
+    one thread (messages, residual history and read-out)."""
+    if case == "mixed":
+        g = W.random_factor_graph(9, num_vars=300, tree=False, extra_factors=250, max_arity=3,
+                                  logical_frac=0.25, explicit_frac=0.4, max_states=4)
+        iters, T = 15, 0.7
+    else:
+        g = W.deconv(seed=4)
+        iters, T = 3, 0.0
+    og = OracleGraph(g)
+    m1, r1 = og.run(iters, 0.5, T, threads=1, residuals=True)
+    m8, r8 = og.run(iters, 0.5, T, threads=8, residuals=True)
+    np.testing.assert_array_equal(m1, m8)
+    np.testing.assert_array_equal(r1, r8)
+    assert r1[-1] > 0
