@@ -201,6 +201,26 @@ int lbp_run_bp(lbp_graph *g, int32_t iters, float damping, float temperature);
 int lbp_run_bp_until(lbp_graph *g, int32_t max_iters, float damping, float temperature, float tol,
                      int32_t check_every, int32_t *iters_done, float *residual_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as lbp_run_bp_until, with the same arguments, the same
+ * iterations run and bitwise the same messages and residual, but its
+ * workspace (the previous-message copy and the residual partials) lives in a
+ * fixed device array of LBP_NOALLOC_SCRATCH_BYTES compiled into the library
+ * (each GPU the library runs on holds one until the process ends; its
+ * address is looked up once per device by lbp_ctx_create).  The call makes
+ * no hipMalloc, hipFree or other allocating call and launches its kernels
+ * one by one (no captured loop).  A graph whose workspace exceeds the array
+ * (message panel floats rounded up to 256 bytes, plus one float per 256
+ * edges, plus one) is refused with LBP_E_UNSUPPORTED before anything runs.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other threads, other contexts, other streams) race and must be
+ * serialised by the caller.  Nothing in the array needs to start at zero:
+ * each call writes what it reads. */
+#define LBP_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int lbp_run_bp_until_noalloc(lbp_graph *g, int32_t max_iters, float damping, float temperature, float tol,
+                             int32_t check_every, int32_t *iters_done, float *residual_out);
+
 /* Beliefs from the current messages at the temperature of the last run (0
  * before any run), VS floats variable-major: normalised q = B - LSE_T(B) when
  * `normalized`, else B.  MAP: lowest-index argmax of B per variable (V int32;

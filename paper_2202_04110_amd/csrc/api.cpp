@@ -90,6 +90,10 @@ int lbp_ctx_create(int device, void *hip_stream, lbp_ctx **out) {
     if (e != hipSuccess) return hip_error(e, "hipGetDeviceCount");
     if (device < 0 || device >= count) return fail(LBP_E_INVALID, "device index out of range");
     HIP_TRY(hipSetDevice(device));
+    // set-up of the fixed scratch of lbp_run_bp_until_noalloc on this device
+    float *scratch_addr = nullptr;
+    e = noalloc_scratch_address(device, &scratch_addr);
+    if (e != hipSuccess) return hip_error(e, "scratch address lookup");
     lbp_ctx *c = new (std::nothrow) lbp_ctx;
     if (!c) return fail(LBP_E_OOM, "host allocation failed");
     c->device = device;
@@ -278,6 +282,55 @@ int lbp_run_bp_until(lbp_graph *g, int32_t max_iters, float damping, float tempe
                          temperature);
         if (e == hipSuccess) e = hipMemcpyAsync(mprev, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = run_loop(g->ctx, g->loops, g->dgraph, nullptr, g->vl, g->fl, 1, damping, temperature);
+        if (e == hipSuccess) e = launch_residual(g->dgraph, (int)g->E, mprev, partial, res, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&r, res, sizeof(float), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_error(e, "iteration launch");
+        done += c;
+        if (r < tol) break;
+    }
+    if (iters_done) *iters_done = done;
+    if (residual_out) *residual_out = r;
+    return LBP_OK;
+}
+
+static_assert(LBP_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "scratch size in lbp.h and kernels.h differ");
+
+int lbp_run_bp_until_noalloc(lbp_graph *g, int32_t max_iters, float damping, float temperature, float tol,
+                             int32_t check_every, int32_t *iters_done, float *residual_out) {
+    if (!g) return fail(LBP_E_INVALID, "graph is NULL");
+    std::string why;
+    if (!valid_params(max_iters, damping, temperature, &why)) return fail(LBP_E_INVALID, why);
+    if (!(tol >= 0.0f) || !std::isfinite(tol)) return fail(LBP_E_INVALID, "tol must be finite and >= 0");
+    if (check_every < 1) return fail(LBP_E_INVALID, "check_every must be >= 1");
+    const size_t mb = align256(sizeof(float) * std::max<int64_t>(1, g->M));
+    const int nb = residual_blocks((int)g->E);
+    const size_t need = mb + sizeof(float) * (size_t)(nb + 1);
+    if (need > kNoAllocScratchBytes)
+        return fail(LBP_E_UNSUPPORTED, "the graph needs " + std::to_string(need) +
+                                           " bytes of scratch, more than the fixed " +
+                                           std::to_string(kNoAllocScratchBytes));
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    float *base = nullptr;
+    HIP_TRY(noalloc_scratch_address(g->ctx->device, &base));
+    hipStream_t st = g->ctx->stream;
+    float *mprev = base, *partial = reinterpret_cast<float *>(reinterpret_cast<char *>(base) + mb),
+          *res = partial + nb;
+    const TParams P = make_params(damping, temperature);
+    const bool maxp = temperature == 0.0f;
+    ++g->version;
+    g->last_T = temperature;
+    int32_t done = 0;
+    float r = 0.0f;
+    // the kernels of lbp_run_bp_until, launched one by one (no captured
+    // loop: instantiating one allocates)
+    while (done < max_iters) {
+        const int32_t c = std::min(check_every, max_iters - done);
+        hipError_t e = hipSuccess;
+        if (c > 1)
+            e = launch_loop(g->dgraph, g->use_fused ? g->fused : nullptr, g->vl, g->fl, c - 1, P, maxp, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(mprev, g->host.m, sizeof(float) * g->M, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = launch_loop(g->dgraph, nullptr, g->vl, g->fl, 1, P, maxp, st);
         if (e == hipSuccess) e = launch_residual(g->dgraph, (int)g->E, mprev, partial, res, st);
         if (e == hipSuccess) e = hipMemcpyAsync(&r, res, sizeof(float), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

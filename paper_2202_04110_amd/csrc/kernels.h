@@ -111,6 +111,13 @@ hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStr
 // residual_blocks(E) floats.
 int residual_blocks(int E);
 hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float *partial, float *out, hipStream_t st);
+// Fixed scratch of the entry point that allocates nothing: a file-scope
+// device array in kernels.hip (every GPU the library runs on holds its own
+// copy until the process ends).  noalloc_scratch_address returns its device
+// address on `device`, which must be the current device; the first call per
+// device looks it up (hipGetSymbolAddress), later calls return the kept value.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch_address(int device, float **out);
 // One graph's convergence check inside a multi-graph launch: g is the
 // device copy of its descriptor, mprev (M floats, M a multiple of 4, 16-byte
 // aligned) receives its messages before the checked iteration, partial holds

@@ -25,8 +25,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "kernels.h"
+
+// Scratch of lbp_run_bp_until_noalloc: the previous-message copy and the
+// residual partials live here instead of in memory the library allocates.
+// In host code this name is a host-side stand-in, not a device address: the
+// address is looked up per device (noalloc_scratch_address) and only that
+// value is handed to kernels and copies.
+static __device__ __align__(256) float scratch[lbp::kNoAllocScratchBytes / sizeof(float)];
 
 namespace lbp {
 
@@ -1703,6 +1711,25 @@ hipError_t launch_evidence_in(const DevGraph *gs, int V, const float *in, hipStr
 }
 
 int residual_blocks(int E) { return residual_block_count(E); }
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_addr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_address(int device, float **out) {
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = static_cast<float *>(p);
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float *partial, float *out, hipStream_t st) {
     const int nb = residual_blocks(E);

@@ -89,6 +89,8 @@ _sig("lbp_batch_autotune", C.c_int, [_P, C.c_float, C.c_float, C.c_int32, C.POIN
 _sig("lbp_batch_free", None, [_P])
 _sig("lbp_run_bp_until", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32,
                                    C.POINTER(C.c_int32), C.POINTER(C.c_float)])
+_sig("lbp_run_bp_until_noalloc", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32,
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_float)])
 _sig("lbp_sampler_create", C.c_int, [_P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_sampler_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, _P, _P, _P])
 _sig("lbp_sampler_free", None, [_P])
@@ -277,6 +279,16 @@ class Graph:
         res = C.c_float()
         check(_lib.lbp_run_bp_until(self.h, int(max_iters), float(damping), float(temperature), float(tol),
                                     int(check_every), C.byref(done), C.byref(res)))
+        return int(done.value), float(res.value)
+
+    def run_bp_until_noalloc(self, max_iters: int, damping: float, temperature: float, tol: float,
+                             check_every: int = 1):
+        """run_bp_until whose workspace is the library's fixed device array
+        (no device allocation; graphs beyond it raise LBP_E_UNSUPPORTED)."""
+        done = C.c_int32()
+        res = C.c_float()
+        check(_lib.lbp_run_bp_until_noalloc(self.h, int(max_iters), float(damping), float(temperature),
+                                            float(tol), int(check_every), C.byref(done), C.byref(res)))
         return int(done.value), float(res.value)
 
     def reset_messages(self):
