@@ -627,6 +627,10 @@ int lbp_autotune(lbp_graph *g, float damping, float temperature, int32_t reps, f
                              : hip_error(e, "autotune backup");
     if (rc == LBP_OK && g->fused)
         rc = tune_fused(g->dgraph, g->fused, 1, g->vl, g->fl, damping, temperature, reps, st, &g->use_fused);
+    // loops captured before the shapes and the iteration form changed would
+    // replay the old launches: drop them before timing the launched loop
+    (void)hipStreamSynchronize(st);
+    destroy_loops(g->loops);
     if (rc == LBP_OK && g->resident_ok) {
         // the resident solver against the launched iterations chosen above
         const TParams P = make_params(damping, temperature);
