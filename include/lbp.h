@@ -465,6 +465,20 @@ int lbp_graph_resident_state(const lbp_graph *g, int32_t out[2]);
 int lbp_time_phase(lbp_graph *g, int32_t phase, int32_t reps, float damping, float temperature,
                    float *ms_out);
 
+/* Diagnostic: average time in milliseconds of one launch of a plain
+ * streaming kernel (float4 accesses, grid-stride, `blocks` workgroups of 256
+ * threads) over `reps` launches after one warm-up, HIP events on the
+ * context's stream.  It sets the bandwidth an ordinary kernel reaches on the
+ * device, beside the nominal peak.  kind 0: read `bytes` of src (device,
+ * contents should be zeros; dst, device, receives at most one float);
+ * 1: copy `bytes` from src to dst; 2: write `bytes` of dst (src unused, may
+ * be NULL); 3: read `bytes` of src and write bytes / 5 of dst (five reads per
+ * write, about the mix of an iteration's factor launches).  bytes > 0 must be
+ * a multiple of 16 (of 80 for kind 3); pointers 16-byte aligned.  The call
+ * synchronises on its end event. */
+int lbp_bandwidth_probe(lbp_ctx *ctx, int32_t kind, const void *src, void *dst, int64_t bytes, int32_t blocks,
+                        int32_t reps, float *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

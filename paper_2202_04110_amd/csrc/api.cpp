@@ -294,6 +294,34 @@ int lbp_run_bp_until(lbp_graph *g, int32_t max_iters, float damping, float tempe
     return LBP_OK;
 }
 
+int lbp_bandwidth_probe(lbp_ctx *ctx, int32_t kind, const void *src, void *dst, int64_t bytes, int32_t blocks,
+                        int32_t reps, float *ms_out) {
+    if (!ctx || !ms_out) return fail(LBP_E_INVALID, "ctx or ms_out is NULL");
+    if (kind < 0 || kind > 3) return fail(LBP_E_INVALID, "kind must be 0..3");
+    if (bytes <= 0 || bytes % (kind == 3 ? 80 : 16) != 0)
+        return fail(LBP_E_INVALID, "bytes must be a positive multiple of 16 (80 for kind 3)");
+    if (blocks < 1 || reps < 1) return fail(LBP_E_INVALID, "blocks and reps must be >= 1");
+    if ((kind != 2 && (!src || ((uintptr_t)src & 15))) || (!dst || ((uintptr_t)dst & 15)))
+        return fail(LBP_E_INVALID, "src and dst must be non-NULL and 16-byte aligned");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e == hipSuccess) e = launch_stream_probe(kind, src, dst, bytes, blocks, st);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    for (int32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_stream_probe(kind, src, dst, bytes, blocks, st);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_error(e, "bandwidth probe");
+    *ms_out = ms / (float)reps;
+    return LBP_OK;
+}
+
 static_assert(LBP_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "scratch size in lbp.h and kernels.h differ");
 
 int lbp_run_bp_until_noalloc(lbp_graph *g, int32_t max_iters, float damping, float temperature, float tol,

@@ -116,6 +116,11 @@ hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float 
 // copy until the process ends).  noalloc_scratch_address returns its device
 // address on `device`, which must be the current device; the first call per
 // device looks it up (hipGetSymbolAddress), later calls return the kept value.
+// Bandwidth probes (plain streaming kernels): kind 0 reads `bytes` of src
+// (dst receives at most one float), 1 copies `bytes` from src to dst, 2
+// writes `bytes` of dst, 3 reads `bytes` of src and writes bytes / 5 of dst.
+// bytes is a multiple of 16 (of 80 for kind 3); pointers 16-byte aligned.
+hipError_t launch_stream_probe(int kind, const void *src, void *dst, int64_t bytes, int blocks, hipStream_t st);
 constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 hipError_t noalloc_scratch_address(int device, float **out);
 // One graph's convergence check inside a multi-graph launch: g is the

@@ -44,6 +44,75 @@ __device__ __forceinline__ int wave_index(int waves_per_block) {
     return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * waves_per_block + (threadIdx.x >> 6)));
 }
 
+// The graph's arrays as global-address-space pointers.  Kernels take the
+// descriptor by pointer, so its pointer fields reach device code as generic
+// pointers, and every access through them would be a flat access (64-bit
+// VGPR addresses, waits shared with scalar loads).  Launched kernels read
+// the descriptor into this view once and pass it to the tile functions
+// (templates on the view type), whose loads and stores then use global
+// instructions with a scalar base; the resident solver, whose descriptor
+// points into LDS, passes the generic descriptor itself.
+// (The host compilation pass of this file generates no device code and has
+// no such address space: there the view holds plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+#else
+template <class T>
+using gptr = T *;
+#endif
+struct GGraph {
+    gptr<float> m, mo, B, theta, phi;
+    gptr<const FTile> ftile;
+    gptr<const int32_t> fvb, fvar;
+    gptr<const VTile> vtile;
+    gptr<const int32_t> vedge, vns;
+    gptr<const HVar> hvar;
+    gptr<const int32_t> hedge;
+    gptr<const GenClass> gcls;
+    gptr<const uint8_t> grows;
+    gptr<const int32_t> edge_maddr;
+    gptr<const int64_t> es_off, vs_off;
+    gptr<const int32_t> vn, fac_phi;
+    gptr<const int64_t> lp_off;
+    gptr<int32_t> flag;
+    int32_t V, E, F, zero_addr;
+};
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T *p) {
+    return (gptr<T>)p;
+}
+__device__ __forceinline__ GGraph glob(const DevGraph &d) {
+    GGraph g;
+    g.m = as_global(d.m);
+    g.mo = as_global(d.mo);
+    g.B = as_global(d.B);
+    g.theta = as_global(d.theta);
+    g.phi = as_global(d.phi);
+    g.ftile = as_global(d.ftile);
+    g.fvb = as_global(d.fvb);
+    g.fvar = as_global(d.fvar);
+    g.vtile = as_global(d.vtile);
+    g.vedge = as_global(d.vedge);
+    g.vns = as_global(d.vns);
+    g.hvar = as_global(d.hvar);
+    g.hedge = as_global(d.hedge);
+    g.gcls = as_global(d.gcls);
+    g.grows = as_global(d.grows);
+    g.edge_maddr = as_global(d.edge_maddr);
+    g.es_off = as_global(d.es_off);
+    g.vs_off = as_global(d.vs_off);
+    g.vn = as_global(d.vn);
+    g.fac_phi = as_global(d.fac_phi);
+    g.lp_off = as_global(d.lp_off);
+    g.flag = as_global(d.flag);
+    g.V = d.V;
+    g.E = d.E;
+    g.F = d.F;
+    g.zero_addr = d.zero_addr;
+    return g;
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin.  With swizzling, block b of
 // n maps to a logical block such that each XCD runs one contiguous range of
 // logical blocks (neighbouring tiles then share that XCD's L2).  A bijection
@@ -178,8 +247,8 @@ __device__ __forceinline__ void damp_store(float *row, const float (&mo)[N], con
 
 // low: NB >= states of every lane; edge rows fetched KU at a time (addresses,
 // then rows, all in flight) and added in edge order.
-template <int NB>
-__device__ __forceinline__ void belief_low_tile(const DevGraph &G, int t, int lane) {
+template <int NB, class GV>
+__device__ __forceinline__ void belief_low_tile(const GV &G, int t, int lane) {
     constexpr int KU = NB <= 4 ? 8 : 4;
     const VTile vt = G.vtile[t];
     const int n = G.vns[t * kLanes + lane];
@@ -211,8 +280,8 @@ __device__ __forceinline__ void belief_low_tile(const DevGraph &G, int t, int la
 // The beliefs of two lane-path variables at once (va with na states, vb with
 // nb) in registers, each with belief_low_tile's additions in its order (theta
 // first, then the edges in order); both gathers are in flight together.
-template <int NA, int NB>
-__device__ __forceinline__ void belief_regs2(const DevGraph &G, int va, int na, int vb, int nb, float (&ba)[NA],
+template <int NA, int NB, class GV>
+__device__ __forceinline__ void belief_regs2(const GV &G, int va, int na, int vb, int nb, float (&ba)[NA],
                                              float (&bb)[NB]) {
     constexpr int KU = 4;
 #pragma unroll
@@ -268,7 +337,8 @@ __device__ __forceinline__ void belief_regs2(const DevGraph &G, int va, int na, 
 
 // mid: lane l holds edge l; a wavefront sum (wave_sum: the same bits in
 // every lane) adds up each state.
-__device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int lane) {
+template <class GV>
+__device__ __forceinline__ void belief_mid_var(const GV &G, int hv, int lane) {
     constexpr int SC = 8;
     const HVar h = G.hvar[hv];
     const int k = h.e_begin + lane;
@@ -299,7 +369,8 @@ __device__ __forceinline__ void belief_mid_var(const DevGraph &G, int hv, int la
 // wavefront sums are added in order.
 constexpr int kHighThreads = 256;
 constexpr int kHighWaves = kHighThreads / 64;
-__device__ __forceinline__ void belief_high_var(const DevGraph &G, int hv, int tid, float (*red)[kHighWaves]) {
+template <class GV>
+__device__ __forceinline__ void belief_high_var(const GV &G, int hv, int tid, float (*red)[kHighWaves]) {
     constexpr int SC = 8;  // states per pass
     constexpr int KC = 4;  // edges per thread fetched together
     const HVar h = G.hvar[hv];
@@ -357,7 +428,7 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
     if ((int)blockIdx.x < n_high) {
         const int hb = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
         const WorkItem it = items[n_low + n_mid + hb];
-        belief_high_var(gs[it.g], it.t, threadIdx.x, red);
+        belief_high_var(glob(gs[it.g]), it.t, threadIdx.x, red);
         return;
     }
     const int nwave = n_low + n_mid;
@@ -367,8 +438,8 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
     const int w = __builtin_amdgcn_readfirstlane(b * 4 + (int)(threadIdx.x >> 6));
     if (w >= nwave) return;
     const WorkItem it = items[w];
-    if (w < n_low) belief_low_tile<NB>(gs[it.g], it.t, lane_id());
-    else belief_mid_var(gs[it.g], it.t, lane_id());
+    if (w < n_low) belief_low_tile<NB>(glob(gs[it.g]), it.t, lane_id());
+    else belief_mid_var(glob(gs[it.g]), it.t, lane_id());
 }
 
 // --------------------------------------------------------------------------
@@ -387,8 +458,8 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
 // wavefront at the cost of registers (fewer wavefronts per SIMD): faster when
 // the graph streams from HBM, slower when it sits in the last-level cache.
 // The arithmetic is the same either way.
-template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED, bool EARLY = false>
-__device__ __forceinline__ void pair_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED, bool EARLY = false, class GV>
+__device__ __forceinline__ void pair_tile(const GV &G, const FTile &ft, int lane, const TParams &P) {
     const int na = EXACT ? NA : ft.a;
     const int nb = EXACT ? NB : ft.b;
     const float *r0 = G.m + ft.m_off + lane;
@@ -493,7 +564,7 @@ __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, c
     const int w = wave_item(swz);
     if (w >= nitems) return;
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     const FTile ft = G.ftile[it.t];
     pair_tile<NA, NB, EXACT, MAXP, FUSED, EARLY>(G, ft, lane_id(), P);
 }
@@ -508,7 +579,7 @@ __global__ __launch_bounds__(256) void k_pair_mix(const DevGraph *__restrict__ g
     const int w = wave_item(swz);
     if (w >= nitems) return;
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     const FTile ft = G.ftile[it.t];
     const int lane = lane_id();
     switch (__builtin_amdgcn_readfirstlane(ft.a)) {
@@ -538,8 +609,8 @@ __global__ __launch_bounds__(256) void k_pair_mix(const DevGraph *__restrict__ g
 // own term.  For AND the two entries of u are swapped.
 
 // one lane per factor, at most kLogLaneArityMax edges
-template <bool MAXP>
-__device__ __forceinline__ void logl_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+template <bool MAXP, class GV>
+__device__ __forceinline__ void logl_tile(const GV &G, const FTile &ft, int lane, const TParams &P) {
     constexpr int K = kLogLaneArityMax;
     const int k = ft.a, p = k - 1;
     const bool flip = ft.b != 0;
@@ -618,8 +689,8 @@ __device__ __forceinline__ void logl_tile(const DevGraph &G, const FTile &ft, in
 }
 
 // one wavefront per factor; edge j sits in chunk j/64 at lane j%64
-template <int CH, bool MAXP>
-__device__ __forceinline__ void logw_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+template <int CH, bool MAXP, class GV>
+__device__ __forceinline__ void logw_tile(const GV &G, const FTile &ft, int lane, const TParams &P) {
     const int k = ft.a, p = k - 1;
     const int nch = (k + kLanes - 1) / kLanes;
     const bool flip = ft.b != 0;
@@ -724,7 +795,7 @@ __global__ __launch_bounds__(256) void k_logical(const DevGraph *__restrict__ gs
     const int w = wave_item(swz);
     if (w >= nitems) return;
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     const FTile ft = G.ftile[it.t];
     if (ft.kind == TK_LOGL) logl_tile<MAXP>(G, ft, lane_id(), P);
     else logw_tile<4, MAXP>(G, ft, lane_id(), P);
@@ -738,7 +809,7 @@ __global__ __launch_bounds__(256) void k_logical_wide(const DevGraph *__restrict
     const int w = wave_item(swz);
     if (w >= nitems) return;
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     logw_tile<kLogWaveChunks, MAXP>(G, G.ftile[it.t], lane_id(), P);
 }
 
@@ -754,8 +825,8 @@ __global__ __launch_bounds__(256) void k_logical_wide(const DevGraph *__restrict
 // iterations; the messages are copied back at the end.
 constexpr int kSolveThreads = 512;
 
-template <bool MAXP>
-__device__ __forceinline__ void pair_any(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+template <bool MAXP, class GV>
+__device__ __forceinline__ void pair_any(const GV &G, const FTile &ft, int lane, const TParams &P) {
     if (ft.a == ft.b) switch (ft.a) {
         case 2: pair_tile<2, 2, true, MAXP, false, false>(G, ft, lane, P); return;
         case 3: pair_tile<3, 3, true, MAXP, false, false>(G, ft, lane, P); return;
@@ -860,8 +931,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve_resident(const DevGraph
 // --------------------------------------------------------------------------
 // One tile of a generic class: `rows` holds the class's configuration rows
 // (C x A bytes), nv / acc / sacc are [R][64] float arrays in LDS.
-template <bool MAXP>
-__device__ __forceinline__ void gen_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P,
+template <bool MAXP, class GV>
+__device__ __forceinline__ void gen_tile(const GV &G, const FTile &ft, int lane, const TParams &P,
                                          uint8_t *rows, float *nv, float *acc, float *sacc) {
     const GenClass gc = G.gcls[ft.a];
     const int A = gc.arity, C = gc.ncfg;
@@ -921,8 +992,8 @@ __device__ __forceinline__ void gen_tile(const DevGraph &G, const FTile &ft, int
 // incoming terms and scores in registers.  The generic class layout (rows of
 // slot j at j*N), so the reverse sweep's generic kernel serves these tiles.
 // u_j[s] = LSE_T{score(c) : c_j = s} - n_j[s], score = phi + n_0 + n_1 + n_2.
-template <int N, bool MAXP>
-__device__ __forceinline__ void tri_tile(const DevGraph &G, const FTile &ft, int lane, const TParams &P) {
+template <int N, bool MAXP, class GV>
+__device__ __forceinline__ void tri_tile(const GV &G, const FTile &ft, int lane, const TParams &P) {
     const float *mrow = G.m + ft.m_off + lane;
     float m[3][N], x[3][N];
 #pragma unroll
@@ -980,7 +1051,7 @@ __global__ __launch_bounds__(256) void k_tri(const DevGraph *__restrict__ gs, co
     const int w = wave_index(4);
     if (w >= nitems) return;
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     tri_tile<N, MAXP>(G, G.ftile[it.t], lane_id(), P);
 }
 
@@ -996,7 +1067,7 @@ __global__ __launch_bounds__(64) void k_gen(const DevGraph *__restrict__ gs, con
     const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
     if (w >= nitems) return;
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     gen_tile<MAXP>(G, G.ftile[it.t], lane_id(), P, rows, nv, acc, sacc);
 }
 
@@ -1009,7 +1080,7 @@ __global__ __launch_bounds__(64) void k_gen_dyn(const DevGraph *__restrict__ gs,
     const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
     if (w >= nitems) return;
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     float *nv = (float *)(smem + rows_bytes);
     float *acc = nv + nrows * kLanes;
     float *sacc = acc + nrows * kLanes;
@@ -1039,7 +1110,7 @@ __global__ __launch_bounds__(256) void k_pair_adj(const DevGraph *__restrict__ g
     if (w >= nitems) return;
     const int lane = lane_id();
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     const FTile ft = G.ftile[it.t];
     const int na = EXACT ? NA : ft.a;
     const int nb = EXACT ? NB : ft.b;
@@ -1196,7 +1267,7 @@ __global__ __launch_bounds__(64) void k_gen_adj(const DevGraph *__restrict__ gs,
     if (w >= nitems) return;
     const int lane = lane_id();
     const WorkItem it = items[w];
-    const DevGraph &G = gs[it.g];
+    const GGraph G = glob(gs[it.g]);
     const FTile ft = G.ftile[it.t];
     const GenClass gc = G.gcls[ft.a];
     const int A = gc.arity, C = gc.ncfg;
@@ -1282,7 +1353,7 @@ __global__ __launch_bounds__(256) void k_readout_adj(const DevGraph *__restrict_
     const int w = wave_index(4);
     if (w >= ntiles) return;
     const int lane = lane_id();
-    const DevGraph &G = gs[0];
+    const GGraph G = glob(gs[0]);
     const int v = w * kLanes + lane;
     if (v >= G.V) return;
     const int n = G.vn[v];
@@ -1311,7 +1382,7 @@ __global__ void k_accumulate(float *__restrict__ y, const float *__restrict__ x,
 }
 
 __global__ void k_logpot_out(const DevGraph *__restrict__ gs, const float *__restrict__ panel, float *__restrict__ out) {
-    const DevGraph &G = gs[0];
+    const GGraph G = glob(gs[0]);
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= G.F) return;
     const int base = G.fac_phi[f];
@@ -1323,7 +1394,7 @@ __global__ void k_logpot_out(const DevGraph *__restrict__ gs, const float *__res
 
 __global__ void k_evidence_out(const DevGraph *__restrict__ gs, const float *__restrict__ panel,
                                float *__restrict__ out) {
-    const DevGraph &G = gs[0];
+    const GGraph G = glob(gs[0]);
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= G.V) return;
     const float *row = panel + G.vtile[v / kLanes].b_off + (v % kLanes);
@@ -1337,8 +1408,8 @@ __global__ void k_evidence_out(const DevGraph *__restrict__ gs, const float *__r
 // q[v,s] = B[v,s] - LSE_T(B[v,:]) (or B), MAP = lowest-index argmax.
 // Variable tile w of G; flag_host (may be null) is also set on a non-finite
 // belief.
-template <bool MAXP>
-__device__ __forceinline__ void readout_tile(const DevGraph &G, int w, const TParams &P, float *__restrict__ qout,
+template <bool MAXP, class GV>
+__device__ __forceinline__ void readout_tile(const GV &G, int w, const TParams &P, float *__restrict__ qout,
                                              int normalized, int32_t *__restrict__ mapout,
                                              int32_t *__restrict__ flag_host) {
     const int lane = lane_id();
@@ -1385,7 +1456,7 @@ __global__ __launch_bounds__(256) void k_readout(const DevGraph *__restrict__ gs
                                                  int32_t *__restrict__ mapout) {
     const int w = wave_index(4);
     if (w >= ntiles) return;
-    readout_tile<MAXP>(gs[0], w, P, qout, normalized, mapout, nullptr);
+    readout_tile<MAXP>(glob(gs[0]), w, P, qout, normalized, mapout, nullptr);
 }
 
 // Read-outs of several graphs in one launch: blockIdx.y = job, each job's
@@ -1395,12 +1466,12 @@ __global__ __launch_bounds__(256) void k_readout_multi(const ReadJob *__restrict
     const ReadJob J = jobs[blockIdx.y];
     const int w = wave_index(4);
     if (w >= J.ntiles) return;
-    if (J.maxp) readout_tile<true>(*J.g, w, J.P, J.q, 1, J.map, J.flag);
-    else readout_tile<false>(*J.g, w, J.P, J.q, 1, J.map, J.flag);
+    if (J.maxp) readout_tile<true>(glob(*J.g), w, J.P, J.q, 1, J.map, J.flag);
+    else readout_tile<false>(glob(*J.g), w, J.P, J.q, 1, J.map, J.flag);
 }
 
 __global__ void k_msgs_out(const DevGraph *__restrict__ gs, float *__restrict__ out) {
-    const DevGraph &G = gs[0];
+    const GGraph G = glob(gs[0]);
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= G.E) return;
     const float *row = G.m + G.edge_maddr[e];
@@ -1410,7 +1481,7 @@ __global__ void k_msgs_out(const DevGraph *__restrict__ gs, float *__restrict__ 
 }
 
 __global__ void k_msgs_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
-    const DevGraph &G = gs[0];
+    const GGraph G = glob(gs[0]);
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= G.E) return;
     float *row = G.m + G.edge_maddr[e];
@@ -1420,7 +1491,7 @@ __global__ void k_msgs_in(const DevGraph *__restrict__ gs, const float *__restri
 }
 
 __global__ void k_evidence_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
-    const DevGraph &G = gs[0];
+    const GGraph G = glob(gs[0]);
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= G.V) return;
     float *row = G.theta + G.vtile[v / kLanes].b_off + (v % kLanes);
@@ -1437,7 +1508,8 @@ __host__ __device__ inline int residual_block_count(int E) {
     return ((E > 1 ? E : 1) + kResidualThreads - 1) / kResidualThreads;
 }
 
-__device__ __forceinline__ void residual_partial(const DevGraph &G, const float *__restrict__ mprev,
+template <class GV>
+__device__ __forceinline__ void residual_partial(const GV &G, const float *__restrict__ mprev,
                                                  float *__restrict__ partial, int block, float (&red)[256]) {
     const int e = block * kResidualThreads + (int)threadIdx.x;
     float r = 0.0f;
@@ -1474,7 +1546,7 @@ __device__ __forceinline__ void max_final(const float *__restrict__ partial, int
 __global__ __launch_bounds__(256) void k_residual(const DevGraph *__restrict__ gs, const float *__restrict__ mprev,
                                                   float *__restrict__ partial) {
     __shared__ float red[256];
-    residual_partial(gs[0], mprev, partial, (int)blockIdx.x, red);
+    residual_partial(glob(gs[0]), mprev, partial, (int)blockIdx.x, red);
 }
 
 __global__ __launch_bounds__(256) void k_max_final(const float *__restrict__ partial, int n, float *__restrict__ out) {
@@ -1497,7 +1569,7 @@ __global__ __launch_bounds__(256) void k_residual_multi(const ConvJob *__restric
     __shared__ float red[256];
     const ConvJob J = jobs[blockIdx.y];
     if ((int)blockIdx.x >= residual_block_count(J.E)) return;  // uniform over the block
-    residual_partial(*J.g, J.mprev, J.partial, (int)blockIdx.x, red);
+    residual_partial(glob(*J.g), J.mprev, J.partial, (int)blockIdx.x, red);
 }
 
 __global__ __launch_bounds__(256) void k_max_final_multi(const ConvJob *__restrict__ jobs, float *__restrict__ out) {
@@ -1511,7 +1583,7 @@ __global__ __launch_bounds__(256) void k_max_final_multi(const ConvJob *__restri
 __global__ void k_evidence_perturb(const DevGraph *__restrict__ views, const float *__restrict__ base,
                                    const float *__restrict__ noise, int64_t VS) {
     const int s = blockIdx.y;
-    const DevGraph &G = views[s];
+    const GGraph G = glob(views[s]);
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= G.V) return;
     const int64_t addr = G.vtile[v / kLanes].b_off + (v % kLanes);
@@ -1520,7 +1592,7 @@ __global__ void k_evidence_perturb(const DevGraph *__restrict__ views, const flo
 }
 
 __global__ void k_logpot_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
-    const DevGraph &G = gs[0];
+    const GGraph G = glob(gs[0]);
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= G.F) return;
     const int base = G.fac_phi[f];
@@ -1735,6 +1807,90 @@ hipError_t launch_residual(const DevGraph *gs, int E, const float *mprev, float 
     const int nb = residual_blocks(E);
     hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, st, gs, mprev, partial);
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, partial, nb, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- bandwidth probes
+// Plain streaming kernels that measure what an ordinary kernel reaches on
+// this device: float4 accesses, grid-stride, four float4 per thread in flight
+// per pass.  Every loaded component feeds the sum, and the sum is stored only
+// when it equals a value that finite sums of the probe's zero-filled data
+// never take, so no load can be dropped.
+namespace {
+constexpr float kProbeNever = -1.2345e-37f;
+
+__global__ __launch_bounds__(256) void k_stream_read(const float4 *__restrict__ src, int64_t n4,
+                                                     float *__restrict__ sink) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float acc = 0.0f;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        acc += ((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w)) + ((c.x + c.y) + (c.z + c.w)) +
+               ((d.x + d.y) + (d.z + d.w));
+    }
+    for (; i < n4; i += stride) {
+        const float4 a = src[i];
+        acc += (a.x + a.y) + (a.z + a.w);
+    }
+    if (acc == kProbeNever) sink[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_stream_copy(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                     int64_t n4) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n4; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_stream_write(float4 *__restrict__ dst, int64_t n4, float v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const float4 x = make_float4(v, v, v, v);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) dst[i] = x;
+}
+
+// reads five float4 per float4 written (src: 5 * m float4, dst: m float4),
+// about the read/write mix of an iteration's factor launches
+__global__ __launch_bounds__(256) void k_stream_mix(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                    int64_t m) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        float4 a = src[i];
+#pragma unroll
+        for (int k = 1; k < 5; ++k) {
+            const float4 b = src[i + k * m];
+            a.x += b.x;
+            a.y += b.y;
+            a.z += b.z;
+            a.w += b.w;
+        }
+        dst[i] = a;
+    }
+}
+}  // namespace
+
+hipError_t launch_stream_probe(int kind, const void *src, void *dst, int64_t bytes, int blocks, hipStream_t st) {
+    const int64_t n4 = bytes / 16;
+    switch (kind) {
+    case 0:
+        hipLaunchKernelGGL(k_stream_read, dim3(blocks), dim3(256), 0, st, (const float4 *)src, n4, (float *)dst);
+        break;
+    case 1:
+        hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, st, (const float4 *)src, (float4 *)dst, n4);
+        break;
+    case 2: hipLaunchKernelGGL(k_stream_write, dim3(blocks), dim3(256), 0, st, (float4 *)dst, n4, 0.0f); break;
+    default:
+        hipLaunchKernelGGL(k_stream_mix, dim3(blocks), dim3(256), 0, st, (const float4 *)src, (float4 *)dst,
+                           n4 / 5);
+        break;
+    }
     return hipGetLastError();
 }
 

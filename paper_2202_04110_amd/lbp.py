@@ -91,6 +91,8 @@ _sig("lbp_run_bp_until", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_floa
                                    C.POINTER(C.c_int32), C.POINTER(C.c_float)])
 _sig("lbp_run_bp_until_noalloc", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_int32,
                                            C.POINTER(C.c_int32), C.POINTER(C.c_float)])
+_sig("lbp_bandwidth_probe", C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_float)])
 _sig("lbp_sampler_create", C.c_int, [_P, C.c_int32, C.POINTER(_P)])
 _sig("lbp_sampler_run", C.c_int, [_P, C.c_int32, C.c_float, C.c_float, _P, _P, _P])
 _sig("lbp_sampler_free", None, [_P])
@@ -228,6 +230,14 @@ class Context:
 
     def use_graphs(self, enable: bool):
         check(_lib.lbp_ctx_use_graphs(self.h, int(bool(enable))))
+
+    def bandwidth_probe(self, kind: int, src, dst, nbytes: int, blocks: int, reps: int = 10) -> float:
+        """Milliseconds per launch of a plain streaming kernel (kind 0 read,
+        1 copy, 2 write, 3 five reads per write) over device buffers."""
+        ms = C.c_float()
+        check(_lib.lbp_bandwidth_probe(self.h, int(kind), _ptr(src) if src is not None else None, _ptr(dst),
+                                       int(nbytes), int(blocks), int(reps), C.byref(ms)))
+        return float(ms.value)
 
     def close(self):
         if self.h:
