@@ -527,6 +527,18 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
                 }
         if (!merged) L->fgroups.push_back(grp);
     }
+    // In the shared logical launch the wavefront-per-factor tiles (long
+    // chains: gathers, then wavefront scans) start first, the widest first,
+    // before the lane tiles fill the machine; launch order changes no
+    // element's arithmetic.
+    for (FGroup &g : L->fgroups) {
+        if (g.kind != TK_LOGL) continue;
+        std::stable_sort(g.tiles.begin(), g.tiles.end(), [&](int32_t x, int32_t y) {
+            const FTile &a = L->ftile[x], &b = L->ftile[y];
+            const int32_t ka = a.kind == TK_LOGW ? a.a : 0, kb = b.kind == TK_LOGW ? b.a : 0;
+            return ka > kb;
+        });
+    }
     L->zero_addr = (int32_t)M;
     M += (int64_t)kLanes * kLowStatesMax;
     L->M = M;
