@@ -356,6 +356,35 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
         } else {
             std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
         }
+        if (std::get<0>(class_key[c]) != TK_PAIR) continue;
+        // pairwise: inside a block whose factors join their two variables at
+        // no more than four distinct offsets (a grid: horizontal and vertical
+        // neighbours), factors with the same offset together, each group in
+        // its existing order; other blocks keep their order
+        auto delta = [&](int32_t f) {
+            const int64_t e0 = d->factor_edge_off[f];
+            return (int64_t)d->edge_var[e0 + 1] - d->edge_var[e0];
+        };
+        for (size_t i = 0; i < fl.size();) {
+            size_t j = i;
+            while (j < fl.size() && key(fl[j]) == key(fl[i])) ++j;
+            int64_t seen[4];
+            int nseen = 0;
+            bool few = true;
+            for (size_t k = i; k < j && few; ++k) {
+                const int64_t dk = delta(fl[k]);
+                int s = 0;
+                while (s < nseen && seen[s] != dk) ++s;
+                if (s == nseen) {
+                    if (nseen == 4) few = false;
+                    else seen[nseen++] = dk;
+                }
+            }
+            if (few && nseen > 1)
+                std::stable_sort(fl.begin() + i, fl.begin() + j,
+                                 [&](int32_t x, int32_t y) { return delta(x) < delta(y); });
+            i = j;
+        }
     }
     for (size_t c = 0; c < class_key.size(); ++c) {
         const int32_t kind = std::get<0>(class_key[c]);
@@ -368,12 +397,27 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             const int32_t na = std::get<1>(class_key[c]), nb = std::get<2>(class_key[c]);
             grp.a = na;
             grp.b = nb;
-            for (size_t i0 = 0; i0 < facs.size(); i0 += kLanes) {
+            // Tiles take 64 consecutive factors, but close early where the
+            // (block, variable offset) group changes once 48 lanes are
+            // filled: a grid's tiles then each hold one run of horizontal or
+            // vertical factors, whose slot variables are consecutive lanes.
+            auto group = [&](size_t i) {
+                const int64_t e0 = d->factor_edge_off[facs[i]];
+                return std::make_pair((int64_t)d->edge_var[e0] / kLanes,
+                                      (int64_t)d->edge_var[e0 + 1] - d->edge_var[e0]);
+            };
+            for (size_t i0 = 0, len = 0; i0 < facs.size(); i0 += len) {
+                len = std::min<size_t>(kLanes, facs.size() - i0);
+                for (size_t l = 48; l < len; ++l)
+                    if (group(i0 + l) != group(i0 + l - 1)) {
+                        len = l;
+                        break;
+                    }
                 FTile ft{};
                 ft.kind = TK_PAIR;
                 ft.a = na;
                 ft.b = nb;
-                ft.nact = (int32_t)std::min<size_t>(kLanes, facs.size() - i0);
+                ft.nact = (int32_t)len;
                 ft.m_off = (int32_t)M;
                 ft.phi_off = (int32_t)P;
                 ft.vb_off = (int32_t)L->fvb.size();
@@ -595,6 +639,20 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
         L->fvb.size() >= (size_t)INT32_MAX)
         return bad(err, "index tables exceed 2^31 entries", LBP_E_UNSUPPORTED);
 
+    // pairwise slots whose lanes hold consecutive variables (grids: nearly
+    // every tile) are described by their first variable, so the fused kernel
+    // reads one value per slot instead of one per lane
+    L->faff.assign(2 * L->ftile.size(), -1);
+    for (size_t t = 0; t < L->ftile.size(); ++t) {
+        const FTile &ft = L->ftile[t];
+        if (ft.kind != TK_PAIR || ft.nact < 1) continue;
+        for (int32_t r = 0; r < 2; ++r) {
+            const int32_t *fv = L->fvar.data() + ft.vb_off + (size_t)r * kLanes;
+            bool affine = true;
+            for (int32_t l = 1; l < ft.nact && affine; ++l) affine = fv[l] == fv[0] + l;
+            if (affine) L->faff[2 * t + r] = fv[0];
+        }
+    }
     L->fusable = L->hvar.empty() && !L->fgroups.empty();
     for (const FGroup &fg : L->fgroups)
         if (fg.kind != TK_PAIR || fg.a != fg.b) L->fusable = false;
@@ -798,6 +856,16 @@ int check_layout(const HostLayout &L, std::string *err) {
             return oob("factor potential address");
     if (!in(L.zero_addr + (int64_t)kLowStatesMax * kLanes - 1, M)) return oob("zero panel");
     if (L.fvar.size() != L.fvb.size()) return oob("fvar size");
+    if (L.faff.size() != 2 * L.ftile.size()) return oob("slot base size");
+    for (size_t t = 0; t < L.ftile.size(); ++t)
+        for (int32_t r = 0; r < 2; ++r) {
+            const int32_t v0 = L.faff[2 * t + r];
+            if (v0 < 0) continue;
+            const FTile &ft = L.ftile[t];
+            if (ft.kind != TK_PAIR) return oob("slot base of a non-pairwise tile");
+            for (int32_t l = 0; l < ft.nact; ++l)
+                if (L.fvar[ft.vb_off + (int64_t)r * kLanes + l] != v0 + l) return oob("slot base");
+        }
     if (L.fusable) {
         // the fused pairwise kernel recomputes each slot variable's belief from
         // its edge rows: the variable's tile, lane states and edge addresses

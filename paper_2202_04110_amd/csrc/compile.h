@@ -70,6 +70,7 @@ struct HostLayout {
     std::vector<FTile> ftile;
     std::vector<int32_t> fvb;
     std::vector<int32_t> fvar;  // variable of each (tile, slot, lane), same indexing as fvb (-1 idle)
+    std::vector<int32_t> faff;  // [tile][2]: first variable of a lane-contiguous pairwise slot, else -1
     bool fusable = false;       // every variable on the lane path, every factor dense pairwise
     std::vector<VTile> vtile;
     std::vector<int32_t> vedge, vns;

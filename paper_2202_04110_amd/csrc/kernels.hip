@@ -64,7 +64,7 @@ using gptr = T *;
 struct GGraph {
     gptr<float> m, mo, B, theta, phi;
     gptr<const FTile> ftile;
-    gptr<const int32_t> fvb, fvar;
+    gptr<const int32_t> fvb, fvar, faff;
     gptr<const VTile> vtile;
     gptr<const int32_t> vedge, vns;
     gptr<const HVar> hvar;
@@ -92,6 +92,7 @@ __device__ __forceinline__ GGraph glob(const DevGraph &d) {
     g.ftile = as_global(d.ftile);
     g.fvb = as_global(d.fvb);
     g.fvar = as_global(d.fvar);
+    g.faff = as_global(d.faff);
     g.vtile = as_global(d.vtile);
     g.vedge = as_global(d.vedge);
     g.vns = as_global(d.vns);
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
 // the graph streams from HBM, slower when it sits in the last-level cache.
 // The arithmetic is the same either way.
 template <int NA, int NB, bool EXACT, bool MAXP, bool FUSED, bool EARLY = false, class GV>
-__device__ __forceinline__ void pair_tile(const GV &G, const FTile &ft, int lane, const TParams &P) {
+__device__ __forceinline__ void pair_tile(const GV &G, const FTile &ft, int lane, const TParams &P, int t = -1) {
     const int na = EXACT ? NA : ft.a;
     const int nb = EXACT ? NB : ft.b;
     const float *r0 = G.m + ft.m_off + lane;
@@ -479,7 +480,12 @@ __device__ __forceinline__ void pair_tile(const GV &G, const FTile &ft, int lane
     float m0[NA], m1[NB], x0[NA], x1[NB];
     if (FUSED) {
         float b0[NA], b1[NB];
-        belief_regs2<NA, NB>(G, G.fvar[ft.vb_off + lane], na, G.fvar[ft.vb_off + kLanes + lane], nb, b0, b1);
+        // slot variables: from the tile's slot bases where the lanes hold
+        // consecutive variables (uniform), else one index per lane
+        const int a0 = t >= 0 ? G.faff[2 * t] : -1, a1 = t >= 0 ? G.faff[2 * t + 1] : -1;
+        const int va = a0 >= 0 ? (lane < ft.nact ? a0 + lane : -1) : G.fvar[ft.vb_off + lane];
+        const int vb = a1 >= 0 ? (lane < ft.nact ? a1 + lane : -1) : G.fvar[ft.vb_off + kLanes + lane];
+        belief_regs2<NA, NB>(G, va, na, vb, nb, b0, b1);
 #pragma unroll
         for (int i = 0; i < NA; ++i)
             if (i < na) {
@@ -566,7 +572,7 @@ __global__ __launch_bounds__(256) void k_pair(const DevGraph *__restrict__ gs, c
     const WorkItem it = items[w];
     const GGraph G = glob(gs[it.g]);
     const FTile ft = G.ftile[it.t];
-    pair_tile<NA, NB, EXACT, MAXP, FUSED, EARLY>(G, ft, lane_id(), P);
+    pair_tile<NA, NB, EXACT, MAXP, FUSED, EARLY>(G, ft, lane_id(), P, it.t);
 }
 
 // Square pairwise tiles of several state counts (2..8) in one launch: each
@@ -583,13 +589,13 @@ __global__ __launch_bounds__(256) void k_pair_mix(const DevGraph *__restrict__ g
     const FTile ft = G.ftile[it.t];
     const int lane = lane_id();
     switch (__builtin_amdgcn_readfirstlane(ft.a)) {
-    case 2: pair_tile<2, 2, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
-    case 3: pair_tile<3, 3, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
-    case 4: pair_tile<4, 4, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
-    case 5: pair_tile<5, 5, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
-    case 6: pair_tile<6, 6, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
-    case 7: pair_tile<7, 7, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
-    default: pair_tile<8, 8, true, MAXP, FUSED, EARLY>(G, ft, lane, P); break;
+    case 2: pair_tile<2, 2, true, MAXP, FUSED, EARLY>(G, ft, lane, P, it.t); break;
+    case 3: pair_tile<3, 3, true, MAXP, FUSED, EARLY>(G, ft, lane, P, it.t); break;
+    case 4: pair_tile<4, 4, true, MAXP, FUSED, EARLY>(G, ft, lane, P, it.t); break;
+    case 5: pair_tile<5, 5, true, MAXP, FUSED, EARLY>(G, ft, lane, P, it.t); break;
+    case 6: pair_tile<6, 6, true, MAXP, FUSED, EARLY>(G, ft, lane, P, it.t); break;
+    case 7: pair_tile<7, 7, true, MAXP, FUSED, EARLY>(G, ft, lane, P, it.t); break;
+    default: pair_tile<8, 8, true, MAXP, FUSED, EARLY>(G, ft, lane, P, it.t); break;
     }
 }
 

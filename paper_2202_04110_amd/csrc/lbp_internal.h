@@ -95,6 +95,7 @@ struct DevGraph {
     const FTile *ftile;
     const int32_t *fvb;   // belief address of each (tile, slot, lane)
     const int32_t *fvar;  // variable of each (tile, slot, lane), -1 for idle lanes
+    const int32_t *faff;  // per pairwise tile and slot: v0 when lane l < nact holds variable v0 + l, else -1
     const VTile *vtile;
     const int32_t *vedge; // message address of each (var tile, k, lane)
     const int32_t *vns;   // states of each low-degree lane, 0 for others

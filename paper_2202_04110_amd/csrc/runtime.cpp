@@ -276,6 +276,7 @@ struct Piece {
 struct GraphPieces {
     std::vector<Piece> p;
     size_t total = 0;
+    size_t faff;
     size_t m, B, th, phi, ft, fvb, fvar, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
     size_t m2 = 0, fdg = 0;
     size_t data_end = 0;
@@ -294,6 +295,7 @@ struct GraphPieces {
         ft = add(L.ftile.data(), sizeof(FTile) * L.ftile.size());
         fvb = add(L.fvb.data(), sizeof(int32_t) * L.fvb.size());
         fvar = add(L.fvar.data(), sizeof(int32_t) * L.fvar.size());
+        faff = add(L.faff.data(), sizeof(int32_t) * L.faff.size());
         vt = add(L.vtile.data(), sizeof(VTile) * L.vtile.size());
         ve = add(L.vedge.data(), sizeof(int32_t) * L.vedge.size());
         vns = add(L.vns.data(), sizeof(int32_t) * L.vns.size());
@@ -381,6 +383,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         h.ftile = (const FTile *)ptr(gp.ft);
         h.fvb = (const int32_t *)ptr(gp.fvb);
         h.fvar = (const int32_t *)ptr(gp.fvar);
+        h.faff = (const int32_t *)ptr(gp.faff);
         h.vtile = (const VTile *)ptr(gp.vt);
         h.vedge = (const int32_t *)ptr(gp.ve);
         h.vns = (const int32_t *)ptr(gp.vns);

@@ -72,7 +72,15 @@ int main() {
          {"factor potential address", [](HostLayout &L) { L.fac_phi[2] = (int32_t)L.P; }},
          {"fused slot variable", [](HostLayout &L) { L.fvar[1] = (int32_t)L.V; }},
          {"fused slot states", [](HostLayout &L) { L.vns[L.fvar[0]] = 2; }},
-         {"zero panel", [](HostLayout &L) { L.zero_addr = (int32_t)L.M; }}});
+         {"zero panel", [](HostLayout &L) { L.zero_addr = (int32_t)L.M; }},
+         {"slot base", [](HostLayout &L) {
+              for (int32_t &v0 : L.faff)
+                  if (v0 >= 0) {
+                      v0 += 1;
+                      break;
+                  }
+          }},
+         {"slot base size", [](HostLayout &L) { L.faff.pop_back(); }}});
 
     // a hub joined to 40 and to 300 binary leaves (wavefront- and
     // block-per-variable paths), an OR over 150 parents (wavefront logical
