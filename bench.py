@@ -116,6 +116,26 @@ def plain_copy_gbps(mib=1024, reps=10):
     return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
+def stream_probes(ctx, mib=1024, blocks=(512, 1024, 2048, 4096), reps=5):
+    """The library's plain streaming kernels (lbp_bandwidth_probe: float4,
+    grid-stride) over `mib` MiB, the best of a few grid sizes per kind: the
+    bandwidth an ordinary kernel reaches on this device, per read/write mix."""
+    import torch
+
+    n = mib * (1 << 20)
+    a = torch.zeros(n // 4, dtype=torch.float32, device="cuda")
+    b = torch.zeros(n // 4, dtype=torch.float32, device="cuda")
+    out = {"bytes": n, "blocks_tried": list(blocks)}
+    for kind, name, moved in ((0, "read_gbps", 1.0), (1, "copy_gbps", 2.0), (2, "write_gbps", 1.0),
+                              (3, "mix5r1w_gbps", 1.2)):
+        nb = n if kind != 3 else (n // 80) * 80
+        best = max(moved * nb / (ctx.bandwidth_probe(kind, a, b, nb, bl, reps) * 1e-3) / 1e9 for bl in blocks)
+        out[name] = best
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(spec, iters_full, damping, temperature, budget_s=12.0):
     """The FP64 oracle on the host's cores, timed on a bounded number of
     iterations of the same graph; scaled to edge-state updates per second."""
@@ -521,6 +541,7 @@ def main():
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, tkey, shape)
     copy_gbps = plain_copy_gbps()
+    probes = stream_probes(ctx)
     out = {
         "metric": "edge-state message updates/sec",
         "value": value,
@@ -542,11 +563,13 @@ def main():
                      "algorithmic_bytes_per_launch": kbytes, "avg_launch_ms": kms,
                      "plain_copy_gbps": copy_gbps,
                      "frac_of_plain_copy": achieved / copy_gbps if copy_gbps else None,
+                     "frac_of_in_house_mix": achieved / probes["mix5r1w_gbps"],
                      "working_set_bytes": bm["floor_bytes"],
                      "cache_resident": bm["floor_bytes"] < LLC_BYTES,
                      "note": ("the working set fits the 256 MB last-level cache, so this fraction is not an HBM "
                               "claim; roofline_beyond_cache holds the HBM-bound case")
                      if bm["floor_bytes"] < LLC_BYTES else "working set exceeds the last-level cache"},
+        "in_house_stream": probes,
         "phases_ms": {"variable": t_var, "factor": t_fac, "two_phase_iteration": t_it, "fused_iteration": t_fused},
         "iteration_gbps": bm["iter_bytes"] / (t_it * 1e-3) / 1e9,
         "solve_gbps": bm["iter_bytes"] * iters / (ms_step * 1e-3) / 1e9,
@@ -563,6 +586,8 @@ def main():
     if not args.no_scaleup and args.workload != "potts2048":
         sc = scaleup_leg(lbp, W, ctx, tune)
         out["roofline_beyond_cache"] = sc.pop("roofline")
+        out["roofline_beyond_cache"]["frac_of_in_house_mix"] = (out["roofline_beyond_cache"]["achieved"] /
+                                                                probes["mix5r1w_gbps"])
         out["potts2048"] = sc
         print("potts2048: %.2f ms per solve, fused launch %.1f us, frac %.3f" % (
             sc["ms_per_solve"], 1e3 * out["roofline_beyond_cache"]["avg_launch_ms"],
