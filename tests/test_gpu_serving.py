@@ -65,6 +65,33 @@ def test_served_mix_equals_lone_runs(lbp, ctx):
         assert np.abs(res[i]["beliefs"] - qo).max() < 1e-4
 
 
+def test_served_full_size_requests_equal_lone_runs(lbp, ctx):
+    """Requests at the top of the served mix's range (sides up to 256, up to
+    8 states, two with a backward pass) arriving together with small ones in
+    a server whose budget holds only a few of them at a time: each result
+    is bitwise its lone run (beliefs, MAP, gradient)."""
+    from paper_2202_04110_amd.serving import run_stream
+    shapes = [(256, 8, True), (16, 3, False), (231, 7, False), (40, 2, False), (256, 8, False),
+              (180, 5, True), (24, 8, False), (200, 6, False)]
+    reqs = [{"id": i, "L": L, "n": n, "seed": 9100 + i, "backward": b} for i, (L, n, b) in enumerate(shapes)]
+    specs = [W.request_graph(r) for r in reqs]
+    gqs = [W.request_loss_coeffs(r) if r["backward"] else None for r in reqs]
+    srv = lbp.Server(ctx, budget_bytes=400 << 20, max_slots=4, steps_per_round=5)
+    res, summ = run_stream(srv, specs, np.zeros(len(specs)), 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10,
+                           timeout=300)
+    st = srv.stats()
+    srv.close()
+    print("served:", {k: v for k, v in summ.items() if k != "stats"}, st)
+    assert summ["ok"] == len(reqs)
+    assert st["max_resident"] > 1
+    for i, spec in enumerate(specs):
+        q, mp, gphi = lone(lbp, ctx, spec, 50, 0.5, 1.0, gqs[i])
+        np.testing.assert_array_equal(res[i]["beliefs"], q)
+        np.testing.assert_array_equal(res[i]["map"], mp)
+        if gqs[i] is not None:
+            np.testing.assert_array_equal(res[i]["grad_logpot"], gphi)
+
+
 def test_mixed_parameters_and_kinds(lbp, ctx):
     """Requests with different temperatures and factor kinds in one server."""
     specs = [W.potts_grid(20, 3, 1), W.ising_grid(16, 2), W.deconv(seed=4, K=2, tw=4, sd=10, img=12),
