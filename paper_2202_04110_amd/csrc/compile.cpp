@@ -738,6 +738,11 @@ int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, floa
     return LBP_OK;
 }
 
+int check_potentials_finite(const lbp_graph_desc *d, int64_t Tn, std::string *err) {
+    const int64_t i = Tn > 0 ? first_nonfinite(d->log_potentials, Tn) : -1;
+    return i >= 0 ? bad(err, at("log_potentials", i) + " is not finite") : LBP_OK;
+}
+
 // Replays the address arithmetic of every kernel over the compiled layout and
 // checks each access against its array's size.  Host only.
 int check_layout(const HostLayout &L, std::string *err) {

@@ -101,6 +101,10 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
 // floats) of a layout compiled from `d`, checking the potentials for NaN and
 // infinity (LBP_E_INVALID naming the first).
 int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, float *phi, std::string *err);
+// LBP_E_INVALID naming the first NaN or infinite log-potential of `d`, else
+// LBP_OK (the check fill_panels makes on its way, for callers that leave the
+// panels to the device).
+int check_potentials_finite(const lbp_graph_desc *d, int64_t Tn, std::string *err);
 // Host replay of every kernel's addresses against the layout's array sizes.
 int check_layout(const HostLayout &L, std::string *err);
 

@@ -277,6 +277,8 @@ struct GraphPieces {
     std::vector<Piece> p;
     size_t total = 0;
     size_t faff;
+    bool raw = false;       // the image holds the raw evidence and tables; panels are scattered on the device
+    size_t rev = 0, rlp = 0;
     size_t m, B, th, phi, ft, fvb, fvar, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
     size_t m2 = 0, fdg = 0;
     size_t data_end = 0;
@@ -289,9 +291,18 @@ struct GraphPieces {
             total += align256(std::max<size_t>(bytes, 4));
             return p.size() - 1;
         };
-        // panels not compiled into the layout are written in place later
-        th = add(L.theta_panel.size() == (size_t)L.VB ? L.theta_panel.data() : nullptr, sizeof(float) * L.VB);
-        phi = add(L.phi_panel.size() == (size_t)L.P ? L.phi_panel.data() : nullptr, sizeof(float) * L.P);
+        // A layout compiled with its panels carries them in the image.  One
+        // compiled without them (the server's preparation threads) carries the
+        // evidence and tables as given instead, and graph_create scatters them
+        // into panels that start as zeros: the device does the transpose.
+        raw = L.theta_panel.size() != (size_t)L.VB || L.phi_panel.size() != (size_t)L.P;
+        if (raw) {
+            rev = add(nullptr, sizeof(float) * L.VS);  // written by graph_fill_image
+            rlp = add(nullptr, sizeof(float) * L.Tn);
+        } else {
+            th = add(L.theta_panel.data(), sizeof(float) * L.VB);
+            phi = add(L.phi_panel.data(), sizeof(float) * L.P);
+        }
         ft = add(L.ftile.data(), sizeof(FTile) * L.ftile.size());
         fvb = add(L.fvb.data(), sizeof(int32_t) * L.fvb.size());
         fvar = add(L.fvar.data(), sizeof(int32_t) * L.fvar.size());
@@ -319,6 +330,10 @@ struct GraphPieces {
         m = add(nullptr, sizeof(float) * L.M);
         B = add(nullptr, sizeof(float) * L.VB);
         fl = add(nullptr, sizeof(int32_t) * 4);
+        if (raw) {
+            th = add(nullptr, sizeof(float) * L.VB);
+            phi = add(nullptr, sizeof(float) * L.P);
+        }
         q = add(nullptr, sizeof(float) * L.VS);
         map = add(nullptr, sizeof(int32_t) * L.V);
         if (fused) {
@@ -339,11 +354,15 @@ int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d, 
     for (const Piece &p : gp.p)
         if (p.src && p.bytes) std::memcpy(image + p.off, p.src, p.bytes);
     pack_lists(gp.ll, image + gp.p[gp.items].off);
-    if (L.theta_panel.size() == (size_t)L.VB && L.phi_panel.size() == (size_t)L.P) return LBP_OK;
-    // panels left to fill_panels: written here, in place
+    if (!gp.raw) return LBP_OK;
+    // the evidence and tables as given (graph_create scatters them into panels)
     std::string e;
     if (!d) return set_error(LBP_E_INVALID, "graph image: the layout has no panels and no description was given");
-    return fill_panels(d, L, (float *)(image + gp.p[gp.th].off), (float *)(image + gp.p[gp.phi].off), err ? err : &e);
+    float *ev = (float *)(image + gp.p[gp.rev].off);
+    if (d->evidence) std::memcpy(ev, d->evidence, sizeof(float) * L.VS);
+    else std::memset(ev, 0, sizeof(float) * L.VS);
+    if (L.Tn > 0) std::memcpy(image + gp.p[gp.rlp].off, d->log_potentials, sizeof(float) * L.Tn);
+    return check_potentials_finite(d, L.Tn, err ? err : &e);
 }
 
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
@@ -371,7 +390,15 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
             wait = true;  // the image built here is freed before returning
             own_image = (char *)panel_alloc(gp.data_end);
             if (!own_image) throw std::bad_alloc();
-            graph_fill_image(L, own_image);  // compiled with its panels
+            std::string ierr;
+            const int irc = gp.raw ? set_error(LBP_E_INVALID, "graph_create: a layout without panels needs its image")
+                                   : graph_fill_image(L, own_image, nullptr, &ierr);  // compiled with its panels
+            if (irc != LBP_OK) {
+                panel_free(own_image);
+                if (g->owns_memory) (void)hipFree(g->dmem);
+                delete g;
+                return irc;
+            }
             image = own_image;
         }
         DevGraph &h = g->host;
@@ -411,6 +438,10 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         std::memcpy(image + gp.p[gp.dg].off, &g->host, sizeof(DevGraph));
         hipError_t e = hipMemcpyAsync(g->dmem, image, gp.data_end, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemsetAsync(g->dmem + gp.data_end, 0, gp.total - gp.data_end, st);
+        if (gp.raw && e == hipSuccess) {  // panels from the raw evidence and tables of the image
+            e = launch_evidence_in(g->dgraph, (int)L.V, (const float *)ptr(gp.rev), st);
+            if (e == hipSuccess) e = launch_logpot_in(g->dgraph, (int)L.F, (const float *)ptr(gp.rlp), st);
+        }
         DevGraph fv[2];
         if (gp.fused) {
             float *m2 = (float *)ptr(gp.m2);

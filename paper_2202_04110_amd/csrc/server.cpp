@@ -1017,11 +1017,16 @@ int server_create(lbp_ctx *ctx, int64_t budget, int32_t max_slots, int32_t steps
         });
         s->th = std::thread([raw] { raw->run(); });
         // preparation threads: half the CPUs this process may run on, at
-        // most 8 (more contend for host memory bandwidth and run slower)
+        // most 8 (more contend for host memory bandwidth and run slower);
+        // LBP_SERVER_PREP_THREADS (1..64) overrides the count
         unsigned hw = std::max(1u, std::thread::hardware_concurrency());
         cpu_set_t set;
         if (sched_getaffinity(0, sizeof(set), &set) == 0) hw = std::max(1, CPU_COUNT(&set));
-        const unsigned np = std::min(8u, std::max(1u, hw / 2));
+        unsigned np = std::min(8u, std::max(1u, hw / 2));
+        if (const char *env = getenv("LBP_SERVER_PREP_THREADS")) {
+            const long v = strtol(env, nullptr, 10);
+            if (v >= 1 && v <= 64) np = (unsigned)v;
+        }
         for (unsigned i = 0; i < np; ++i) s->preps.emplace_back([raw] { raw->prep_loop(); });
         *out = s.release();
         return LBP_OK;
