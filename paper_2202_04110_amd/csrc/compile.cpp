@@ -397,10 +397,12 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             const int32_t na = std::get<1>(class_key[c]), nb = std::get<2>(class_key[c]);
             grp.a = na;
             grp.b = nb;
-            // Tiles take 64 consecutive factors, but close early where the
-            // (block, variable offset) group changes once 48 lanes are
-            // filled: a grid's tiles then each hold one run of horizontal or
-            // vertical factors, whose slot variables are consecutive lanes.
+            // Tiles take 64 consecutive factors, but a tile whose factors so
+            // far form one (block, variable offset) group closes early where
+            // that group ends, once 48 lanes are filled: a grid's tiles then
+            // each hold one run of horizontal or vertical factors, whose slot
+            // variables are consecutive lanes.  Graphs whose offsets scatter
+            // keep full tiles.
             auto group = [&](size_t i) {
                 const int64_t e0 = d->factor_edge_off[facs[i]];
                 return std::make_pair((int64_t)d->edge_var[e0] / kLanes,
@@ -408,11 +410,11 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             };
             for (size_t i0 = 0, len = 0; i0 < facs.size(); i0 += len) {
                 len = std::min<size_t>(kLanes, facs.size() - i0);
-                for (size_t l = 48; l < len; ++l)
-                    if (group(i0 + l) != group(i0 + l - 1)) {
-                        len = l;
-                        break;
-                    }
+                if (len > 48 && group(i0) == group(i0 + 47)) {
+                    size_t l = 1;
+                    while (l < len && group(i0 + l) == group(i0)) ++l;
+                    if (l >= 48) len = l;  // one run up to lane l (else the run broke early: a full tile)
+                }
                 FTile ft{};
                 ft.kind = TK_PAIR;
                 ft.a = na;
