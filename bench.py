@@ -172,7 +172,7 @@ def cpu_baseline(spec, iters_full, damping, temperature, budget_s=12.0):
             "host_cpu": model, "host_cpus_visible": os.cpu_count()}
 
 
-def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
+def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5, steps=10, slots=64):
     """Served stream: n Potts requests (side log-uniform 16..256, 2..8
     states, sum-product T=1, damping 0.5, 50 iterations; 10% carry a backward
     pass with checkpoints every 10), per HBM budget.  Capacity R is measured
@@ -188,16 +188,17 @@ def serving_leg(lbp, W, ctx, n, budgets_mb, seed=5):
     specs = [W.request_graph(r) for r in reqs]
     gqs = [W.request_loss_coeffs(r) if r["backward"] else None for r in reqs]
     out = {"requests": n, "iters": 50, "backward_requests": sum(g is not None for g in gqs),
+           "max_slots": slots, "steps_per_round": steps,
            "edge_states_mean": float(np.mean([s.num_edge_states for s in specs])), "budgets": {},
            "warmup": "one untimed burst of the same requests first (fills the process-wide pinned result pool)"}
-    srv = lbp.Server(ctx, budget_bytes=budgets_mb[0] << 20, max_slots=64, steps_per_round=5)
+    srv = lbp.Server(ctx, budget_bytes=budgets_mb[0] << 20, max_slots=slots, steps_per_round=steps)
     run_stream(srv, specs, np.zeros(n), 50, 0.5, 1.0, grad_qs=gqs, ckpt_every=10)
     srv.close()
     for budget_mb in budgets_mb:
         runs = {}
         for label, frac in (("burst", None), ("0.5R", 0.5), ("0.8R", 0.8), ("1.0R", 1.0),
                             ("burst, early exit", None)):
-            srv = lbp.Server(ctx, budget_bytes=budget_mb << 20, max_slots=64, steps_per_round=5)
+            srv = lbp.Server(ctx, budget_bytes=budget_mb << 20, max_slots=slots, steps_per_round=steps)
             if frac is None:
                 arr = np.zeros(n)
             else:
@@ -445,6 +446,9 @@ def main():
                     help="also run the served stream with N requests (0: skip)")
     ap.add_argument("--serving-budget-mb", default="512,2048",
                     help="comma-separated HBM budgets of the served stream, in MiB")
+    ap.add_argument("--serving-steps", type=int, default=10,
+                    help="iterations per server round (requests join and leave at round boundaries)")
+    ap.add_argument("--serving-slots", type=int, default=64, help="most requests resident at once")
     ap.add_argument("--samples", type=int, default=0, metavar="S",
                     help="also time S perturb-and-MAP samples of the deconvolution graph in shared launches")
     ap.add_argument("--batch", type=int, default=64, metavar="N",
@@ -582,7 +586,8 @@ def main():
     }
     if args.serving:
         out["serving"] = serving_leg(lbp, W, ctx, args.serving,
-                                     [int(x) for x in str(args.serving_budget_mb).split(",") if x])
+                                     [int(x) for x in str(args.serving_budget_mb).split(",") if x],
+                                     steps=args.serving_steps, slots=args.serving_slots)
     if not args.no_scaleup and args.workload != "potts2048":
         sc = scaleup_leg(lbp, W, ctx, tune)
         out["roofline_beyond_cache"] = sc.pop("roofline")
