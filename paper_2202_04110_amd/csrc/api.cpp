@@ -754,9 +754,9 @@ int lbp_batch_create(lbp_ctx *ctx, lbp_graph *const *graphs, int32_t num_graphs,
     try {
         HIP_TRY(hipSetDevice(ctx->device));
         LaunchLists ll;
-        std::vector<WorkItem> mids, highs;
-        for (int32_t gi = 0; gi < num_graphs; ++gi) add_to_lists(ll, gi, graphs[gi]->shape, &mids, &highs);
-        finish_lists(ll, mids, highs, true);
+        std::vector<WorkItem> mids, highs, cols;
+        for (int32_t gi = 0; gi < num_graphs; ++gi) add_to_lists(ll, gi, graphs[gi]->shape, &mids, &highs, &cols);
+        finish_lists(ll, mids, highs, cols, true);
         const size_t gbytes = align256(sizeof(DevGraph) * 3 * std::max(1, num_graphs));
         const size_t total = gbytes + lists_bytes(ll);
         b = new lbp_batch;
@@ -832,9 +832,9 @@ int lbp_sampler_create(lbp_graph *g, int32_t num_samples, lbp_sampler **out) {
         HIP_TRY(hipSetDevice(g->ctx->device));
         const int32_t S = num_samples;
         LaunchLists ll;
-        std::vector<WorkItem> mids, highs;
-        for (int32_t s = 0; s < S; ++s) add_to_lists(ll, s, g->shape, &mids, &highs);
-        finish_lists(ll, mids, highs);
+        std::vector<WorkItem> mids, highs, cols;
+        for (int32_t s = 0; s < S; ++s) add_to_lists(ll, s, g->shape, &mids, &highs, &cols);
+        finish_lists(ll, mids, highs, cols);
         const size_t vbytes = align256(sizeof(DevGraph) * S), lbytes = lists_bytes(ll);
         const size_t mb = align256(sizeof(float) * g->M), bb = align256(sizeof(float) * g->VB),
                      fb = align256(sizeof(int32_t) * 4);

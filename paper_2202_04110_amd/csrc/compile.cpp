@@ -593,26 +593,62 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
     // ------------------------------------------------ variable edge-address rows
     L->vns.assign(nvt * kLanes, 0);
     std::map<int32_t, size_t> vgroup_of;
+    auto degree = [&](int64_t v) { return adj_off[v + 1] - adj_off[v]; };
+    auto edge_addr = [&](int64_t v, int64_t k) { return L->edge_maddr[adj[adj_off[v] + k]]; };
+    // Column group of w variables from v (inside [v, vend) of one var tile):
+    // all on the block path with v's state count, and for each neighbouring
+    // pair, variable u + 1's k-th edge is the message right after variable
+    // u's in at least 3/4 of their edge rows.
+    auto column_ok = [&](int64_t v, int64_t w, int64_t vend) {
+        if (v + w > vend) return false;
+        for (int64_t u = v; u < v + w; ++u)
+            if (degree(u) <= kMidDegMax || L->vn[u] != L->vn[v]) return false;
+        for (int64_t u = v; u + 1 < v + w; ++u) {
+            const int64_t both = std::min(degree(u), degree(u + 1));
+            int64_t side = 0;
+            for (int64_t k = 0; k < both; ++k) side += edge_addr(u + 1, k) == edge_addr(u, k) + 1;
+            if (4 * side < 3 * std::max(degree(u), degree(u + 1))) return false;
+        }
+        return true;
+    };
     for (int64_t t = 0; t < nvt; ++t) {
         int32_t kmax = 0, nlow = 0;
         const int64_t v0 = t * kLanes, v1 = std::min<int64_t>(V, v0 + kLanes);
         for (int64_t v = v0; v < v1; ++v) {
-            int64_t deg = adj_off[v + 1] - adj_off[v];
+            int64_t deg = degree(v);
             const bool low = deg <= kLowDegMax && L->vn[v] <= kLowStatesMax;
             if (low) {
                 kmax = std::max<int32_t>(kmax, (int32_t)deg);
                 nlow = std::max<int32_t>(nlow, L->vn[v]);
                 L->vns[v] = L->vn[v];
-            } else {
-                HVar h{};
-                h.b_addr = vaddr[v];
-                h.n = L->vn[v];
-                h.e_begin = (int32_t)L->hedge.size();
-                for (int64_t i = adj_off[v]; i < adj_off[v + 1]; ++i) L->hedge.push_back(L->edge_maddr[adj[i]]);
-                h.e_end = (int32_t)L->hedge.size();
-                (deg <= kMidDegMax ? L->mids : L->highs).push_back((int32_t)L->hvar.size());
-                L->hvar.push_back(h);
+                continue;
             }
+            // the widest group that leaves each of its 256 threads at most
+            // about 16 edges, between 4 and 16 variables
+            int64_t w = 0;
+            if (deg > kMidDegMax) {
+                int64_t w0 = kColLanesMax;
+                while (w0 > kColLanesMin && w0 * deg > 256 * 16) w0 /= 2;
+                for (int64_t c = w0; c >= kColLanesMin && !w; c /= 2)
+                    if (column_ok(v, c, v1)) w = c;
+            }
+            HVar h{};
+            h.b_addr = vaddr[v];
+            h.n = (int16_t)L->vn[v];
+            h.lanes = (int16_t)std::max<int64_t>(w, 1);
+            h.e_begin = (int32_t)L->hedge.size();
+            if (w) {
+                int64_t rows = 0;
+                for (int64_t u = v; u < v + w; ++u) rows = std::max(rows, degree(u));
+                for (int64_t k = 0; k < rows; ++k)
+                    for (int64_t u = v; u < v + w; ++u) L->hedge.push_back(k < degree(u) ? edge_addr(u, k) : -1);
+                v += w - 1;
+            } else {
+                for (int64_t i = adj_off[v]; i < adj_off[v + 1]; ++i) L->hedge.push_back(L->edge_maddr[adj[i]]);
+            }
+            h.e_end = (int32_t)L->hedge.size();
+            (w ? L->cols : deg <= kMidDegMax ? L->mids : L->highs).push_back((int32_t)L->hvar.size());
+            L->hvar.push_back(h);
         }
         VTile &vt = L->vtile[t];
         vt.kmax = kmax;
@@ -771,16 +807,32 @@ int check_layout(const HostLayout &L, std::string *err) {
         }
     // variable phase, wavefront- and block-per-variable paths
     for (int32_t i : L.mids)
-        if (!in(i, (int64_t)L.hvar.size()) || L.hvar[i].e_end - L.hvar[i].e_begin > kMidDegMax)
+        if (!in(i, (int64_t)L.hvar.size()) || L.hvar[i].e_end - L.hvar[i].e_begin > kMidDegMax ||
+            L.hvar[i].lanes != 1)
             return oob("wavefront-per-variable entry");
     for (int32_t i : L.highs)
-        if (!in(i, (int64_t)L.hvar.size())) return oob("block-per-variable entry");
-    if (L.mids.size() + L.highs.size() != L.hvar.size()) return oob("variable path lists");
-    for (const HVar &h : L.hvar) {
+        if (!in(i, (int64_t)L.hvar.size()) || L.hvar[i].lanes != 1) return oob("block-per-variable entry");
+    std::vector<char> block_path(L.hvar.size(), 0);
+    for (int32_t i : L.cols) {
+        if (!in(i, (int64_t)L.hvar.size()) || L.hvar[i].lanes == 1) return oob("column group entry");
+        block_path[i] = 1;
+    }
+    if (L.mids.size() + L.highs.size() + L.cols.size() != L.hvar.size()) return oob("variable path lists");
+    for (size_t i = 0; i < L.hvar.size(); ++i) {
+        const HVar &h = L.hvar[i];
         if (h.e_begin < 0 || h.e_end < h.e_begin || h.e_end > (int64_t)L.hedge.size()) return oob("hedge range");
-        if (!rows_in(h.b_addr, h.n, VB)) return oob("belief-high B/theta");
+        // a column group: a power of two of variables in one panel row
+        // (b_addr .. b_addr + lanes - 1 share the row), on the block path,
+        // whole edge rows; -1 entries are skipped
+        const int32_t w = h.lanes;
+        const bool col = w != 1;
+        if (col && (w < kColLanesMin || w > kColLanesMax || (w & (w - 1)) || !block_path[i] ||
+                    (h.e_end - h.e_begin) % w != 0 || h.b_addr % kLanes + w > kLanes))
+            return oob("column group");
+        for (int32_t l = 0; l < w; ++l)
+            if (!rows_in(h.b_addr + l, h.n, VB)) return oob("belief-high B/theta");
         for (int32_t k = h.e_begin; k < h.e_end; ++k)
-            if (!rows_in(L.hedge[k], h.n, M)) return oob("belief-high message");
+            if (!(col && L.hedge[k] == -1) && !rows_in(L.hedge[k], h.n, M)) return oob("belief-high message");
     }
     // factor phase
     auto vb_rows = [&](const FTile &ft, int32_t rows, const int32_t *row_n) -> bool {

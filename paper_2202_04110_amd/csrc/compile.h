@@ -77,6 +77,7 @@ struct HostLayout {
     std::vector<HVar> hvar;
     std::vector<int32_t> hedge;
     std::vector<int32_t> mids, highs;  // indices into hvar: wavefront- / block-per-variable paths
+    std::vector<int32_t> cols;         // indices into hvar: column groups (block path)
     std::vector<GenClass> gcls;
     std::vector<uint8_t> grows;
     std::vector<int32_t> edge_maddr;

@@ -420,16 +420,82 @@ __device__ __forceinline__ void belief_high_var(const GV &G, int hv, int tid, fl
     }
 }
 
+// column group (HVar.lanes = w > 1): variables l = 0..w-1 at belief
+// addresses b_addr + l, edge rows [k][w].  Thread (kg, l), kg = tid / w,
+// sums variable l's edges kg, kg + KG, ... (KG = 256 / w) in order, so each
+// load instruction reads 64 / w runs of w adjacent messages.  The KG
+// partial sums of a (variable, state) are then added in a fixed order: an
+// xor tree over the 64 / w lanes of each wavefront that hold the variable,
+// then the four wavefront sums in order.
+constexpr int kColStates = 2;  // states per pass
+constexpr int kColRound = 16;  // edges per thread fetched together
+constexpr int kColRed = kColStates * kHighWaves * kColLanesMax;
+template <class GV>
+__device__ __forceinline__ void belief_col_group(const GV &G, const HVar &h, int tid, float *red) {
+    const int lsh = __builtin_ctz((unsigned)h.lanes), w = h.lanes;  // a power of two
+    const int l = tid & (w - 1), kg = tid >> lsh, KG = kHighThreads >> lsh;
+    const int kmax = (h.e_end - h.e_begin) >> lsh;
+    for (int s0 = 0; s0 < h.n; s0 += kColStates) {
+        const int ns = min(kColStates, h.n - s0);  // uniform
+        // thread tid < w * ns writes variable tid % w, state s0 + tid / w;
+        // its evidence term is loaded with the edge rows
+        const bool own = tid < w * ns;
+        const int ol = tid & (w - 1), os = s0 + (tid >> lsh);
+        const float th = own ? G.theta[h.b_addr + ol + os * kLanes] : 0.0f;
+        float part[kColStates];
+#pragma unroll
+        for (int j = 0; j < kColStates; ++j) part[j] = 0.0f;
+        for (int k0 = kg; k0 < kmax; k0 += kColRound * KG) {
+            int a[kColRound];
+#pragma unroll
+            for (int u = 0; u < kColRound; ++u) {
+                const int k = k0 + u * KG;
+                a[u] = k < kmax ? G.hedge[h.e_begin + (k << lsh) + l] : -1;
+            }
+            float x[kColRound][kColStates];
+#pragma unroll
+            for (int u = 0; u < kColRound; ++u)
+#pragma unroll
+                for (int j = 0; j < kColStates; ++j)
+                    x[u][j] = (a[u] >= 0 && j < ns) ? G.m[a[u] + (s0 + j) * kLanes] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < kColRound; ++u)
+#pragma unroll
+                for (int j = 0; j < kColStates; ++j)
+                    if (a[u] >= 0 && j < ns) part[j] += x[u][j];
+        }
+        const int wave = tid >> 6;
+#pragma unroll
+        for (int j = 0; j < kColStates; ++j) {
+            for (int msk = w; msk < kLanes; msk <<= 1) part[j] += __shfl_xor(part[j], msk);
+            if ((tid & 63) < w) red[(j * kHighWaves + wave) * kColLanesMax + l] = part[j];
+        }
+        __syncthreads();
+        if (own) {
+            const float *r = red + (os - s0) * kHighWaves * kColLanesMax + ol;
+            float v = r[0];
+#pragma unroll
+            for (int wv = 1; wv < kHighWaves; ++wv) v += r[wv * kColLanesMax];
+            G.B[h.b_addr + ol + os * kLanes] = th + v;
+        }
+        __syncthreads();
+    }
+}
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs, const WorkItem *__restrict__ items,
                                                 int n_low, int n_mid, int n_high, int swz) {
     __shared__ float red[8][kHighWaves];
+    __shared__ float cred[kColRed];
     // block-per-variable items first: they are the longest, so they start
     // before the wavefront items fill the machine
     if ((int)blockIdx.x < n_high) {
         const int hb = __builtin_amdgcn_readfirstlane((int)blockIdx.x);
         const WorkItem it = items[n_low + n_mid + hb];
-        belief_high_var(glob(gs[it.g]), it.t, threadIdx.x, red);
+        const auto G = glob(gs[it.g]);
+        const HVar h = G.hvar[it.t];
+        if (h.lanes > 1) belief_col_group(G, h, threadIdx.x, cred);
+        else belief_high_var(G, it.t, threadIdx.x, red);
         return;
     }
     const int nwave = n_low + n_mid;

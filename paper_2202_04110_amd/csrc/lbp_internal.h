@@ -50,10 +50,18 @@ struct VTile {
     int32_t e_off;    // base of the edge-address rows [k][64]
 };
 
-// A variable handled by the wavefront- or block-per-variable belief path.
+// A variable handled by the wavefront- or block-per-variable belief path,
+// or (block path, lanes > 1) a column group: `lanes` consecutive variables
+// of one belief panel (belief addresses b_addr + l) with equal state counts,
+// whose edge addresses form rows [k][lanes] in e_begin..e_end, -1 past a
+// variable's last edge.  The compiler forms a group where the variables'
+// k-th edges mostly sit side by side in the message panels (the hidden
+// units of a dense bipartite layer), so one load reads a run of them.
+constexpr int kColLanesMin = 4, kColLanesMax = 16;
 struct HVar {
     int32_t b_addr;   // belief address of state 0
-    int32_t n;
+    int16_t n;        // states
+    int16_t lanes;    // 1, or the column group's variables (4, 8 or 16)
     int32_t e_begin;  // range in the high-degree edge-address list
     int32_t e_end;
 };

@@ -41,7 +41,7 @@ bool valid_params(int32_t iters, float d, float T, std::string *why) {
 
 // ------------------------------------------------------------ launch lists
 void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<WorkItem> *mids,
-                  std::vector<WorkItem> *highs) {
+                  std::vector<WorkItem> *highs, std::vector<WorkItem> *cols) {
     for (const VGroup &vg : s.vgroups) {
         size_t i = 0;
         while (i < ll.vbucket.size() && ll.vbucket[i] != vg.bucket) ++i;
@@ -53,6 +53,7 @@ void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<
     }
     for (int32_t h : s.mids) mids->push_back(WorkItem{gi, h});
     for (int32_t h : s.highs) highs->push_back(WorkItem{gi, h});
+    for (int32_t h : s.cols) cols->push_back(WorkItem{gi, h});
     for (const FGroup &fg : s.fgroups) {
         size_t i = 0;
         while (i < ll.fshape.size() &&
@@ -113,17 +114,26 @@ void merge_lists(LaunchLists &ll) {
 }
 }  // namespace
 
-void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs, bool merge) {
+void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs,
+                  std::vector<WorkItem> &cols, bool merge) {
     if (merge) merge_lists(ll);
-    if (mids.empty() && highs.empty()) return;
+    if (mids.empty() && highs.empty() && cols.empty()) return;
     if (ll.vbucket.empty()) {
         ll.vbucket.push_back(2);
         ll.vitems.emplace_back();
     }
     ll.n_mid = (int32_t)mids.size();
-    ll.n_high = (int32_t)highs.size();
-    ll.vitems[0].insert(ll.vitems[0].end(), mids.begin(), mids.end());
-    ll.vitems[0].insert(ll.vitems[0].end(), highs.begin(), highs.end());
+    ll.n_high = (int32_t)(cols.size() + highs.size());
+    std::vector<WorkItem> &v = ll.vitems[0];
+    v.insert(v.end(), mids.begin(), mids.end());
+    // Block b of the variable launch takes block-path item b and runs on XCD
+    // b mod 8 (workgroups go to the XCDs in turn).  Column group position p
+    // holds group (p mod 8) * q + p / 8 (q = n / 8; the last n mod 8 keep
+    // their place), so each XCD runs a run of consecutive groups: the groups
+    // that read one cache line of edge rows then share that XCD's L2.
+    const int64_t n = (int64_t)cols.size(), q = n / 8;
+    for (int64_t p = 0; p < n; ++p) v.push_back(cols[p < 8 * q ? (p % 8) * q + p / 8 : p]);
+    v.insert(v.end(), highs.begin(), highs.end());
 }
 
 size_t lists_bytes(const LaunchLists &ll) {
@@ -320,10 +330,10 @@ struct GraphPieces {
         vn = add(L.vn.data(), sizeof(int32_t) * L.vn.size());
         fp = add(L.fac_phi.data(), sizeof(int32_t) * L.fac_phi.size());
         lp = add(L.lp_off.data(), sizeof(int64_t) * L.lp_off.size());
-        GraphShape s{L.fgroups, L.vgroups, L.mids, L.highs};
-        std::vector<WorkItem> mids, highs;
-        add_to_lists(ll, 0, s, &mids, &highs);
-        finish_lists(ll, mids, highs);
+        GraphShape s{L.fgroups, L.vgroups, L.mids, L.highs, L.cols};
+        std::vector<WorkItem> mids, highs, cols;
+        add_to_lists(ll, 0, s, &mids, &highs, &cols);
+        finish_lists(ll, mids, highs, cols);
         items = add(nullptr, lists_bytes(ll));  // packed by pack_lists
         dg = add(nullptr, sizeof(DevGraph));    // written into the image by graph_create
         data_end = total;  // everything above is copied from the host image, everything below starts zero
@@ -466,7 +476,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
             delete g;
             return hip_error(e, "graph upload");
         }
-        g->shape = GraphShape{L.fgroups, L.vgroups, L.mids, L.highs};
+        g->shape = GraphShape{L.fgroups, L.vgroups, L.mids, L.highs, L.cols};
         for (const FGroup &fg : L.fgroups)
             if (fg.kind == TK_LOGL || fg.kind == TK_LOGW) g->has_logical = true;
         g->V = L.V; g->VS = L.VS; g->F = L.F; g->E = L.E; g->ES = L.ES; g->Tn = L.Tn;

@@ -44,21 +44,24 @@ struct Launch {
 // in each work item), before upload.
 struct LaunchLists {
     std::vector<int32_t> vbucket;                 // variable launches: state bucket
-    std::vector<std::vector<WorkItem>> vitems;    // tiles, then (first launch only) mids, highs
-    int32_t n_mid = 0, n_high = 0;
+    std::vector<std::vector<WorkItem>> vitems;    // tiles, then (first launch only) mids, column groups, highs
+    int32_t n_mid = 0, n_high = 0;                // n_high counts column groups and single block-path variables
     std::vector<FGroup> fshape;                   // factor launches: kind, a, b
     std::vector<std::vector<WorkItem>> fitems;
 };
 
 struct GraphShape;  // below
 void add_to_lists(LaunchLists &ll, int32_t gi, const GraphShape &s, std::vector<WorkItem> *mids,
-                  std::vector<WorkItem> *highs);
+                  std::vector<WorkItem> *highs, std::vector<WorkItem> *cols);
 // merge (lists of several graphs): square pairwise launches of 2..8 states
 // become one mixed launch (a = b = 0; each wavefront takes its tile's own
 // state count), and variable launches of buckets up to 8 become one launch
 // of the largest bucket, so graphs of different state counts share launches.
-// The arithmetic of each element is unchanged.
-void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs, bool merge = false);
+// The arithmetic of each element is unchanged.  Block-path items: column
+// groups first (the longest), ordered so that consecutive groups of a graph,
+// whose edge rows share cache lines, run on one XCD; then single variables.
+void finish_lists(LaunchLists &ll, std::vector<WorkItem> &mids, std::vector<WorkItem> &highs,
+                  std::vector<WorkItem> &cols, bool merge = false);
 // Device bytes of the lists' work items (one 256-aligned piece per launch).
 size_t lists_bytes(const LaunchLists &ll);
 // Launch descriptors of lists whose items sit at device address `mem`.
@@ -92,7 +95,7 @@ void destroy_loops(std::vector<CachedLoop> &v);
 struct GraphShape {
     std::vector<FGroup> fgroups;
     std::vector<VGroup> vgroups;
-    std::vector<int32_t> mids, highs;
+    std::vector<int32_t> mids, highs, cols;
 };
 
 }  // namespace lbp

@@ -601,13 +601,13 @@ private:
             p->hgs.push_back(r->g->host);
         }
         size_t total = 0;
-        std::vector<std::vector<WorkItem>> mids(parts_.size()), highs(parts_.size());
+        std::vector<std::vector<WorkItem>> mids(parts_.size()), highs(parts_.size()), cols(parts_.size());
         for (size_t i = 0; i < parts_.size(); ++i) {
             int32_t gi = 0;
             for (Request *r : active)
                 if (r->d == parts_[i].d && r->T == parts_[i].T)
-                    add_to_lists(parts_[i].ll, gi++, r->g->shape, &mids[i], &highs[i]);
-            finish_lists(parts_[i].ll, mids[i], highs[i], true);
+                    add_to_lists(parts_[i].ll, gi++, r->g->shape, &mids[i], &highs[i], &cols[i]);
+            finish_lists(parts_[i].ll, mids[i], highs[i], cols[i], true);
             total += align256(sizeof(DevGraph) * parts_[i].hgs.size()) + lists_bytes(parts_[i].ll);
         }
         if (total > stage_bytes_) {

@@ -4,6 +4,7 @@
 // with the matching message.  Built and run by tests/test_layout_check.py.
 #include <cstdio>
 #include <functional>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -119,6 +120,77 @@ int main() {
           }},
          {"three-way table", [](HostLayout &L) { L.grows[L.gcls[0].rows_off] = 200; }},
          {"read-out", [](HostLayout &L) { L.vn[0] = 9; }}});
+
+    // a dense bipartite layer, 70 visible x 80 hidden binary units (every
+    // unit on the block path): the hidden units' k-th edges sit side by side,
+    // so they form column groups of 16, 8 and 4 units; the visible units'
+    // edges run along their own rows and stay single
+    Builder rb;
+    const int nvis = 70, nhid = 80;
+    for (int i = 0; i < nvis + nhid; ++i) rb.var(2);
+    const int tr = rb.table(2);
+    for (int i = 0; i < nvis; ++i)
+        for (int j = 0; j < nhid; ++j) rb.enumf({i, nvis + j}, tr);
+    {
+        HostLayout L;
+        std::string err;
+        expect(compile_desc(rb.desc(), &L, &err) == LBP_OK, "bipartite: compile: " + err);
+        std::vector<int> widths;
+        int singles = 0;
+        for (const HVar &h : L.hvar) {
+            if (h.lanes > 1) widths.push_back(h.lanes);
+            else ++singles;
+        }
+        // Hidden unit 70 + j's k-th edge is factor 80 k + j.  Where
+        // (16 k + j) mod 64 = 63 the next unit's edge starts a new tile, which
+        // splits a quarter of the rows of the pairs j = 15/16, 31/32, 47/48
+        // and 63/64 (units 85/86, 101/102, 117/118, 133/134): no group spans
+        // them.  Var tiles [64, 128) and [128, 192) give groups at 70, 86,
+        // 102 (16 each), 118 (8), 128 (4) and 134 (16); units 126, 127, 132
+        // and 133 stay single, as do the 70 visible units.
+        const std::vector<int> want{16, 16, 16, 8, 4, 16};
+        expect(widths == want, "bipartite: column group widths");
+        expect(singles == nvis + 4, "bipartite: single block-path units");
+    }
+    run("bipartite", rb,
+        {{"column group", [](HostLayout &L) {
+              for (HVar &h : L.hvar)
+                  if (h.lanes > 1) {
+                      h.lanes = 3;
+                      break;
+                  }
+          }},
+         {"column group", [](HostLayout &L) {
+              for (HVar &h : L.hvar)
+                  if (h.lanes > 1) {
+                      h.b_addr += kLanes - h.lanes + 1;  // the group would leave its panel row
+                      break;
+                  }
+          }},
+         {"column group", [](HostLayout &L) {
+              for (HVar &h : L.hvar)
+                  if (h.lanes > 1) {
+                      h.e_end -= 1;  // a partial edge row
+                      break;
+                  }
+          }},
+         {"belief-high message", [](HostLayout &L) {
+              for (HVar &h : L.hvar)
+                  if (h.lanes == 1) {
+                      L.hedge[h.e_begin] = -1;  // skipped only inside column groups
+                      break;
+                  }
+          }},
+         {"belief-high message", [](HostLayout &L) {
+              for (HVar &h : L.hvar)
+                  if (h.lanes > 1) {
+                      L.hedge[h.e_end - 1] = (int32_t)L.M;
+                      break;
+                  }
+          }},
+         {"block-per-variable entry", [](HostLayout &L) { std::swap(L.cols[0], L.highs[0]); }},
+         {"column group entry", [](HostLayout &L) { L.cols.push_back(L.highs.back()); }},
+         {"variable path lists", [](HostLayout &L) { L.cols.pop_back(); }}});
 
     if (failures) {
         std::printf("%d failures\n", failures);

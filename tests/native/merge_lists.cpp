@@ -42,7 +42,7 @@ GraphShape shape_of(Builder &b, HostLayout &L) {
     std::string err;
     const int rc = compile_desc(b.desc(), &L, &err);
     expect(rc == LBP_OK, "compile: " + err);
-    return GraphShape{L.fgroups, L.vgroups, L.mids, L.highs};
+    return GraphShape{L.fgroups, L.vgroups, L.mids, L.highs, L.cols};
 }
 
 using Item = std::tuple<int32_t, int32_t, int32_t>;  // (kind tag, graph, tile)
@@ -61,9 +61,9 @@ std::vector<Item> items_of(const LaunchLists &ll) {
 
 LaunchLists lists(const std::vector<GraphShape> &shapes, bool merge) {
     LaunchLists ll;
-    std::vector<WorkItem> mids, highs;
-    for (size_t g = 0; g < shapes.size(); ++g) add_to_lists(ll, (int32_t)g, shapes[g], &mids, &highs);
-    finish_lists(ll, mids, highs, merge);
+    std::vector<WorkItem> mids, highs, cols;
+    for (size_t g = 0; g < shapes.size(); ++g) add_to_lists(ll, (int32_t)g, shapes[g], &mids, &highs, &cols);
+    finish_lists(ll, mids, highs, cols, merge);
     return ll;
 }
 
@@ -132,6 +132,46 @@ int main() {
     expect(mb.vbucket.size() == 2, "buckets above 8 are not merged");
     expect(count_pair(mb, 2, 2) == 1, "a 9-state class does not join the mixed launch");
     expect(items_of(mb) == items_of(lists(big, false)), "work items kept with a large class");
+
+    // two dense bipartite layers (70 x 80 and 70 x 100 binary units): their
+    // hidden units form column groups.  The block-path items of the variable
+    // launch are the groups of both graphs, then the single variables; group
+    // position p holds group (p mod 8) * q + p / 8 of the graphs' groups in
+    // order (q = n / 8; the last n mod 8 in place), so block p, on XCD p mod 8,
+    // belongs to a run of consecutive groups.
+    Builder b1, b2;
+    auto layer = [](Builder &b, int nv, int nh) {
+        for (int i = 0; i < nv + nh; ++i) b.var(2);
+        const int t = b.table(2);
+        for (int i = 0; i < nv; ++i)
+            for (int j = 0; j < nh; ++j) b.enumf({i, nv + j}, t);
+    };
+    layer(b1, 70, 80);
+    layer(b2, 70, 100);
+    HostLayout Lb1, Lb2;
+    std::vector<GraphShape> bip{shape_of(b1, Lb1), shape_of(b2, Lb2)};
+    const LaunchLists lb = lists(bip, true);
+    std::vector<WorkItem> groups;
+    for (int32_t g = 0; g < 2; ++g)
+        for (int32_t c : bip[g].cols) groups.push_back(WorkItem{g, c});
+    const int64_t n = (int64_t)groups.size(), q = n / 8;
+    expect(n >= 10 && !bip[0].cols.empty() && !bip[1].cols.empty(), "bipartite layers form column groups");
+    expect(lb.n_high == (int32_t)(n + bip[0].highs.size() + bip[1].highs.size()), "block items: groups and singles");
+    const std::vector<WorkItem> &v = lb.vitems[0];
+    const size_t first = v.size() - (size_t)lb.n_high;
+    bool order_ok = true;
+    for (int64_t p = 0; p < n; ++p) {
+        const WorkItem &want = groups[p < 8 * q ? (p % 8) * q + p / 8 : p];
+        order_ok = order_ok && v[first + p].g == want.g && v[first + p].t == want.t;
+    }
+    size_t k = first + (size_t)n;
+    for (int32_t g = 0; g < 2; ++g)
+        for (int32_t h : bip[g].highs) {
+            order_ok = order_ok && v[k].g == g && v[k].t == h;
+            ++k;
+        }
+    expect(order_ok && k == v.size(), "column groups (swizzled), then single block-path variables");
+    expect(items_of(lb) == items_of(lists(bip, false)), "work items kept with column groups");
 
     if (failures) {
         std::printf("%d failures\n", failures);

@@ -472,8 +472,11 @@ def test_warm_start_and_determinism(lbp, ctx):
 
 
 def test_batch_matches_alone_bitwise(lbp, ctx):
+    # the two larger RBMs put their hidden units in column groups (16 units
+    # of more than 64 edges each), which the batch orders across graphs
     specs = [W.potts_grid(17, 3, 31), W.potts_grid(40, 5, 32), W.ising_grid(9, 33), mixed_graph(34),
-             big_logical(35), W.rbm(30, 20, 36), W.potts_grid(23, 5, 37)]
+             big_logical(35), W.rbm(30, 20, 36), W.potts_grid(23, 5, 37), W.rbm(100, 90, 38),
+             W.rbm(70, 130, 39)]
     for T in (0.0, 1.0):
         alone = []
         for s in specs:

@@ -95,8 +95,8 @@ def test_served_full_size_requests_equal_lone_runs(lbp, ctx):
 def test_mixed_parameters_and_kinds(lbp, ctx):
     """Requests with different temperatures and factor kinds in one server."""
     specs = [W.potts_grid(20, 3, 1), W.ising_grid(16, 2), W.deconv(seed=4, K=2, tw=4, sd=10, img=12),
-             W.rbm(30, 20, 3), W.potts_grid(33, 5, 4)]
-    params = [(30, 0.5, 1.0), (30, 0.5, 0.0), (40, 0.5, 0.0), (25, 0.3, 0.05), (30, 0.5, 1.0)]
+             W.rbm(30, 20, 3), W.potts_grid(33, 5, 4), W.rbm(100, 90, 7)]
+    params = [(30, 0.5, 1.0), (30, 0.5, 0.0), (40, 0.5, 0.0), (25, 0.3, 0.05), (30, 0.5, 1.0), (20, 0.5, 0.0)]
     srv = lbp.Server(ctx, budget_bytes=256 << 20, max_slots=4, steps_per_round=7)
     for i, (s, (it, d, T)) in enumerate(zip(specs, params)):
         srv.submit(s, it, d, T, req_id=i)
