@@ -357,6 +357,27 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
         }
         if (std::get<0>(class_key[c]) != TK_PAIR) continue;
+        // pairwise factors that all join two block-path variables (a dense
+        // bipartite layer): ordered by the 16-variable block of the second
+        // variable, then the first, so a tile holds 4 x 16 factors and a run
+        // of tiles (the share of one XCD in the factor launch) covers a range
+        // of second variables, the range the column groups of those
+        // variables read from on the same XCD in the variable launch
+        {
+            auto var0 = [&](int32_t f) { return (int64_t)d->edge_var[d->factor_edge_off[f]]; };
+            auto var1 = [&](int32_t f) { return (int64_t)d->edge_var[d->factor_edge_off[f] + 1]; };
+            bool layer = !fl.empty();
+            for (size_t i = 0; i < fl.size() && layer; ++i)
+                layer = adj_off[var0(fl[i]) + 1] - adj_off[var0(fl[i])] > kMidDegMax &&
+                        adj_off[var1(fl[i]) + 1] - adj_off[var1(fl[i])] > kMidDegMax;
+            if (layer) {
+                std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) {
+                    const int64_t bx = var1(x) / 16, by = var1(y) / 16;
+                    return bx != by ? bx < by : var0(x) < var0(y);
+                });
+                continue;
+            }
+        }
         // pairwise: inside a block whose factors join their two variables at
         // no more than four distinct offsets (a grid: horizontal and vertical
         // neighbours), factors with the same offset together, each group in
@@ -595,22 +616,40 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
     std::map<int32_t, size_t> vgroup_of;
     auto degree = [&](int64_t v) { return adj_off[v + 1] - adj_off[v]; };
     auto edge_addr = [&](int64_t v, int64_t k) { return L->edge_maddr[adj[adj_off[v] + k]]; };
-    // Column group of w variables from v (inside [v, vend) of one var tile):
-    // all on the block path with v's state count, and for each neighbouring
-    // pair, variable u + 1's k-th edge is the message right after variable
-    // u's in at least 3/4 of their edge rows.
-    auto column_ok = [&](int64_t v, int64_t w, int64_t vend) {
+    // Column group of w variables from v (inside [v, vend) of one var tile),
+    // all on the block path with v's state count.  Its edge rows pair up
+    // messages that sit side by side: variable v + l's edge at message
+    // address a goes to the row keyed a - l, rows in increasing key order,
+    // -1 where a variable has no edge of that key.  A lane's edges then come
+    // in increasing address order.  Taken when edges fill at least 3/4 of the
+    // rows' entries.
+    std::vector<std::pair<int64_t, int32_t>> keyed;  // (key, lane)
+    auto column_rows = [&](int64_t v, int64_t w, int64_t vend, std::vector<int32_t> *rows) {
         if (v + w > vend) return false;
-        for (int64_t u = v; u < v + w; ++u)
+        int64_t edges = 0;
+        for (int64_t u = v; u < v + w; ++u) {
             if (degree(u) <= kMidDegMax || L->vn[u] != L->vn[v]) return false;
-        for (int64_t u = v; u + 1 < v + w; ++u) {
-            const int64_t both = std::min(degree(u), degree(u + 1));
-            int64_t side = 0;
-            for (int64_t k = 0; k < both; ++k) side += edge_addr(u + 1, k) == edge_addr(u, k) + 1;
-            if (4 * side < 3 * std::max(degree(u), degree(u + 1))) return false;
+            edges += degree(u);
+        }
+        keyed.clear();
+        for (int64_t u = v; u < v + w; ++u)
+            for (int64_t k = 0; k < degree(u); ++k)
+                keyed.emplace_back((int64_t)edge_addr(u, k) - (u - v), (int32_t)(u - v));
+        std::sort(keyed.begin(), keyed.end());
+        int64_t nrows = 0;
+        for (size_t i = 0; i < keyed.size(); ++i) nrows += i == 0 || keyed[i].first != keyed[i - 1].first;
+        if (4 * edges < 3 * nrows * w) return false;
+        if (rows) {
+            rows->assign((size_t)(nrows * w), -1);
+            int64_t r = -1;
+            for (size_t i = 0; i < keyed.size(); ++i) {
+                if (i == 0 || keyed[i].first != keyed[i - 1].first) ++r;
+                (*rows)[(size_t)(r * w + keyed[i].second)] = (int32_t)(keyed[i].first + keyed[i].second);
+            }
         }
         return true;
     };
+    std::vector<int32_t> col_rows;
     for (int64_t t = 0; t < nvt; ++t) {
         int32_t kmax = 0, nlow = 0;
         const int64_t v0 = t * kLanes, v1 = std::min<int64_t>(V, v0 + kLanes);
@@ -630,7 +669,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
                 int64_t w0 = kColLanesMax;
                 while (w0 > kColLanesMin && w0 * deg > 256 * 16) w0 /= 2;
                 for (int64_t c = w0; c >= kColLanesMin && !w; c /= 2)
-                    if (column_ok(v, c, v1)) w = c;
+                    if (column_rows(v, c, v1, &col_rows)) w = c;
             }
             HVar h{};
             h.b_addr = vaddr[v];
@@ -638,10 +677,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             h.lanes = (int16_t)std::max<int64_t>(w, 1);
             h.e_begin = (int32_t)L->hedge.size();
             if (w) {
-                int64_t rows = 0;
-                for (int64_t u = v; u < v + w; ++u) rows = std::max(rows, degree(u));
-                for (int64_t k = 0; k < rows; ++k)
-                    for (int64_t u = v; u < v + w; ++u) L->hedge.push_back(k < degree(u) ? edge_addr(u, k) : -1);
+                L->hedge.insert(L->hedge.end(), col_rows.begin(), col_rows.end());
                 v += w - 1;
             } else {
                 for (int64_t i = adj_off[v]; i < adj_off[v + 1]; ++i) L->hedge.push_back(L->edge_maddr[adj[i]]);

@@ -141,14 +141,15 @@ int main() {
             if (h.lanes > 1) widths.push_back(h.lanes);
             else ++singles;
         }
-        // Hidden unit 70 + j's k-th edge is factor 80 k + j.  Where
-        // (16 k + j) mod 64 = 63 the next unit's edge starts a new tile, which
-        // splits a quarter of the rows of the pairs j = 15/16, 31/32, 47/48
-        // and 63/64 (units 85/86, 101/102, 117/118, 133/134): no group spans
-        // them.  Var tiles [64, 128) and [128, 192) give groups at 70, 86,
-        // 102 (16 each), 118 (8), 128 (4) and 134 (16); units 126, 127, 132
-        // and 133 stay single, as do the 70 visible units.
-        const std::vector<int> want{16, 16, 16, 8, 4, 16};
+        // Every factor joins two block-path units, so the layer is ordered by
+        // the 16-unit block of the hidden unit, then the visible unit: a tile
+        // holds 4 visible x 16 hidden units, and hidden unit u's edge sits in
+        // the lane after unit u - 1's wherever both fall in one block (units
+        // 64..79, 80..95, ...).  A group never spans a block boundary (its
+        // rows would be half empty) or a var tile ([64, 128), [128, 192)):
+        // groups at 70 (8), 80, 96, 112, 128 (16 each) and 144 (4); units
+        // 78, 79, 148 and 149 stay single, as do the 70 visible units.
+        const std::vector<int> want{8, 16, 16, 16, 16, 4};
         expect(widths == want, "bipartite: column group widths");
         expect(singles == nvis + 4, "bipartite: single block-path units");
     }
