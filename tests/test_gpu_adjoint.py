@@ -58,10 +58,23 @@ def small_graphs():
         ("potts9x3", W.potts_grid(9, 3, seed=6)),
         ("rect", W.disjoint_union([W.potts_grid(6, 2, 1), W.potts_grid(5, 7, 2)])),
         ("triplet7x3", W.triplet_grid(7, 3, 9)),
+        ("layer70x80", layer(10, 70, 80)),
     ]
 
 
-@pytest.mark.parametrize("idx", range(6))
+def layer(seed, nv, nh, drop=0.03):
+    """A bipartite layer of binary units with about 3% of its factors missing:
+    every unit has more than 64 edges, so the hidden units sum their messages
+    in column groups in the recorded forward sweep."""
+    rng = np.random.default_rng(seed)
+    i, j = np.nonzero(rng.random((nv, nh)) >= drop)
+    pairs = np.stack([i, nv + j], 1).astype(np.int64)
+    ev = rng.normal(0, 0.5, (nv + nh) * 2).astype(np.float32)
+    tab = rng.normal(0, 0.3, (pairs.shape[0], 4)).astype(np.float32)
+    return W._pairwise_graph(np.full(nv + nh, 2, np.int32), ev, pairs, tab, "layer%dx%d" % (nv, nh))
+
+
+@pytest.mark.parametrize("idx", range(7))
 @pytest.mark.parametrize("T,d", [(1.0, 0.5), (0.5, 0.3)])
 def test_adjoint_matches_oracle(lbp, ctx, idx, T, d):
     name, spec = small_graphs()[idx]

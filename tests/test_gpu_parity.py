@@ -207,6 +207,22 @@ def states64(seed):
     return W._general_graph(ns, ev, facs, "states64")
 
 
+def ragged_layer(seed, nv, nh, n, drop=0.03):
+    """A bipartite layer of n-state units, visible 0..nv-1 and hidden nv.., each
+    visible-hidden factor present with probability 1 - drop (ragged degrees),
+    dense n x n tables and evidence ~ N(0, 1).  With more than 64 edges per
+    unit, the hidden units form column groups whose edge rows have gaps where
+    a factor is missing, and n > 2 takes several state passes per group."""
+    rng = np.random.default_rng(seed)
+    keep = rng.random((nv, nh)) >= drop
+    i, j = np.nonzero(keep)
+    pairs = np.stack([i, nv + j], 1).astype(np.int64)
+    V = nv + nh
+    ev = rng.normal(0, 1, V * n).astype(np.float32)
+    tab = rng.normal(0, 1, (pairs.shape[0], n * n)).astype(np.float32)
+    return W._pairwise_graph(np.full(V, n, np.int32), ev, pairs, tab, "layer%dx%dx%d" % (nv, nh, n))
+
+
 def wide_states(seed, n=16, L=6):
     g = W.potts_grid(L, n, seed=seed)
     g.name = "potts%dx%d" % (L, n)
@@ -238,6 +254,9 @@ STEP_CASES = [
     ("rect3x5", lambda: rect_pairs(8, 3, 5), [0.0, 1.0]),
     ("potts6x16", lambda: wide_states(9, 16, 6), [0.0, 1.0]),
     ("potts4x30", lambda: wide_states(10, 30, 4), [1.0]),
+    ("layer90x100x3", lambda: ragged_layer(13, 90, 100, 3), [0.0, 1.0]),
+    ("layer80x96x5", lambda: ragged_layer(14, 80, 96, 5), [0.5]),
+    ("layer90x100x3_sparse", lambda: ragged_layer(15, 90, 100, 3, drop=0.1), [0.0]),
 ]
 
 
