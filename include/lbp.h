@@ -409,11 +409,13 @@ void lbp_server_destroy(lbp_server *s);
  * so that each of the 8 XCDs takes a contiguous range of tiles.  Shapes never
  * change any element's arithmetic, so results are identical whatever the
  * shape.  lbp_autotune times every candidate shape of every group with HIP
- * events (reps launches each, messages saved and restored) and keeps the
- * fastest; best_ms_out (may be NULL) receives the chosen launch time per
- * group.  lbp_graph_get_launch returns {phase (0 variable, 1 factor), kind,
- * a, b, waves per block, swizzle, work items, fused waves per block, fused
- * variant} for group i.
+ * events inside whole two-phase iterations (reps iterations each, the other
+ * groups at their current shapes, two passes over the groups; messages saved
+ * and restored), so what one phase leaves in the caches for the next counts,
+ * and keeps the fastest; best_ms_out (may be NULL) receives, per group, the
+ * iteration time with its chosen shape.  lbp_graph_get_launch returns
+ * {phase (0 variable, 1 factor), kind, a, b, waves per block, swizzle, work
+ * items, fused waves per block, fused variant} for group i.
  */
 int lbp_graph_num_launches(const lbp_graph *g, int32_t *n_out);
 int lbp_graph_get_launch(const lbp_graph *g, int32_t i, int32_t out[9]);

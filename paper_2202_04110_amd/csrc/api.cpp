@@ -454,16 +454,14 @@ std::vector<Launch *> all_launches(std::vector<Launch> &vl, std::vector<Launch> 
     return v;
 }
 
-// Times `reps` launches of one launch group (after one warm-up launch).
-hipError_t time_one(const DevGraph *gs, const Launch &L, bool variable, const TParams &P, bool maxp, hipStream_t st,
-                    int reps, hipEvent_t a, hipEvent_t b, float *ms) {
-    std::vector<Launch> one{L}, none;
-    const std::vector<Launch> &vl = variable ? one : none;
-    const std::vector<Launch> &fl = variable ? none : one;
-    const int ph = variable ? 1 : 2;
-    hipError_t e = launch_iteration(gs, vl, fl, P, maxp, st, ph);
+// Times `reps` whole two-phase iterations with the groups' current shapes
+// (after one warm-up iteration).
+hipError_t time_iterations(const DevGraph *gs, const std::vector<Launch> &vl, const std::vector<Launch> &fl,
+                           const TParams &P, bool maxp, hipStream_t st, int reps, hipEvent_t a, hipEvent_t b,
+                           float *ms) {
+    hipError_t e = launch_iteration(gs, vl, fl, P, maxp, st, 3);
     if (e == hipSuccess) e = hipEventRecord(a, st);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_iteration(gs, vl, fl, P, maxp, st, ph);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_iteration(gs, vl, fl, P, maxp, st, 3);
     if (e == hipSuccess) e = hipEventRecord(b, st);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
@@ -471,9 +469,15 @@ hipError_t time_one(const DevGraph *gs, const Launch &L, bool variable, const TP
     return e;
 }
 
-// Picks, per launch group, the fastest shape: variable phase {swizzle off, on};
-// lane-per-item factor kernels {1, 2, 4 wavefronts per block} x {swizzle off,
-// on}; generic enumeration launches keep their fixed shape.
+// Picks, per launch group, the shape that makes whole two-phase iterations
+// fastest, the other groups at their current shapes, in two passes over the
+// groups: variable phase {swizzle off, on}; lane-per-item factor kernels
+// {1, 2, 4 wavefronts per block} x {swizzle off, on}; generic enumeration
+// launches keep their fixed shape.  Timing whole iterations rather than one
+// launch at a time sees what one phase leaves in the XCDs' L2 for the next:
+// a bipartite layer's factor tiles swizzled into per-XCD runs are read by
+// the column groups of the same XCD (RBM 784x500: 9.1 against 10.6 us per
+// iteration unswizzled), which a launch timed alone cannot show.
 int tune_launches(const DevGraph *gs, std::vector<Launch> &vl, std::vector<Launch> &fl, float d, float T, int reps,
                   hipStream_t st, float *best_ms) {
     const TParams P = make_params(d, T);
@@ -485,34 +489,36 @@ int tune_launches(const DevGraph *gs, std::vector<Launch> &vl, std::vector<Launc
         (void)hipEventDestroy(a);
         return hip_error(e, "hipEventCreate");
     }
-    int idx = 0;
-    for (Launch *L : all_launches(vl, fl)) {
-        const bool variable = L->kind == -1;
-        std::vector<LaunchShape> cand;
-        if (variable) {
-            cand = {LaunchShape{4, 0}, LaunchShape{4, 1}};
-        } else if (L->kind == TK_GEN) {
-            cand = {L->shape};
-        } else {
-            for (int w : {1, 2, 4})
-                for (int z : {0, 1}) cand.push_back(LaunchShape{w, z});
-        }
-        LaunchShape best = L->shape;
-        float best_t = 1e30f;
-        for (const LaunchShape &c : cand) {
-            L->shape = c;
-            float ms = 0.0f;
-            e = time_one(gs, *L, variable, P, maxp, st, reps, a, b, &ms);
-            if (e != hipSuccess) break;
-            if (ms < best_t) {
-                best_t = ms;
-                best = c;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+        int idx = 0;
+        for (Launch *L : all_launches(vl, fl)) {
+            const bool variable = L->kind == -1;
+            std::vector<LaunchShape> cand;
+            if (variable) {
+                cand = {LaunchShape{4, 0}, LaunchShape{4, 1}};
+            } else if (L->kind == TK_GEN) {
+                cand = {L->shape};
+            } else {
+                for (int w : {1, 2, 4})
+                    for (int z : {0, 1}) cand.push_back(LaunchShape{w, z});
             }
+            LaunchShape best = L->shape;
+            float best_t = 1e30f;
+            for (const LaunchShape &c : cand) {
+                L->shape = c;
+                float ms = 0.0f;
+                e = time_iterations(gs, vl, fl, P, maxp, st, reps, a, b, &ms);
+                if (e != hipSuccess) break;
+                if (ms < best_t) {
+                    best_t = ms;
+                    best = c;
+                }
+            }
+            L->shape = best;
+            if (best_ms) best_ms[idx] = best_t;
+            ++idx;
+            if (e != hipSuccess) break;
         }
-        L->shape = best;
-        if (best_ms) best_ms[idx] = best_t;
-        ++idx;
-        if (e != hipSuccess) break;
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
