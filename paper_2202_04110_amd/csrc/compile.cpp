@@ -371,10 +371,18 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
                 layer = adj_off[var0(fl[i]) + 1] - adj_off[var0(fl[i])] > kMidDegMax &&
                         adj_off[var1(fl[i]) + 1] - adj_off[var1(fl[i])] > kMidDegMax;
             if (layer) {
-                std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) {
-                    const int64_t bx = var1(x) / 16, by = var1(y) / 16;
-                    return bx != by ? bx < by : var0(x) < var0(y);
-                });
+                // two stable counting passes: by first variable, then by
+                // the second variable's block
+                auto pass = [&](auto bucket, int64_t nb) {
+                    std::vector<int64_t> at(nb + 1, 0);
+                    for (int32_t f : fl) ++at[bucket(f) + 1];
+                    for (int64_t b = 0; b < nb; ++b) at[b + 1] += at[b];
+                    sorted.resize(fl.size());
+                    for (int32_t f : fl) sorted[at[bucket(f)]++] = f;
+                    fl.swap(sorted);
+                };
+                pass(var0, V);
+                pass([&](int32_t f) { return var1(f) / 16; }, V / 16 + 1);
                 continue;
             }
         }
@@ -622,8 +630,24 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
     // address a goes to the row keyed a - l, rows in increasing key order,
     // -1 where a variable has no edge of that key.  A lane's edges then come
     // in increasing address order.  Taken when edges fill at least 3/4 of the
-    // rows' entries.
-    std::vector<std::pair<int64_t, int32_t>> keyed;  // (key, lane)
+    // rows' entries.  The rows are a w-way merge of the variables' addresses,
+    // sorted once per variable; the merge stops as soon as the rows can no
+    // longer be 3/4 full.
+    std::vector<int32_t> saddr;  // block-path variables' edge addresses, ascending, at adj_off[v]
+    std::vector<char> sorted_v;
+    auto sorted_addr = [&](int64_t u) {
+        if (saddr.empty()) {
+            saddr.assign(E, 0);
+            sorted_v.assign(V, 0);
+        }
+        if (!sorted_v[u]) {
+            for (int64_t k = 0; k < degree(u); ++k) saddr[adj_off[u] + k] = edge_addr(u, k);
+            if (!std::is_sorted(saddr.begin() + adj_off[u], saddr.begin() + adj_off[u + 1]))
+                std::sort(saddr.begin() + adj_off[u], saddr.begin() + adj_off[u + 1]);
+            sorted_v[u] = 1;
+        }
+        return saddr.data() + adj_off[u];
+    };
     auto column_rows = [&](int64_t v, int64_t w, int64_t vend, std::vector<int32_t> *rows) {
         if (v + w > vend) return false;
         int64_t edges = 0;
@@ -631,20 +655,37 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             if (degree(u) <= kMidDegMax || L->vn[u] != L->vn[v]) return false;
             edges += degree(u);
         }
-        keyed.clear();
-        for (int64_t u = v; u < v + w; ++u)
-            for (int64_t k = 0; k < degree(u); ++k)
-                keyed.emplace_back((int64_t)edge_addr(u, k) - (u - v), (int32_t)(u - v));
-        std::sort(keyed.begin(), keyed.end());
-        int64_t nrows = 0;
-        for (size_t i = 0; i < keyed.size(); ++i) nrows += i == 0 || keyed[i].first != keyed[i - 1].first;
-        if (4 * edges < 3 * nrows * w) return false;
-        if (rows) {
-            rows->assign((size_t)(nrows * w), -1);
-            int64_t r = -1;
-            for (size_t i = 0; i < keyed.size(); ++i) {
-                if (i == 0 || keyed[i].first != keyed[i - 1].first) ++r;
-                (*rows)[(size_t)(r * w + keyed[i].second)] = (int32_t)(keyed[i].first + keyed[i].second);
+        const int32_t *a[kColLanesMax];
+        int64_t pos[kColLanesMax], len[kColLanesMax];
+        for (int64_t l = 0; l < w; ++l) {
+            a[l] = sorted_addr(v + l);
+            pos[l] = 0;
+            len[l] = degree(v + l);
+        }
+        // the rows are at least the distinct keys of the first two lanes:
+        // a cheap test that rejects most variables that form no group
+        {
+            const int64_t cap = 4 * edges / (3 * w);  // the most rows a taken group has
+            int64_t i = 0, j = 0, keys = 0;
+            while ((i < len[0] || j < len[1]) && keys <= cap) {
+                const int64_t k0 = i < len[0] ? (int64_t)a[0][i] : INT64_MAX;
+                const int64_t k1 = j < len[1] ? (int64_t)a[1][j] - 1 : INT64_MAX;
+                i += k0 <= k1;
+                j += k1 <= k0;
+                ++keys;
+            }
+            if (keys > cap) return false;
+        }
+        rows->clear();
+        for (int64_t left = edges; left > 0;) {
+            if (4 * edges < 3 * (int64_t)(rows->size() + w)) return false;  // one more row: below 3/4 full
+            int64_t key = INT64_MAX;
+            for (int64_t l = 0; l < w; ++l)
+                if (pos[l] < len[l]) key = std::min<int64_t>(key, (int64_t)a[l][pos[l]] - l);
+            for (int64_t l = 0; l < w; ++l) {
+                const bool take = pos[l] < len[l] && (int64_t)a[l][pos[l]] - l == key;
+                rows->push_back(take ? a[l][pos[l]++] : -1);
+                left -= take;
             }
         }
         return true;
