@@ -397,6 +397,54 @@ def scaleup_leg(lbp, W, ctx, tune, reps=50, solves=3):
     return out
 
 
+def small_graphs_leg(lbp, W, ctx, tune, solves=5, reps=200):
+    """The paper's small workloads in the shipped launch shapes: the RBM
+    784x500 (200 max-product iterations) and the deconvolution graph (1000),
+    each timed as whole solves (message reset, iterations, beliefs and MAP
+    into device buffers) between device synchronisations, plus the RBM's
+    variable phase in place against its algorithmic bytes."""
+    import torch
+
+    out = {}
+    for name in ("rbm", "deconv"):
+        make, iters, d, T, desc = WORKLOADS[name]
+        spec = make(W)
+        g = lbp.Graph(ctx, spec)
+        tuned = tune.apply_or_tune(g, d, T)
+        bm = byte_model(spec, iters)
+        ES = spec.num_edge_states
+        q = torch.empty(g.VS, device="cuda", dtype=torch.float32)
+        mp = torch.empty(g.V, device="cuda", dtype=torch.int32)
+
+        def solve():
+            g.reset_messages()
+            g.run_bp(iters, d, T)
+            g.get_beliefs(out=q)
+            g.decode_map(out=mp)
+
+        solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(solves):
+            solve()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / solves
+        g.status()
+        r = {"workload": desc, "ms_per_solve": ms, "us_per_iteration": 1e3 * ms / iters,
+             "edge_state_updates_per_s": ES * iters / (ms * 1e-3), "tune_source": tuned["source"],
+             "launch_shapes": [[l["phase"], l["wpb"], l["swizzle"]] for l in g.launches()]}
+        if name == "rbm":
+            tv = g.time_phase(0, reps, d, T)
+            ach = bm["variable_bytes"] / (tv * 1e-3) / 1e9
+            r["variable_phase"] = {"avg_launch_ms": tv, "algorithmic_bytes_per_launch": bm["variable_bytes"],
+                                   "achieved_gbps": ach, "frac": ach / HBM_PEAK_GBS}
+        out[name] = r
+        g.free()
+        del spec
+    torch.cuda.empty_cache()
+    return out
+
+
 def paper_rbm_leg(lbp, W, ctx, runs=10):
     """The paper's timing protocol on MAP inference: fully connected binary
     RBMs of 40, 60, ..., 200 units (half visible, half hidden), max-product,
@@ -457,18 +505,20 @@ def main():
                     help="the paper's MAP timing protocol: RBMs of 40..200 units, 200 max-product iterations")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip timing a recorded solve plus its reverse sweep against the forward solve")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the RBM 784x500 and deconvolution per-iteration leg")
     ap.add_argument("--no-scaleup", action="store_true",
                     help="skip the Potts 2048x2048 roofline (the HBM-bound case)")
     ap.add_argument("--headline-only", action="store_true",
-                    help="only the timed workload and its roofline (no serving, batch, gradient, scale-up or "
-                         "CPU baseline legs), e.g. under a profiler")
+                    help="only the timed workload and its roofline (no serving, batch, gradient, scale-up, "
+                         "small-graph or CPU baseline legs), e.g. under a profiler")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 5 times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.headline_only:
         args.serving = args.batch = args.samples = 0
-        args.no_gradient = args.no_scaleup = args.no_cpu_baseline = True
+        args.no_gradient = args.no_scaleup = args.no_cpu_baseline = args.no_small = True
         args.paper_rbm = False
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -597,6 +647,11 @@ def main():
         print("potts2048: %.2f ms per solve, fused launch %.1f us, frac %.3f" % (
             sc["ms_per_solve"], 1e3 * out["roofline_beyond_cache"]["avg_launch_ms"],
             out["roofline_beyond_cache"]["frac"]), file=sys.stderr, flush=True)
+    if not args.no_small and args.workload not in ("rbm", "rbm_t005", "deconv"):
+        out["small_graphs"] = small_graphs_leg(lbp, W, ctx, tune)
+        print("small graphs: RBM %.2f us, deconvolution %.2f us per iteration" % (
+            out["small_graphs"]["rbm"]["us_per_iteration"], out["small_graphs"]["deconv"]["us_per_iteration"]),
+            file=sys.stderr, flush=True)
     if not args.no_gradient:
         out["gradient"] = gradient_leg(lbp, W, ctx)
     if args.samples:
