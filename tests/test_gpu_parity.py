@@ -257,6 +257,10 @@ STEP_CASES = [
     ("layer90x100x3", lambda: ragged_layer(13, 90, 100, 3), [0.0, 1.0]),
     ("layer80x96x5", lambda: ragged_layer(14, 80, 96, 5), [0.5]),
     ("layer90x100x3_sparse", lambda: ragged_layer(15, 90, 100, 3, drop=0.1), [0.0]),
+    # hidden units of about 1960 and 1180 edges: groups of 4 whose threads
+    # take two rounds of 16 edges each
+    ("layer2000x80", lambda: ragged_layer(16, 2000, 80, 2, drop=0.02), [0.0, 1.0]),
+    ("layer1200x70x3", lambda: ragged_layer(17, 1200, 70, 3, drop=0.02), [0.5]),
 ]
 
 
