@@ -394,6 +394,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             const int64_t e0 = d->factor_edge_off[f];
             return (int64_t)d->edge_var[e0 + 1] - d->edge_var[e0];
         };
+        std::vector<int32_t> part;
         for (size_t i = 0; i < fl.size();) {
             size_t j = i;
             while (j < fl.size() && key(fl[j]) == key(fl[i])) ++j;
@@ -409,9 +410,14 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
                     else seen[nseen++] = dk;
                 }
             }
-            if (few && nseen > 1)
-                std::stable_sort(fl.begin() + i, fl.begin() + j,
-                                 [&](int32_t x, int32_t y) { return delta(x) < delta(y); });
+            if (few && nseen > 1) {  // a stable partition by increasing offset
+                std::sort(seen, seen + nseen);
+                part.clear();
+                for (int s = 0; s < nseen; ++s)
+                    for (size_t k = i; k < j; ++k)
+                        if (delta(fl[k]) == seen[s]) part.push_back(fl[k]);
+                std::copy(part.begin(), part.end(), fl.begin() + (int64_t)i);
+            }
             i = j;
         }
     }
