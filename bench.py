@@ -65,15 +65,20 @@ def kernel_source_sha():
 def byte_model(spec, iters):
     """Algorithmic bytes (index arrays excluded).
 
-    factor phase per launch: read potentials 4*Tn, read messages 4*ES, read
-    beliefs 4*VS (each unique belief once), write messages 4*ES.
-    variable phase per launch: read messages 4*ES, evidence 4*VS, write beliefs 4*VS.
+    A message is one row per state, except a two-state message, which is one
+    number (its rows are normalised, so m1 - m0 determines both): MS stored
+    message floats, ES - (two-state edges).
+    factor phase per launch: read potentials 4*Tn, read messages 4*MS, read
+    beliefs 4*VS (each unique belief once), write messages 4*MS.
+    variable phase per launch: read messages 4*MS, evidence 4*VS, write beliefs 4*VS.
     """
     ES, VS, Tn = spec.num_edge_states, spec.num_var_states, spec.num_logpots
-    factor = 4 * Tn + 8 * ES + 4 * VS
-    var = 4 * ES + 8 * VS
+    two = int(np.count_nonzero(np.asarray(spec.var_num_states)[np.asarray(spec.edge_var)] == 2))
+    MS = ES - two
+    factor = 4 * Tn + 8 * MS + 4 * VS
+    var = 4 * MS + 8 * VS
     return {"factor_bytes": factor, "variable_bytes": var, "iter_bytes": factor + var,
-            "floor_bytes": 8 * ES + 4 * Tn + 4 * VS}
+            "floor_bytes": 8 * MS + 4 * Tn + 4 * VS, "message_floats": MS}
 
 
 def measured_traffic(workload, kernel, shape):

@@ -236,7 +236,12 @@ int lbp_decode_map(lbp_graph *g, int32_t *out, int out_on_device);
 int lbp_graph_status(lbp_graph *g);
 
 /* Message state in the flat edge-state order (ES floats), for checkpoints and
- * for starting several runs from one state. */
+ * for starting several runs from one state.  The library keeps every message
+ * row normalised (its largest state at 0; a row of two states is stored as
+ * the one number m1 - m0), so lbp_set_messages normalises the rows of
+ * two-state edges it is given: lbp_get_messages then returns them shifted to
+ * a largest state of 0.  A shift of a whole row changes no belief or later
+ * message (the update is invariant under it), only the rounding. */
 int lbp_get_messages(lbp_graph *g, float *out, int on_device);
 int lbp_set_messages(lbp_graph *g, const float *values, int on_device);
 

@@ -76,7 +76,7 @@ struct GGraph {
     gptr<const int32_t> vn, fac_phi;
     gptr<const int64_t> lp_off;
     gptr<int32_t> flag;
-    int32_t V, E, F, zero_addr;
+    int32_t V, E, F, zero_addr, raw_msgs;
 };
 template <class T>
 __device__ __forceinline__ gptr<T> as_global(T *p) {
@@ -111,6 +111,7 @@ __device__ __forceinline__ GGraph glob(const DevGraph &d) {
     g.E = d.E;
     g.F = d.F;
     g.zero_addr = d.zero_addr;
+    g.raw_msgs = d.raw_msgs;
     return g;
 }
 
@@ -216,6 +217,44 @@ __device__ __forceinline__ float lem_t(float a, const TParams &P) {
     return a + P.T * logf(-expm1f(-a * P.invT));
 }
 
+// Message rows of two states hold one value, d = m1 - m0, in their first
+// row (the second row of the slot is never read or written).  Every row is
+// stored normalised, its larger state exactly zero (x - x = +0), so the two
+// states come back exactly: m0 = -max(d, 0), m1 = min(d, 0).  Binary
+// messages then move half the bytes.
+__device__ __forceinline__ float pk_m0(float d) { return d > 0.0f ? -d : 0.0f; }
+__device__ __forceinline__ float pk_m1(float d) { return d < 0.0f ? d : 0.0f; }
+// states s0 .. s0 + N - 1 of the message row at p, a row of n states, into
+// x (0 past the row's end, or everywhere when !ok, and then p is not read).
+// MODE 2: the row is packed (n is 2, s0 is 0); MODE 1: packed when n is 2;
+// MODE 0: one state per panel row whatever n (the reverse sweep's sums).
+// Callers pick the mode once per tile or variable where they can, so the
+// loads of an unrolled loop stay in one block.
+template <int N, int MODE, class PT>
+__device__ __forceinline__ void msg_load(PT p, int n, int s0, bool ok, float (&x)[N]) {
+    static_assert(N >= 2, "a packed row yields two states");
+    if (MODE == 2 || (MODE == 1 && n == 2)) {
+        const float d = ok ? p[0] : 0.0f;
+        x[0] = pk_m0(d);
+        x[1] = pk_m1(d);
+#pragma unroll
+        for (int s = 2; s < N; ++s) x[s] = 0.0f;
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < N; ++s) x[s] = (ok && s0 + s < n) ? p[(s0 + s) * kLanes] : 0.0f;
+}
+
+// state s of the message row at p, a row of n states (packed when n == 2)
+template <class PT>
+__device__ __forceinline__ float msg_state(PT p, int n, int s) {
+    if (n == 2) {
+        const float d = p[0];
+        return s == 0 ? pk_m0(d) : pk_m1(d);
+    }
+    return p[s * kLanes];
+}
+
 // damp, normalise and store one message row of n states held in registers
 template <int N>
 __device__ __forceinline__ void damp_store(float *row, const float (&mo)[N], const float (&u)[N], int n,
@@ -230,6 +269,10 @@ __device__ __forceinline__ void damp_store(float *row, const float (&mo)[N], con
             mn[s] = a + b;
             mx = fmaxf(mx, mn[s]);
         }
+    if (n == 2) {  // one of the two normalised states is +0, so the difference is exact
+        row[0] = (mn[1 % N] - mx) - (mn[0] - mx);
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < N; ++s)
         if (s < n) row[s * kLanes] = mn[s] - mx;
@@ -247,9 +290,9 @@ __device__ __forceinline__ void damp_store(float *row, const float (&mo)[N], con
 // blocks one high variable each.
 
 // low: NB >= states of every lane; edge rows fetched KU at a time (addresses,
-// then rows, all in flight) and added in edge order.
-template <int NB, class GV>
-__device__ __forceinline__ void belief_low_tile(const GV &G, int t, int lane) {
+// then rows, all in flight) and added in edge order.  MODE as for msg_load.
+template <int NB, int MODE, class GV>
+__device__ __forceinline__ void belief_low_tile_m(const GV &G, int t, int lane) {
     constexpr int KU = NB <= 4 ? 8 : 4;
     const VTile vt = G.vtile[t];
     const int n = G.vns[t * kLanes + lane];
@@ -264,9 +307,7 @@ __device__ __forceinline__ void belief_low_tile(const GV &G, int t, int lane) {
         for (int u = 0; u < KU; ++u) a[u] = (k0 + u < vt.kmax) ? ea[(k0 + u) * kLanes] : -1;
         float x[KU][NB];
 #pragma unroll
-        for (int u = 0; u < KU; ++u)
-#pragma unroll
-            for (int s = 0; s < NB; ++s) x[u][s] = (a[u] >= 0 && s < n) ? G.m[a[u] + s * kLanes] : 0.0f;
+        for (int u = 0; u < KU; ++u) msg_load<NB, MODE>(G.m + (a[u] >= 0 ? a[u] : 0), n, 0, a[u] >= 0, x[u]);
 #pragma unroll
         for (int u = 0; u < KU; ++u)
 #pragma unroll
@@ -276,6 +317,15 @@ __device__ __forceinline__ void belief_low_tile(const GV &G, int t, int lane) {
 #pragma unroll
     for (int s = 0; s < NB; ++s)
         if (s < n) G.B[base + s * kLanes] = acc[s];
+}
+
+// A tile whose panel has two rows holds only two-state variables (and idle
+// lanes): every row it reads is packed.
+template <int NB, class GV>
+__device__ __forceinline__ void belief_low_tile(const GV &G, int t, int lane) {
+    if (G.raw_msgs) belief_low_tile_m<NB, 0>(G, t, lane);
+    else if (G.vtile[t].n == 2) belief_low_tile_m<NB, 2>(G, t, lane);
+    else belief_low_tile_m<NB, 1>(G, t, lane);
 }
 
 // The beliefs of two lane-path variables at once (va with na states, vb with
@@ -319,10 +369,8 @@ __device__ __forceinline__ void belief_regs2(const GV &G, int va, int na, int vb
         float x[KU][NA], y[KU][NB];
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
-#pragma unroll
-            for (int s = 0; s < NA; ++s) x[u][s] = (a[u] >= 0 && s < na) ? G.m[a[u] + s * kLanes] : 0.0f;
-#pragma unroll
-            for (int s = 0; s < NB; ++s) y[u][s] = (b[u] >= 0 && s < nb) ? G.m[b[u] + s * kLanes] : 0.0f;
+            msg_load<NA, 1>(G.m + (a[u] >= 0 ? a[u] : 0), na, 0, a[u] >= 0, x[u]);
+            msg_load<NB, 1>(G.m + (b[u] >= 0 ? b[u] : 0), nb, 0, b[u] >= 0, y[u]);
         }
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
@@ -350,8 +398,8 @@ __device__ __forceinline__ void belief_mid_var(const GV &G, int hv, int lane) {
         const bool own = lane < SC && s0 + lane < h.n;
         const float th = own ? G.theta[h.b_addr + (s0 + lane) * kLanes] : 0.0f;
         float x[SC];
-#pragma unroll
-        for (int j = 0; j < SC; ++j) x[j] = (a >= 0 && s0 + j < h.n) ? G.m[a + (s0 + j) * kLanes] : 0.0f;
+        if (G.raw_msgs) msg_load<SC, 0>(G.m + (a >= 0 ? a : 0), h.n, s0, a >= 0, x);
+        else msg_load<SC, 1>(G.m + (a >= 0 ? a : 0), h.n, s0, a >= 0, x);
 #pragma unroll
         for (int j = 0; j < SC; ++j)
             if (s0 + j < h.n) x[j] = wave_sum(x[j]);  // uniform condition
@@ -370,7 +418,7 @@ __device__ __forceinline__ void belief_mid_var(const GV &G, int hv, int lane) {
 // wavefront sums are added in order.
 constexpr int kHighThreads = 256;
 constexpr int kHighWaves = kHighThreads / 64;
-template <class GV>
+template <int MODE, class GV>
 __device__ __forceinline__ void belief_high_var(const GV &G, int hv, int tid, float (*red)[kHighWaves]) {
     constexpr int SC = 8;  // states per pass
     constexpr int KC = 4;  // edges per thread fetched together
@@ -394,9 +442,7 @@ __device__ __forceinline__ void belief_high_var(const GV &G, int hv, int tid, fl
             float x[KC][SC];
 #pragma unroll
             for (int u = 0; u < KC; ++u)
-#pragma unroll
-                for (int j = 0; j < SC; ++j)
-                    x[u][j] = (a[u] >= 0 && j < ns) ? G.m[a[u] + (s0 + j) * kLanes] : 0.0f;
+                msg_load<SC, MODE>(G.m + (a[u] >= 0 ? a[u] : 0), h.n, s0, a[u] >= 0, x[u]);
 #pragma unroll
             for (int u = 0; u < KC; ++u)
 #pragma unroll
@@ -430,7 +476,7 @@ __device__ __forceinline__ void belief_high_var(const GV &G, int hv, int tid, fl
 constexpr int kColStates = 2;  // states per pass
 constexpr int kColRound = 16;  // edges per thread fetched together
 constexpr int kColRed = kColStates * kHighWaves * kColLanesMax;
-template <class GV>
+template <int MODE, class GV>
 __device__ __forceinline__ void belief_col_group(const GV &G, const HVar &h, int tid, float *red) {
     const int lsh = __builtin_ctz((unsigned)h.lanes), w = h.lanes;  // a power of two
     const int l = tid & (w - 1), kg = tid >> lsh, KG = kHighThreads >> lsh;
@@ -455,9 +501,7 @@ __device__ __forceinline__ void belief_col_group(const GV &G, const HVar &h, int
             float x[kColRound][kColStates];
 #pragma unroll
             for (int u = 0; u < kColRound; ++u)
-#pragma unroll
-                for (int j = 0; j < kColStates; ++j)
-                    x[u][j] = (a[u] >= 0 && j < ns) ? G.m[a[u] + (s0 + j) * kLanes] : 0.0f;
+                msg_load<kColStates, MODE>(G.m + (a[u] >= 0 ? a[u] : 0), h.n, s0, a[u] >= 0, x[u]);
 #pragma unroll
             for (int u = 0; u < kColRound; ++u)
 #pragma unroll
@@ -494,8 +538,16 @@ __global__ __launch_bounds__(256) void k_belief(const DevGraph *__restrict__ gs,
         const WorkItem it = items[n_low + n_mid + hb];
         const auto G = glob(gs[it.g]);
         const HVar h = G.hvar[it.t];
-        if (h.lanes > 1) belief_col_group(G, h, threadIdx.x, cred);
-        else belief_high_var(G, it.t, threadIdx.x, red);
+        // two-state rows are packed except in the reverse sweep's sums;
+        // rows of other variables hold one state per panel row
+        const bool pk = h.n == 2 && !G.raw_msgs;
+        if (h.lanes > 1) {
+            if (pk) belief_col_group<2>(G, h, threadIdx.x, cred);
+            else belief_col_group<0>(G, h, threadIdx.x, cred);
+        } else {
+            if (pk) belief_high_var<2>(G, it.t, threadIdx.x, red);
+            else belief_high_var<0>(G, it.t, threadIdx.x, red);
+        }
         return;
     }
     const int nwave = n_low + n_mid;
@@ -552,33 +604,25 @@ __device__ __forceinline__ void pair_tile(const GV &G, const FTile &ft, int lane
         const int va = a0 >= 0 ? (lane < ft.nact ? a0 + lane : -1) : G.fvar[ft.vb_off + lane];
         const int vb = a1 >= 0 ? (lane < ft.nact ? a1 + lane : -1) : G.fvar[ft.vb_off + kLanes + lane];
         belief_regs2<NA, NB>(G, va, na, vb, nb, b0, b1);
+        msg_load<NA, 1>(r0, na, 0, true, m0);
+        msg_load<NB, 1>(r1, nb, 0, true, m1);
 #pragma unroll
         for (int i = 0; i < NA; ++i)
-            if (i < na) {
-                m0[i] = r0[i * kLanes];
-                x0[i] = b0[i] - m0[i];
-            }
+            if (i < na) x0[i] = b0[i] - m0[i];
 #pragma unroll
         for (int j = 0; j < NB; ++j)
-            if (j < nb) {
-                m1[j] = r1[j * kLanes];
-                x1[j] = b1[j] - m1[j];
-            }
+            if (j < nb) x1[j] = b1[j] - m1[j];
     } else {
         const int va = G.fvb[ft.vb_off + lane];
         const int vb = G.fvb[ft.vb_off + kLanes + lane];
+        msg_load<NA, 1>(r0, na, 0, true, m0);
+        msg_load<NB, 1>(r1, nb, 0, true, m1);
 #pragma unroll
         for (int i = 0; i < NA; ++i)
-            if (i < na) {
-                m0[i] = r0[i * kLanes];
-                x0[i] = G.B[va + i * kLanes] - m0[i];
-            }
+            if (i < na) x0[i] = G.B[va + i * kLanes] - m0[i];
 #pragma unroll
         for (int j = 0; j < NB; ++j)
-            if (j < nb) {
-                m1[j] = r1[j * kLanes];
-                x1[j] = G.B[vb + j * kLanes] - m1[j];
-            }
+            if (j < nb) x1[j] = G.B[vb + j * kLanes] - m1[j];
     }
     if (!EARLY) load_table();
     float u0[NA], u1[NB];
@@ -692,8 +736,9 @@ __device__ __forceinline__ void logl_tile(const GV &G, const FTile &ft, int lane
 #pragma unroll
     for (int j = 0; j < K; ++j)
         if (j < k) {
-            m0[j] = rows[(2 * j) * kLanes];
-            m1[j] = rows[(2 * j + 1) * kLanes];
+            const float dj = rows[(2 * j) * kLanes];  // packed binary row
+            m0[j] = pk_m0(dj);
+            m1[j] = pk_m1(dj);
             const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
             const float n0 = G.B[vb] - m0[j];
             const float n1 = G.B[vb + kLanes] - m1[j];
@@ -755,8 +800,7 @@ __device__ __forceinline__ void logl_tile(const GV &G, const FTile &ft, int lane
             const float u0 = flip ? a1 : a0, u1 = flip ? a0 : a1;
             const float w0 = P.d * m0[j] + P.omd * u0, w1 = P.d * m1[j] + P.omd * u1;
             const float mx = fmaxf(w0, w1);
-            wrows[(2 * j) * kLanes] = w0 - mx;
-            wrows[(2 * j + 1) * kLanes] = w1 - mx;
+            wrows[(2 * j) * kLanes] = (w1 - mx) - (w0 - mx);
         }
 }
 
@@ -773,9 +817,9 @@ __device__ __forceinline__ void logw_tile(const GV &G, const FTile &ft, int lane
         dl[c] = 0.0f;
         t[c] = 0.0f;
         if (c < nch && j < k) {
-            const float *row = G.m + ft.m_off + c * 2 * kLanes + lane;
-            m0[c] = row[0];
-            m1[c] = row[kLanes];
+            const float dm = G.m[ft.m_off + c * 2 * kLanes + lane];  // packed binary row
+            m0[c] = pk_m0(dm);
+            m1[c] = pk_m1(dm);
             const int vb = G.fvb[ft.vb_off + j];
             const float n0 = G.B[vb] - m0[c];
             const float n1 = G.B[vb + kLanes] - m1[c];
@@ -852,9 +896,7 @@ __device__ __forceinline__ void logw_tile(const GV &G, const FTile &ft, int lane
             const float u0 = flip ? a1 : a0, u1 = flip ? a0 : a1;
             const float w0 = P.d * m0[c] + P.omd * u0, w1 = P.d * m1[c] + P.omd * u1;
             const float mx = fmaxf(w0, w1);
-            float *row = G.mo + ft.m_off + c * 2 * kLanes + lane;
-            row[0] = w0 - mx;
-            row[kLanes] = w1 - mx;
+            G.mo[ft.m_off + c * 2 * kLanes + lane] = (w1 - mx) - (w0 - mx);
         }
     }
 }
@@ -1015,7 +1057,7 @@ __device__ __forceinline__ void gen_tile(const GV &G, const FTile &ft, int lane,
         const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
         for (int s = 0; s < gc.slot_n[j]; ++s) {
             const int r = gc.slot_row[j] + s;
-            nv[r * kLanes + lane] = G.B[vb + s * kLanes] - mrow[r * kLanes];
+            nv[r * kLanes + lane] = G.B[vb + s * kLanes] - msg_state(mrow + gc.slot_row[j] * kLanes, gc.slot_n[j], s);
             acc[r * kLanes + lane] = -INFINITY;
             sacc[r * kLanes + lane] = 0.0f;
         }
@@ -1048,9 +1090,13 @@ __device__ __forceinline__ void gen_tile(const GV &G, const FTile &ft, int lane,
             const float lse =
                 MAXP ? acc[r * kLanes + lane] : acc[r * kLanes + lane] + flog2(sacc[r * kLanes + lane]) * P.r;
             const float u = lse - nv[r * kLanes + lane];
-            const float mn = P.d * mrow[r * kLanes] + P.omd * u;
+            const float mn = P.d * msg_state(mrow + r0 * kLanes, n, s) + P.omd * u;
             sacc[r * kLanes + lane] = mn;  // reuse as staging for the normalisation
             mx = fmaxf(mx, mn);
+        }
+        if (n == 2) {  // packed: one of the two normalised states is +0
+            wrow[r0 * kLanes] = (sacc[(r0 + 1) * kLanes + lane] - mx) - (sacc[r0 * kLanes + lane] - mx);
+            continue;
         }
         for (int s = 0; s < n; ++s) {
             const int r = r0 + s;
@@ -1073,7 +1119,7 @@ __device__ __forceinline__ void tri_tile(const GV &G, const FTile &ft, int lane,
         const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
 #pragma unroll
         for (int s = 0; s < N; ++s) {
-            m[j][s] = mrow[(j * N + s) * kLanes];
+            m[j][s] = msg_state(mrow + j * N * kLanes, N, s);
             x[j][s] = G.B[vb + s * kLanes] - m[j][s];
         }
     }
@@ -1190,18 +1236,14 @@ __global__ __launch_bounds__(256) void k_pair_adj(const DevGraph *__restrict__ g
     const int vb = G.fvb[ft.vb_off + kLanes + lane];
     const int o0 = ft.m_off + lane, o1 = o0 + na * kLanes;
     float m0[NA], m1[NB], x0[NA], x1[NB];
+    msg_load<NA, 1>(G.m + o0, na, 0, true, m0);
+    msg_load<NB, 1>(G.m + o1, nb, 0, true, m1);
 #pragma unroll
     for (int i = 0; i < NA; ++i)
-        if (i < na) {
-            m0[i] = G.m[o0 + i * kLanes];
-            x0[i] = G.B[va + i * kLanes] - m0[i];
-        }
+        if (i < na) x0[i] = G.B[va + i * kLanes] - m0[i];
 #pragma unroll
     for (int j = 0; j < NB; ++j)
-        if (j < nb) {
-            m1[j] = G.m[o1 + j * kLanes];
-            x1[j] = G.B[vb + j * kLanes] - m1[j];
-        }
+        if (j < nb) x1[j] = G.B[vb + j * kLanes] - m1[j];
     const float *ph = G.phi + ft.phi_off + lane;
     float p[NA][NB];
 #pragma unroll
@@ -1349,7 +1391,7 @@ __global__ __launch_bounds__(64) void k_gen_adj(const DevGraph *__restrict__ gs,
         const int vb = G.fvb[ft.vb_off + j * kLanes + lane];
         for (int s = 0; s < gc.slot_n[j]; ++s) {
             const int r = gc.slot_row[j] + s;
-            nv[r][lane] = G.B[vb + s * kLanes] - G.m[base + r * kLanes];
+            nv[r][lane] = G.B[vb + s * kLanes] - msg_state(G.m + base + gc.slot_row[j] * kLanes, gc.slot_n[j], s);
             lse[r][lane] = -INFINITY;
             acc[r][lane] = 0.0f;
         }
@@ -1381,7 +1423,7 @@ __global__ __launch_bounds__(64) void k_gen_adj(const DevGraph *__restrict__ gs,
             const int r = r0 + s;
             lse[r][lane] = lse[r][lane] + flog2(acc[r][lane]) * P.r;
             const float u = lse[r][lane] - nv[r][lane];
-            const float mp = P.d * G.m[base + r * kLanes] + P.omd * u;
+            const float mp = P.d * msg_state(G.m + base + r0 * kLanes, n, s) + P.omd * u;
             if (mp > mx) {
                 mx = mp;
                 am = s;
@@ -1549,7 +1591,7 @@ __global__ void k_msgs_out(const DevGraph *__restrict__ gs, float *__restrict__ 
     const float *row = G.m + G.edge_maddr[e];
     const int64_t o = G.es_off[e];
     const int n = (int)(G.es_off[e + 1] - o);
-    for (int s = 0; s < n; ++s) out[o + s] = row[s * kLanes];
+    for (int s = 0; s < n; ++s) out[o + s] = msg_state(row, n, s);
 }
 
 __global__ void k_msgs_in(const DevGraph *__restrict__ gs, const float *__restrict__ in) {
@@ -1559,6 +1601,11 @@ __global__ void k_msgs_in(const DevGraph *__restrict__ gs, const float *__restri
     float *row = G.m + G.edge_maddr[e];
     const int64_t o = G.es_off[e];
     const int n = (int)(G.es_off[e + 1] - o);
+    if (n == 2) {  // packed: the row is normalised first (its larger state to +0)
+        const float v0 = in[o], v1 = in[o + 1], mx = fmaxf(v0, v1);
+        row[0] = (v1 - mx) - (v0 - mx);
+        return;
+    }
     for (int s = 0; s < n; ++s) row[s * kLanes] = in[o + s];
 }
 
@@ -1589,7 +1636,7 @@ __device__ __forceinline__ void residual_partial(const GV &G, const float *__res
         const int a = G.edge_maddr[e];
         const int n = (int)(G.es_off[e + 1] - G.es_off[e]);
         for (int s = 0; s < n; ++s) {
-            const float d = fabsf(G.m[a + s * kLanes] - mprev[a + s * kLanes]);
+            const float d = fabsf(msg_state(G.m + a, n, s) - msg_state(mprev + a, n, s));
             r = (d == d && d <= 3.0e38f) ? fmaxf(r, d) : INFINITY;
         }
     }

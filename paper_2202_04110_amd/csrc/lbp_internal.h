@@ -120,6 +120,10 @@ struct DevGraph {
     const int64_t *lp_off;       // F+1
     int32_t *flag;               // non-finite read-out flag
     int32_t V, E, F, zero_addr;
+    // 0: message rows of two states are packed (one value, m1 - m0, see the
+    // kernels); 1: every row holds its states one per panel row (the reverse
+    // sweep's adjoint sums, summed by the variable phase like messages)
+    int32_t raw_msgs;
 };
 
 // A unit of a launch: tile t of graph g (index into the launch's graph array).

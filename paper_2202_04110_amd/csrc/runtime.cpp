@@ -439,6 +439,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         h.E = (int32_t)L.E;
         h.F = (int32_t)L.F;
         h.zero_addr = L.zero_addr;
+        h.raw_msgs = 0;
         g->dgraph = (DevGraph *)ptr(gp.dg);
         g->q_tmp = (float *)ptr(gp.q);
         g->map_tmp = (int32_t *)ptr(gp.map);
@@ -645,6 +646,7 @@ int adjoint_prepare(lbp_graph *g, int32_t iters, float d, float T, int32_t ckpt_
     views[k].B = J.Bt;
     views[k + 1].m = J.nbar;
     views[k + 1].mo = J.nbar;
+    views[k + 1].raw_msgs = 1;  // adjoint sums, one state per panel row
     views[k + 1].theta = J.zeros;
     views[k + 1].B = J.Bbar;
     HIP_TRY(hipMemcpyAsync(J.views, views.data(), sizeof(DevGraph) * (k + 2), hipMemcpyHostToDevice, st));

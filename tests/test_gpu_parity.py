@@ -123,10 +123,23 @@ def check_row_max_zero(spec, mg):
         assert np.all(mx == 0.0)
 
 
+def normalised(spec, m):
+    """Each message row shifted so that its largest state is 0: the form every
+    iteration leaves (the library keeps rows so, and stores a two-state row
+    as one number)."""
+    n = spec.var_num_states[spec.edge_var].astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(n)[:-1]])
+    if m.size == 0:
+        return m
+    return (m - np.repeat(np.maximum.reduceat(m, starts), n)).astype(m.dtype)
+
+
 def step_parity(lbp, ctx, spec, T, d=0.5, steps=1, seed=0, tol=TOL_STEP):
+    """Steps from random normalised messages, against the oracle's steps from
+    the same messages."""
     g = lbp.Graph(ctx, spec)
     og = OracleGraph(spec)
-    m0 = random_state(og, seed)
+    m0 = normalised(spec, random_state(og, seed))
     g.set_messages(m0)
     g.run_bp(steps, d, T)
     mg = g.get_messages()
