@@ -529,6 +529,38 @@ def test_batch_matches_alone_bitwise(lbp, ctx):
         b.free()
 
 
+def test_set_messages_keeps_two_state_rows_normalised(lbp, ctx):
+    """Two-state message rows are stored as one number, so lbp_set_messages
+    normalises them (largest state to 0, the difference kept to rounding);
+    rows of more states come back exactly as set.  A step from the raw state
+    and one from its normalised form match, since the update does not see a
+    shift of a whole row."""
+    spec = mixed_graph(7)
+    og = OracleGraph(spec)
+    n = spec.var_num_states[spec.edge_var].astype(np.int64)
+    assert (n == 2).any() and (n > 2).any()
+    off = np.concatenate([[0], np.cumsum(n)])
+    m = random_state(og, 11, scale=2.0)
+    g = lbp.Graph(ctx, spec)
+    g.set_messages(m)
+    got = g.get_messages()
+    for e in range(n.size):
+        a, b = off[e], off[e + 1]
+        if n[e] == 2:
+            assert got[a:b].max() == 0.0
+            assert abs((got[b - 1] - got[a]) - (m[b - 1] - m[a])) <= 4e-7 * max(1.0, abs(m[a]) + abs(m[b - 1]))
+        else:
+            np.testing.assert_array_equal(got[a:b], m[a:b])
+    g.run_bp(1, 0.5, 1.0)
+    h = lbp.Graph(ctx, spec)
+    h.set_messages(normalised(spec, m))
+    h.run_bp(1, 0.5, 1.0)
+    np.testing.assert_allclose(g.get_messages(), h.get_messages(), atol=2e-5)
+    np.testing.assert_allclose(g.get_beliefs(), h.get_beliefs(), atol=2e-5)
+    g.free()
+    h.free()
+
+
 # ------------------------------------------------------------ edge cases
 def test_zero_iterations_and_isolated_variables(lbp, ctx):
     spec = W.potts_grid(9, 3, 41)
