@@ -526,7 +526,7 @@ def main():
         args.no_gradient = args.no_scaleup = args.no_cpu_baseline = args.no_small = True
         args.paper_rbm = False
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -52,7 +52,7 @@ enum {
     LBP_E_STATE = -4,       /* call not valid in the object's current state */
     LBP_E_BUDGET = -5,      /* request larger than the server's memory budget */
     LBP_E_NONFINITE = -6,   /* beliefs contain NaN or infinity */
-    LBP_E_UNSUPPORTED = -7  /* valid graph outside this build's kernel limits */
+    LBP_E_UNSUPPORTED = -7  /* valid graph outside the library's kernel limits */
 };
 
 enum { LBP_FACTOR_ENUM = 0, LBP_FACTOR_OR = 1, LBP_FACTOR_AND = 2 };
