@@ -861,7 +861,31 @@ int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, floa
 
 int check_potentials_finite(const lbp_graph_desc *d, int64_t Tn, std::string *err) {
     const int64_t i = Tn > 0 ? first_nonfinite(d->log_potentials, Tn) : -1;
-    return i >= 0 ? bad(err, at("log_potentials", i) + " is not finite") : LBP_OK;
+    return i >= 0 ? nonfinite_potential(i, err) : LBP_OK;
+}
+
+int nonfinite_potential(int64_t i, std::string *err) { return bad(err, at("log_potentials", i) + " is not finite"); }
+
+int64_t copy_check_finite(float *dst, const float *src, int64_t n) {
+    constexpr int64_t B = 4096;
+    int64_t first = -1;
+    for (int64_t b = 0; b < n; b += B) {
+        const int64_t e = std::min(n, b + B);
+        uint32_t hit = 0;
+        for (int64_t i = b; i < e; ++i) {
+            uint32_t u;
+            std::memcpy(&u, src + i, sizeof u);
+            std::memcpy(dst + i, &u, sizeof u);
+            hit |= (uint32_t)((u & 0x7f800000u) == 0x7f800000u);
+        }
+        if (hit && first < 0)
+            for (int64_t i = b; i < e; ++i)
+                if (!std::isfinite(dst[i])) {
+                    first = i;
+                    break;
+                }
+    }
+    return first;
 }
 
 // Replays the address arithmetic of every kernel over the compiled layout and
@@ -1011,6 +1035,19 @@ int check_layout(const HostLayout &L, std::string *err) {
     if (L.fusable) {
         // the fused pairwise kernel recomputes each slot variable's belief from
         // its edge rows: the variable's tile, lane states and edge addresses
+        // (checked once per variable, then per slot that the variable and its
+        // state count are the tile's)
+        std::vector<char> rows_ok(L.V);
+        for (int64_t v = 0; v < L.V; ++v) {
+            const VTile &vt = L.vtile[v / kLanes];
+            const int32_t n = L.vns[v];
+            bool ok = in(vt.b_off + v % kLanes + (int64_t)(n - 1) * kLanes, VB);
+            for (int32_t k = 0; ok && k < vt.kmax; ++k) {
+                const int64_t ei = vt.e_off + (int64_t)k * kLanes + v % kLanes;
+                ok = in(ei, (int64_t)L.vedge.size()) && in(L.vedge[ei] + (int64_t)(n - 1) * kLanes, M);
+            }
+            rows_ok[v] = ok;
+        }
         for (const FGroup &fg : L.fgroups)
             for (int32_t t : fg.tiles) {
                 const FTile &ft = L.ftile[t];
@@ -1018,15 +1055,8 @@ int check_layout(const HostLayout &L, std::string *err) {
                     for (int32_t l = 0; l < ft.nact; ++l) {
                         const int32_t v = L.fvar[ft.vb_off + (int64_t)r * kLanes + l];
                         if (!in(v, L.V)) return oob("fused slot variable");
-                        const VTile &vt = L.vtile[v / kLanes];
-                        const int32_t n = L.vns[v];
-                        if (n != (r == 0 ? ft.a : ft.b)) return oob("fused slot states");
-                        for (int32_t k = 0; k < vt.kmax; ++k) {
-                            const int64_t ei = vt.e_off + (int64_t)k * kLanes + v % kLanes;
-                            if (!in(ei, (int64_t)L.vedge.size()) || !in(L.vedge[ei] + (int64_t)(n - 1) * kLanes, M))
-                                return oob("fused edge rows");
-                        }
-                        if (!in(vt.b_off + v % kLanes + (int64_t)(n - 1) * kLanes, VB)) return oob("fused evidence");
+                        if (L.vns[v] != (r == 0 ? ft.a : ft.b)) return oob("fused slot states");
+                        if (!rows_ok[v]) return oob("fused edge rows or evidence");
                     }
             }
     }

@@ -106,6 +106,11 @@ int fill_panels(const lbp_graph_desc *d, const HostLayout &L, float *theta, floa
 // LBP_OK (the check fill_panels makes on its way, for callers that leave the
 // panels to the device).
 int check_potentials_finite(const lbp_graph_desc *d, int64_t Tn, std::string *err);
+// Copies n floats and returns the index of the first NaN or infinity among
+// them, or -1 (one pass over the source).
+int64_t copy_check_finite(float *dst, const float *src, int64_t n);
+// LBP_E_INVALID naming log_potentials[i] as not finite.
+int nonfinite_potential(int64_t i, std::string *err);
 // Host replay of every kernel's addresses against the layout's array sizes.
 int check_layout(const HostLayout &L, std::string *err);
 

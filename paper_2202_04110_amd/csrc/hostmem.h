@@ -16,6 +16,6 @@ void *panel_alloc(size_t bytes);
 // Returns a buffer from panel_alloc (nullptr is ignored).
 void panel_free(void *p);
 
-constexpr size_t kPinnedPanelCap = size_t(1) << 30;
+constexpr size_t kPinnedPanelCap = size_t(4) << 30;
 
 }  // namespace lbp

@@ -289,6 +289,7 @@ struct GraphPieces {
     size_t faff;
     bool raw = false;       // the image holds the raw evidence and tables; panels are scattered on the device
     size_t rev = 0, rlp = 0;
+    size_t base = 0;        // device offset where the host image starts (after the raw potentials)
     size_t m, B, th, phi, ft, fvb, fvar, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
     size_t m2 = 0, fdg = 0;
     size_t data_end = 0;
@@ -303,12 +304,14 @@ struct GraphPieces {
         };
         // A layout compiled with its panels carries them in the image.  One
         // compiled without them (the server's preparation threads) carries the
-        // evidence and tables as given instead, and graph_create scatters them
-        // into panels that start as zeros: the device does the transpose.
+        // evidence as given instead, the tables as given come from a buffer
+        // of their own, and graph_create scatters both into panels that
+        // start as zeros: the device does the transpose.
         raw = L.theta_panel.size() != (size_t)L.VB || L.phi_panel.size() != (size_t)L.P;
         if (raw) {
+            rlp = add(nullptr, sizeof(float) * L.Tn);  // copied from the caller's buffer, not the image
+            base = total;
             rev = add(nullptr, sizeof(float) * L.VS);  // written by graph_fill_image
-            rlp = add(nullptr, sizeof(float) * L.Tn);
         } else {
             th = add(L.theta_panel.data(), sizeof(float) * L.VB);
             phi = add(L.phi_panel.data(), sizeof(float) * L.P);
@@ -357,26 +360,28 @@ struct GraphPieces {
 
 size_t graph_device_bytes(const HostLayout &L, bool with_fused) { return GraphPieces(L, with_fused).total; }
 
-size_t graph_image_bytes(const HostLayout &L) { return GraphPieces(L, false).data_end; }
-
-int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d, std::string *err) {
+size_t graph_image_bytes(const HostLayout &L) {
     GraphPieces gp(L, false);
+    return gp.data_end - gp.base;
+}
+
+int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d) {
+    GraphPieces gp(L, false);
+    char *at = image - gp.base;  // pieces are placed by device offset
     for (const Piece &p : gp.p)
-        if (p.src && p.bytes) std::memcpy(image + p.off, p.src, p.bytes);
-    pack_lists(gp.ll, image + gp.p[gp.items].off);
+        if (p.src && p.bytes) std::memcpy(at + p.off, p.src, p.bytes);
+    pack_lists(gp.ll, at + gp.p[gp.items].off);
     if (!gp.raw) return LBP_OK;
-    // the evidence and tables as given (graph_create scatters them into panels)
-    std::string e;
+    // the evidence as given (graph_create scatters it into its panel)
     if (!d) return set_error(LBP_E_INVALID, "graph image: the layout has no panels and no description was given");
-    float *ev = (float *)(image + gp.p[gp.rev].off);
+    float *ev = (float *)(at + gp.p[gp.rev].off);
     if (d->evidence) std::memcpy(ev, d->evidence, sizeof(float) * L.VS);
     else std::memset(ev, 0, sizeof(float) * L.VS);
-    if (L.Tn > 0) std::memcpy(image + gp.p[gp.rlp].off, d->log_potentials, sizeof(float) * L.Tn);
-    return check_potentials_finite(d, L.Tn, err ? err : &e);
+    return LBP_OK;
 }
 
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
-                 char *image, bool wait) {
+                 char *image, bool wait, const float *raw_lp) {
     lbp_graph *g = nullptr;
     char *own_image = nullptr;  // built here when the caller brings none
     try {
@@ -396,19 +401,16 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         }
         g->dbytes = gp.total;
         auto ptr = [&](size_t i) { return (void *)(g->dmem + gp.p[i].off); };
+        if (gp.raw && (!image || (L.Tn > 0 && !raw_lp))) {
+            if (g->owns_memory) (void)hipFree(g->dmem);
+            delete g;
+            return set_error(LBP_E_INVALID, "graph_create: a layout without panels needs its image and potentials");
+        }
         if (!image) {
             wait = true;  // the image built here is freed before returning
             own_image = (char *)panel_alloc(gp.data_end);
             if (!own_image) throw std::bad_alloc();
-            std::string ierr;
-            const int irc = gp.raw ? set_error(LBP_E_INVALID, "graph_create: a layout without panels needs its image")
-                                   : graph_fill_image(L, own_image, nullptr, &ierr);  // compiled with its panels
-            if (irc != LBP_OK) {
-                panel_free(own_image);
-                if (g->owns_memory) (void)hipFree(g->dmem);
-                delete g;
-                return irc;
-            }
+            graph_fill_image(L, own_image, nullptr);  // compiled with its panels: cannot fail
             image = own_image;
         }
         DevGraph &h = g->host;
@@ -446,8 +448,12 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         // the descriptor travels in the image: one copy of every host piece
         // (a single DMA when the image is page-locked), one fill for
         // messages, beliefs, flag and scratch
-        std::memcpy(image + gp.p[gp.dg].off, &g->host, sizeof(DevGraph));
-        hipError_t e = hipMemcpyAsync(g->dmem, image, gp.data_end, hipMemcpyHostToDevice, st);
+        std::memcpy(image + (gp.p[gp.dg].off - gp.base), &g->host, sizeof(DevGraph));
+        hipError_t e = hipSuccess;
+        if (gp.raw && L.Tn > 0)
+            e = hipMemcpyAsync(ptr(gp.rlp), raw_lp, sizeof(float) * L.Tn, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->dmem + gp.base, image, gp.data_end - gp.base, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemsetAsync(g->dmem + gp.data_end, 0, gp.total - gp.data_end, st);
         if (gp.raw && e == hipSuccess) {  // panels from the raw evidence and tables of the image
             e = launch_evidence_in(g->dgraph, (int)L.V, (const float *)ptr(gp.rev), st);

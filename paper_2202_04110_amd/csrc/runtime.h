@@ -186,17 +186,21 @@ size_t graph_device_bytes(const HostLayout &L, bool with_fused);
 // graph_fill_image), uploaded with one copy.
 size_t graph_image_bytes(const HostLayout &L);
 // Writes the image.  A layout compiled without its panels (compile_desc with
-// fill = false) has them written here from `d`, with fill_panels' checks.
-int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d = nullptr, std::string *err = nullptr);
+// fill = false) gets the evidence of `d` as given (checked by compile_desc);
+// its log-potentials as given travel in a buffer of the caller's, checked by
+// the caller, and are not part of the image.
+int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d = nullptr);
 // Creates a graph from a compiled (and checked) layout.  mem: a 256-aligned
 // region of graph_device_bytes(L, with_fused) bytes the caller owns, or
 // nullptr to allocate.  image: the layout's host image, or nullptr to build
-// one here (the graph's device descriptor is written into it).  Copies run
-// on `st`, and the call waits for them unless wait is
-// false and the caller brings the image: then the image must outlive the
+// one here (the graph's device descriptor is written into it); a layout
+// compiled without its panels needs its image and, when it has any, its
+// L.Tn log-potentials as given in raw_lp (NaN and infinity already refused).
+// Copies run on `st`, and the call waits for them unless wait is false and
+// the caller brings the image: then the image and raw_lp must outlive the
 // copies and work on other streams must wait for `st` before using the graph.
 int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, hipStream_t st, lbp_graph **out,
-                 char *image = nullptr, bool wait = true);
+                 char *image = nullptr, bool wait = true, const float *raw_lp = nullptr);
 void graph_destroy(lbp_graph *g);
 // The resident solver's plan of a graph's launch lists, if the graph fits it
 // (messages and beliefs within limit_words 4-byte words of LDS, no

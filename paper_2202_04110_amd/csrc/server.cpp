@@ -43,12 +43,21 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+struct PanelFree {
+    void operator()(char *p) const { panel_free(p); }
+};
+using PanelPtr = std::unique_ptr<char, PanelFree>;
+
 // Host copy of a graph description (the caller may free its arrays once
-// lbp_server_submit returns).
+// lbp_server_submit returns).  The log-potentials go to a pooled page-locked
+// buffer, checked for NaN and infinity on the way; the GPU executor uploads
+// them from there as they are (the device writes their panel).
 struct DescCopy {
     std::vector<int32_t> nst, kind, evar, ftab, tab_ncfg, tab_arity, tab_states;
-    std::vector<float> ev, lp;
+    std::vector<float> ev;
     std::vector<int64_t> fe_off, tab_off, lp_off;
+    PanelPtr lp;
+    int64_t lp_bad = -1;  // index of the first non-finite log-potential, or -1
     lbp_graph_desc d{};
 
     // `src` must have passed validate_desc with these sizes.
@@ -67,7 +76,9 @@ struct DescCopy {
             if (tab_off[NT] > 0) tab_states.assign(src->cfg_table_states, src->cfg_table_states + tab_off[NT]);
         }
         lp_off.assign(src->logpot_off, src->logpot_off + F + 1);
-        lp.assign(src->log_potentials, src->log_potentials + Tn);
+        lp.reset((char *)panel_alloc(sizeof(float) * std::max<int64_t>(1, Tn)));
+        if (!lp) throw std::bad_alloc();
+        if (Tn > 0) lp_bad = copy_check_finite((float *)lp.get(), src->log_potentials, Tn);
         d.num_vars = (int32_t)V;
         d.var_num_states = nst.data();
         d.evidence = src->evidence ? ev.data() : nullptr;
@@ -82,7 +93,7 @@ struct DescCopy {
         d.cfg_table_off = NT > 0 ? tab_off.data() : nullptr;
         d.cfg_table_states = tab_states.data();
         d.logpot_off = lp_off.data();
-        d.log_potentials = lp.data();
+        d.log_potentials = (const float *)lp.get();
     }
 };
 
@@ -122,12 +133,10 @@ struct Request {
     int32_t *map = nullptr;
     float *gphi = nullptr;
     float *gq_dev = nullptr, *gphi_dev = nullptr;
-    // device data packed for one upload (built by a prep thread; freed at
-    // admission or with the request)
-    struct ImageFree {
-        void operator()(char *p) const { panel_free(p); }
-    };
-    std::unique_ptr<char, ImageFree> image;
+    // device data packed for one upload (built by a prep thread) and the
+    // log-potentials as given (copied at submission), freed once the upload
+    // has completed or with the request
+    PanelPtr image, lp;
 };
 
 // What the scheduler asks of the machine.  The GPU executor runs the HIP
@@ -288,7 +297,7 @@ public:
     // flight).  One event after them all carries the upload generation.
     int admit(Request &r) override {
         char *mem = base_ + r.off;
-        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get(), false);
+        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get(), false, (const float *)r.lp.get());
         if (rc != LBP_OK) return rc;
         r.up_gen = ++up_gen_;  // from here on release waits for the copy stream
         r.g->last_T = r.T;
@@ -368,7 +377,10 @@ public:
 
     // the image of a request whose upload is known to have completed
     void drop_image(Request &r) {
-        if (r.image && r.up_gen <= up_done_) r.image.reset();
+        if (r.image && r.up_gen <= up_done_) {
+            r.image.reset();
+            r.lp.reset();
+        }
     }
 
     void residuals(const std::vector<Request *> &active) override {
@@ -456,6 +468,7 @@ public:
                 up_done_ = up_gen_;
             }
             r.image.reset();
+            r.lp.reset();
         }
         graph_destroy(r.g);  // the arena owns the memory
         r.g = nullptr;
@@ -753,11 +766,19 @@ struct lbp_server {
                 if (rc == LBP_OK && exec->wants_image()) {
                     // pack the upload here, off the worker thread, with the
                     // evidence and potential panels written in place
-                    r->image.reset((char *)panel_alloc(graph_image_bytes(r->L)));
-                    if (!r->image) throw std::bad_alloc();
-                    rc = graph_fill_image(r->L, r->image.get(), &r->desc->d, &err);
+                    if (r->desc->lp_bad >= 0) {
+                        rc = nonfinite_potential(r->desc->lp_bad, &err);
+                    } else {
+                        r->image.reset((char *)panel_alloc(graph_image_bytes(r->L)));
+                        if (!r->image) throw std::bad_alloc();
+                        rc = graph_fill_image(r->L, r->image.get(), &r->desc->d);
+                        r->lp = std::move(r->desc->lp);
+                    }
                     std::vector<int32_t>().swap(r->L.tile_fac);
-                    if (rc != LBP_OK) r->image.reset();
+                    if (rc != LBP_OK) {
+                        r->image.reset();
+                        r->lp.reset();
+                    }
                 }
             } catch (const std::bad_alloc &) {
                 rc = LBP_E_OOM;
