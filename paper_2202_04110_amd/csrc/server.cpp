@@ -117,6 +117,8 @@ struct Request {
     size_t conv_bytes = 0;    // previous messages, partial maxima, residual
     char *conv = nullptr;
     uint64_t up_gen = 0;      // upload number (executor's count) while its upload may be in flight
+    bool uploading = false;   // worker: handed to the executor's uploader, not yet taken back
+    int upload_status = LBP_OK;
     bool in_backward = false; // read out; its reverse sweep runs on the executor's finisher thread
     int back_status = LBP_OK;
     std::vector<float> grad_q;
@@ -167,6 +169,12 @@ public:
     virtual void take_backward(std::vector<Request *> &) {}
     virtual void set_wake(std::function<void()>) {}
     virtual void drain_backward() {}
+    // Uploads off the worker thread: admit may hand the request to an
+    // uploader (setting r.uploading) and return at once; take_uploaded
+    // returns those whose uploads are queued, with upload_status set (wake
+    // is called when one is); drain_uploads waits until none is left.
+    virtual void take_uploaded(std::vector<Request *> &) {}
+    virtual void drain_uploads() {}
     virtual int alloc_outputs(Request &r) = 0;
     virtual void free_outputs(Request &r) = 0;
     // whether prep threads should pack each request's upload image
@@ -206,6 +214,14 @@ public:
 class GpuExecutor : public Executor {
 public:
     ~GpuExecutor() override {
+        if (up_th_.joinable()) {
+            {
+                std::lock_guard<std::mutex> lk(umu_);
+                ustop_ = true;
+            }
+            ucv_.notify_all();
+            up_th_.join();
+        }
         if (fin_th_.joinable()) {
             {
                 std::lock_guard<std::mutex> lk(fmu_);
@@ -274,8 +290,9 @@ public:
         }
         try {
             fin_th_ = std::thread([this] { finisher(); });
+            up_th_ = std::thread([this] { uploader(); });
         } catch (const std::system_error &) {
-            return set_error(LBP_E_OOM, "could not start the finisher thread");
+            return set_error(LBP_E_OOM, "could not start the finisher or uploader thread");
         }
         return LBP_OK;
     }
@@ -285,40 +302,50 @@ public:
 
     bool wants_image() const override { return true; }
 
-    // Forward requests upload without waiting: the image stays with the
-    // request, the compute stream waits for the copy stream before the next
-    // round (or read-out) and the image is freed once that has completed.
-    // Backward requests (their adjoint buffers are prepared here) wait.
-    // Queues the request's uploads on the copy stream and waits for none of
-    // them: the graph image, and for a backward request the reverse sweep's
-    // views and its loss vector, all from host memory the request keeps
-    // (the image until a round or read-out has waited for this upload, the
-    // rest until the request ends; release waits for an upload still in
-    // flight).  One event after them all carries the upload generation.
+    // Admission hands the request to the uploader thread, which queues its
+    // uploads on the copy stream and waits for none of them: the graph image
+    // and potentials, and for a backward request the reverse sweep's views
+    // and its loss vector, all from host memory the request keeps (the image
+    // and potentials until a round or read-out has waited for this upload,
+    // the rest until the request ends; release waits for an upload still in
+    // flight).  The upload generation and the event recorded after each
+    // request's copies change together under umu_, so a wait on the event
+    // covers every request whose generation was read before it.
     int admit(Request &r) override {
-        char *mem = base_ + r.off;
-        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get(), false, (const float *)r.lp.get());
-        if (rc != LBP_OK) return rc;
-        r.up_gen = ++up_gen_;  // from here on release waits for the copy stream
-        r.g->last_T = r.T;
-        if (r.tol >= 0.0f) r.conv = mem + Arena::round(r.graph_bytes);
-        if (r.backward) {
-            char *am = mem + Arena::round(r.graph_bytes);
-            rc = adjoint_prepare(r.g, r.iters, r.d, r.T, r.k, am, copy_, &r.adj_views);
-            if (rc != LBP_OK) return rc;
-            r.gq_dev = (float *)(am + Arena::round(r.adj_bytes));
-            r.gphi_dev = (float *)((char *)r.gq_dev + Arena::round(sizeof(float) * r.L.VS));
-            HIP_TRY(hipMemcpyAsync(r.gq_dev, r.grad_q.data(), sizeof(float) * r.L.VS, hipMemcpyHostToDevice, copy_));
+        r.uploading = true;
+        {
+            std::lock_guard<std::mutex> lk(umu_);
+            uq_.push_back(&r);
+            ++upending_;
         }
-        HIP_TRY(hipEventRecord(up_ev_, copy_));
+        ucv_.notify_one();
         return LBP_OK;
     }
 
-    int round(const std::vector<Request *> &active, int32_t steps) override {
+    void take_uploaded(std::vector<Request *> &out) override {
+        std::lock_guard<std::mutex> lk(umu_);
+        out.insert(out.end(), udone_.begin(), udone_.end());
+        udone_.clear();
+    }
+
+    void drain_uploads() override {
+        std::unique_lock<std::mutex> lk(umu_);
+        udone_cv_.wait(lk, [&] { return upending_ == 0; });
+    }
+
+    // The compute stream waits for every upload queued so far.
+    int wait_uploads() {
+        std::lock_guard<std::mutex> lk(umu_);
         if (up_gen_ > up_done_) {
             HIP_TRY(hipStreamWaitEvent(compute_, up_ev_, 0));
             round_gen_ = up_gen_;
         }
+        return LBP_OK;
+    }
+
+    int round(const std::vector<Request *> &active, int32_t steps) override {
+        int urc = wait_uploads();
+        if (urc != LBP_OK) return urc;
         std::vector<uint64_t> ids;
         for (Request *r : active) ids.push_back(r->id);
         if (ids != ids_) {
@@ -394,8 +421,8 @@ public:
     // buffers, then one wait.  Backward requests then go to the finisher.
     int finish_begin(Request &r, int32_t slot) override {
         if (r.up_gen > up_done_) {  // not covered by a round yet (zero iterations)
-            HIP_TRY(hipStreamWaitEvent(compute_, up_ev_, 0));
-            round_gen_ = up_gen_;
+            int urc = wait_uploads();
+            if (urc != LBP_OK) return urc;
         }
         const TParams P = make_params(0.5f, r.T);
         HIP_TRY(launch_iteration(r.g->dgraph, r.g->vl, r.g->fl, P, r.T == 0.0f, compute_, 1));
@@ -464,8 +491,13 @@ public:
             // an upload that no round or read-out has waited for yet: the
             // arena memory and the image are reused only after it completes
             if (r.up_gen > up_done_) {
+                uint64_t g;
+                {
+                    std::lock_guard<std::mutex> lk(umu_);
+                    g = up_gen_;
+                }
                 (void)hipStreamSynchronize(copy_);
-                up_done_ = up_gen_;
+                up_done_ = std::max(up_done_, g);
             }
             r.image.reset();
             r.lp.reset();
@@ -476,7 +508,8 @@ public:
     }
 
     void images_done(const std::vector<Request *> &resident) override {
-        for (Request *r : resident) drop_image(*r);
+        for (Request *r : resident)
+            if (!r->uploading) drop_image(*r);  // the uploader still owns the others
     }
 
     int alloc_outputs(Request &r) override {
@@ -501,6 +534,62 @@ public:
     }
 
 private:
+    // A request's uploads on the copy stream (see admit).
+    int upload(Request &r) {
+        char *mem = base_ + r.off;
+        int rc = graph_create(&ctx_, r.L, false, mem, copy_, &r.g, r.image.get(), false, (const float *)r.lp.get());
+        if (rc == LBP_OK) {
+            r.g->last_T = r.T;
+            if (r.tol >= 0.0f) r.conv = mem + Arena::round(r.graph_bytes);
+            if (r.backward) {
+                char *am = mem + Arena::round(r.graph_bytes);
+                rc = adjoint_prepare(r.g, r.iters, r.d, r.T, r.k, am, copy_, &r.adj_views);
+                if (rc == LBP_OK) {
+                    r.gq_dev = (float *)(am + Arena::round(r.adj_bytes));
+                    r.gphi_dev = (float *)((char *)r.gq_dev + Arena::round(sizeof(float) * r.L.VS));
+                    hipError_t e = hipMemcpyAsync(r.gq_dev, r.grad_q.data(), sizeof(float) * r.L.VS,
+                                                  hipMemcpyHostToDevice, copy_);
+                    if (e != hipSuccess) rc = hip_error(e, "loss vector upload");
+                }
+            }
+        }
+        // from here on release waits for the copy stream (also after a
+        // failure part-way: some copies may be queued)
+        std::lock_guard<std::mutex> lk(umu_);
+        r.up_gen = ++up_gen_;
+        hipError_t e = hipEventRecord(up_ev_, copy_);
+        if (e != hipSuccess && rc == LBP_OK) rc = hip_error(e, "upload event");
+        return rc;
+    }
+
+    void uploader() {
+        (void)hipSetDevice(ctx_.device);
+        for (;;) {
+            Request *r = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(umu_);
+                ucv_.wait(lk, [&] { return ustop_ || !uq_.empty(); });
+                if (uq_.empty()) return;  // stopping with nothing queued
+                r = uq_.front();
+                uq_.pop_front();
+            }
+            const int rc = upload(*r);
+            std::function<void()> wake;
+            {
+                std::lock_guard<std::mutex> lk(umu_);
+                r->upload_status = rc;
+                udone_.push_back(r);
+                --upending_;
+            }
+            udone_cv_.notify_all();
+            {
+                std::lock_guard<std::mutex> lk(fmu_);
+                wake = wake_;
+            }
+            if (wake) wake();
+        }
+    }
+
     // The finisher: reverse sweeps of read-out backward requests on their own
     // stream, so they overlap the worker's rounds.  A request's graph is not
     // touched by the worker while it is here (it is resident but not active).
@@ -670,8 +759,15 @@ private:
     int fpending_ = 0;               // fmu_: handed over and not yet swept
     bool fstop_ = false;             // fmu_
     std::function<void()> wake_;
-    hipEvent_t up_ev_ = nullptr;     // recorded on the copy stream after each upload
-    uint64_t up_gen_ = 0;            // uploads issued
+    std::thread up_th_;              // the uploader
+    std::mutex umu_;
+    std::condition_variable ucv_, udone_cv_;
+    std::deque<Request *> uq_;       // umu_: admitted, waiting for the uploader
+    std::vector<Request *> udone_;   // umu_: uploads queued, for the worker to take back
+    int upending_ = 0;               // umu_: handed over and not yet taken back by the uploader
+    bool ustop_ = false;             // umu_
+    hipEvent_t up_ev_ = nullptr;     // umu_: recorded on the copy stream after each request's uploads
+    uint64_t up_gen_ = 0;            // umu_: uploads issued
     uint64_t up_done_ = 0;           // uploads known to have completed
     uint64_t round_gen_ = 0;         // uploads the compute stream was last made to wait for
     ConvJob *jobs_host_ = nullptr; // pinned staging of the round's checks
@@ -700,6 +796,7 @@ struct lbp_server {
     std::deque<Request *> pending;     // worker only
     std::vector<Request *> resident;   // worker only
     int64_t n_in_backward = 0;         // worker only: resident requests with the finisher
+    int64_t n_uploading = 0;           // worker only: resident requests with the uploader
     int back_ready = 0;                // mu: finisher completions not yet taken
     bool stop = false;                 // mu
     std::thread th;
@@ -853,7 +950,23 @@ struct lbp_server {
                 continue;
             }
             r->t_admit = clock();
+            if (r->uploading) ++n_uploading;
             resident.push_back(r);
+        }
+    }
+
+    // Requests the uploader has handed back; those whose upload failed leave.
+    void take_uploaded() {
+        std::vector<Request *> up;
+        exec->take_uploaded(up);
+        for (Request *r : up) {
+            r->uploading = false;
+            --n_uploading;
+            if (r->upload_status != LBP_OK) {
+                drop_resident(r);
+                resident.erase(std::find(resident.begin(), resident.end(), r));
+                complete(r, r->upload_status);
+            }
         }
     }
 
@@ -872,7 +985,7 @@ struct lbp_server {
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv.wait(lk, [&] {
-                    return stop || !incoming.empty() || (int64_t)resident.size() > n_in_backward ||
+                    return stop || !incoming.empty() || (int64_t)resident.size() > n_in_backward + n_uploading ||
                            !cancels.empty() || back_ready > 0 || (!pending.empty() && pending.front()->prep != 0);
                 });
                 if (stop) break;
@@ -889,6 +1002,7 @@ struct lbp_server {
                 }
                 cancels.clear();
             }
+            take_uploaded();
             // requests whose reverse sweep has finished leave
             {
                 std::vector<Request *> swept;
@@ -902,9 +1016,10 @@ struct lbp_server {
                 }
             }
             // cancelled resident requests leave at this round boundary (those
-            // with the finisher complete when their sweep does)
+            // with the finisher complete when their sweep does, those with
+            // the uploader once it hands them back)
             for (size_t i = 0; i < resident.size();) {
-                if (resident[i]->cancel && !resident[i]->in_backward) {
+                if (resident[i]->cancel && !resident[i]->in_backward && !resident[i]->uploading) {
                     Request *r = resident[i];
                     drop_resident(r);
                     resident.erase(resident.begin() + i);
@@ -918,7 +1033,7 @@ struct lbp_server {
             std::vector<Request *> active;
             int32_t s = steps;
             for (Request *r : resident)
-                if (r->done < r->iters && !r->settled) {
+                if (r->done < r->iters && !r->settled && !r->uploading) {
                     active.push_back(r);
                     s = std::min(s, r->iters - r->done);
                     if (r->backward) s = std::min(s, r->k - r->done % r->k);
@@ -960,7 +1075,7 @@ struct lbp_server {
             // leaves (its memory is reused only after the wait)
             std::vector<Request *> fin;
             for (Request *r : resident)
-                if ((r->done >= r->iters || r->settled) && !r->in_backward) fin.push_back(r);
+                if ((r->done >= r->iters || r->settled) && !r->in_backward && !r->uploading) fin.push_back(r);
             if (!fin.empty()) {
                 const double tf = clock();
                 std::vector<int> rcs(fin.size(), LBP_OK);
@@ -987,7 +1102,10 @@ struct lbp_server {
             }
             update_stats();
         }
-        // shutting down: sweeps under way finish, everything else is cancelled
+        // shutting down: uploads and sweeps under way finish, everything else
+        // is cancelled
+        exec->drain_uploads();
+        take_uploaded();
         exec->drain_backward();
         {
             std::vector<Request *> swept;
