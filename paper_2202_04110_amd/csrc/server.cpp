@@ -117,6 +117,7 @@ struct Request {
     size_t conv_bytes = 0;    // previous messages, partial maxima, residual
     char *conv = nullptr;
     uint64_t up_gen = 0;      // upload number (executor's count) while its upload may be in flight
+    hipEvent_t up_ev = nullptr;  // recorded on the copy stream after its uploads (while they may be in flight)
     bool uploading = false;   // worker: handed to the executor's uploader, not yet taken back
     int upload_status = LBP_OK;
     bool in_backward = false; // read out; its reverse sweep runs on the executor's finisher thread
@@ -150,6 +151,8 @@ public:
     virtual int admit(Request &r) = 0;
     virtual int round(const std::vector<Request *> &active, int32_t steps) = 0;
     virtual int wait() = 0;
+    // waits for everything queued for rounds (after a failed launch)
+    virtual void quiesce() {}
     // Read-out of finished requests: finish_begin for each (slot: its index
     // in this batch, < max_slots), one finish_wait, then finish_end for each.
     virtual int finish_begin(Request &r, int32_t slot) = 0;
@@ -233,6 +236,8 @@ public:
         (void)hipSetDevice(ctx_.device);
         if (back_) (void)hipStreamSynchronize(back_);
         if (back_) (void)hipStreamDestroy(back_);
+        if (read_) (void)hipStreamSynchronize(read_);
+        if (read_) (void)hipStreamDestroy(read_);
         if (compute_) (void)hipStreamSynchronize(compute_);
         if (copy_) (void)hipStreamSynchronize(copy_);
         if (stage_) (void)hipFree(stage_);
@@ -241,7 +246,7 @@ public:
         if (jobs_host_) (void)hipHostFree(jobs_host_);
         if (flags_host_) (void)hipHostFree(flags_host_);
         if (read_host_) (void)hipHostFree(read_host_);
-        if (up_ev_) (void)hipEventDestroy(up_ev_);
+        for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
         if (jobs_dev_) (void)hipFree(jobs_dev_);
         if (ev_) (void)hipEventDestroy(ev_);
         if (compute_) (void)hipStreamDestroy(compute_);
@@ -255,8 +260,8 @@ public:
         HIP_TRY(hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking));
         HIP_TRY(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
         HIP_TRY(hipStreamCreateWithFlags(&back_, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&read_, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&up_ev_, hipEventDisableTiming));
         if (hipHostMalloc((void **)&flags_host_, sizeof(int32_t) * (size_t)max_slots) != hipSuccess ||
             hipHostMalloc((void **)&read_host_, sizeof(ReadJob) * (size_t)max_slots) != hipSuccess) {
             (void)hipGetLastError();
@@ -308,9 +313,10 @@ public:
     // and its loss vector, all from host memory the request keeps (the image
     // and potentials until a round or read-out has waited for this upload,
     // the rest until the request ends; release waits for an upload still in
-    // flight).  The upload generation and the event recorded after each
-    // request's copies change together under umu_, so a wait on the event
-    // covers every request whose generation was read before it.
+    // flight).  Each request's copies end with an event of its own, recorded
+    // with its upload number under umu_ (numbers follow the copy stream's
+    // order), so a round waits only for the uploads of the requests it runs:
+    // those of the latest of them, and with them every earlier one.
     int admit(Request &r) override {
         r.uploading = true;
         {
@@ -333,18 +339,29 @@ public:
         udone_cv_.wait(lk, [&] { return upending_ == 0; });
     }
 
-    // The compute stream waits for every upload queued so far.
-    int wait_uploads() {
-        std::lock_guard<std::mutex> lk(umu_);
-        if (up_gen_ > up_done_) {
-            HIP_TRY(hipStreamWaitEvent(compute_, up_ev_, 0));
-            round_gen_ = up_gen_;
+    // Stream st waits for the uploads of requests rs not yet known complete;
+    // *gen records how far that reaches (complete once st has been waited for).
+    int wait_uploads(hipStream_t st, Request *const *rs, size_t n, uint64_t *gen) {
+        const Request *last = nullptr;
+        for (size_t i = 0; i < n; ++i)
+            if (rs[i]->up_gen > up_done_ && (!last || rs[i]->up_gen > last->up_gen)) last = rs[i];
+        if (last) {
+            HIP_TRY(hipStreamWaitEvent(st, last->up_ev, 0));
+            *gen = std::max(*gen, last->up_gen);
         }
         return LBP_OK;
     }
 
+    // an upload known complete: its event goes back to the pool
+    void retire_upload(Request &r) {
+        if (!r.up_ev) return;
+        std::lock_guard<std::mutex> lk(umu_);
+        ev_pool_.push_back(r.up_ev);
+        r.up_ev = nullptr;
+    }
+
     int round(const std::vector<Request *> &active, int32_t steps) override {
-        int urc = wait_uploads();
+        int urc = wait_uploads(compute_, active.data(), active.size(), &round_gen_);
         if (urc != LBP_OK) return urc;
         std::vector<uint64_t> ids;
         for (Request *r : active) ids.push_back(r->id);
@@ -396,6 +413,8 @@ public:
         return LBP_OK;
     }
 
+    void quiesce() override { (void)hipStreamSynchronize(compute_); }
+
     int wait() override {
         HIP_TRY(hipEventSynchronize(ev_));
         up_done_ = std::max(up_done_, round_gen_);
@@ -407,6 +426,7 @@ public:
         if (r.image && r.up_gen <= up_done_) {
             r.image.reset();
             r.lp.reset();
+            retire_upload(r);
         }
     }
 
@@ -415,17 +435,20 @@ public:
             if (r->check_now) r->residual = res_host_[r->res_slot];
     }
 
-    // A batch of read-outs: each graph's beliefs from its messages (its own
-    // belief launches), then one launch that writes every request's
-    // normalised beliefs and MAP straight into its page-locked result
-    // buffers, then one wait.  Backward requests then go to the finisher.
+    // A batch of read-outs on the read-out stream, beside the next round
+    // (which holds none of these graphs): each graph's beliefs from its
+    // messages (its own belief launches), then one launch that writes every
+    // request's normalised beliefs and MAP straight into its page-locked
+    // result buffers, then one wait.  Backward requests then go to the
+    // finisher.  The worker has waited for the round that last ran them.
     int finish_begin(Request &r, int32_t slot) override {
         if (r.up_gen > up_done_) {  // not covered by a round yet (zero iterations)
-            int urc = wait_uploads();
+            Request *rp = &r;
+            int urc = wait_uploads(read_, &rp, 1, &read_gen_);
             if (urc != LBP_OK) return urc;
         }
         const TParams P = make_params(0.5f, r.T);
-        HIP_TRY(launch_iteration(r.g->dgraph, r.g->vl, r.g->fl, P, r.T == 0.0f, compute_, 1));
+        HIP_TRY(launch_iteration(r.g->dgraph, r.g->vl, r.g->fl, P, r.T == 0.0f, read_, 1));
         flags_host_[slot] = 0;
         ReadJob &J = read_host_[fin_.size()];  // jobs packed in the order they are queued
         J.g = r.g->dgraph;
@@ -445,13 +468,13 @@ public:
         for (int i = 0; i < n; ++i) max_tiles = std::max(max_tiles, read_host_[i].ntiles);
         int rc = LBP_OK;
         if (n > 0) {
-            hipError_t e = hipMemcpyAsync(read_dev_, read_host_, sizeof(ReadJob) * n, hipMemcpyHostToDevice, compute_);
-            if (e == hipSuccess) e = launch_readout_multi(read_dev_, n, max_tiles, compute_);
+            hipError_t e = hipMemcpyAsync(read_dev_, read_host_, sizeof(ReadJob) * n, hipMemcpyHostToDevice, read_);
+            if (e == hipSuccess) e = launch_readout_multi(read_dev_, n, max_tiles, read_);
             if (e != hipSuccess) rc = hip_error(e, "read-out launch");
         }
         fin_.clear();
-        HIP_TRY(hipStreamSynchronize(compute_));
-        up_done_ = std::max(up_done_, round_gen_);
+        HIP_TRY(hipStreamSynchronize(read_));
+        up_done_ = std::max(up_done_, read_gen_);
         return rc;
     }
 
@@ -491,17 +514,14 @@ public:
             // an upload that no round or read-out has waited for yet: the
             // arena memory and the image are reused only after it completes
             if (r.up_gen > up_done_) {
-                uint64_t g;
-                {
-                    std::lock_guard<std::mutex> lk(umu_);
-                    g = up_gen_;
-                }
-                (void)hipStreamSynchronize(copy_);
-                up_done_ = std::max(up_done_, g);
+                if (r.up_ev) (void)hipEventSynchronize(r.up_ev);
+                else (void)hipStreamSynchronize(copy_);
+                up_done_ = std::max(up_done_, r.up_gen);
             }
             r.image.reset();
             r.lp.reset();
         }
+        retire_upload(r);
         graph_destroy(r.g);  // the arena owns the memory
         r.g = nullptr;
         ids_.clear();        // the resident set changes
@@ -557,7 +577,19 @@ private:
         // failure part-way: some copies may be queued)
         std::lock_guard<std::mutex> lk(umu_);
         r.up_gen = ++up_gen_;
-        hipError_t e = hipEventRecord(up_ev_, copy_);
+        hipError_t e = hipSuccess;
+        if (!ev_pool_.empty()) {
+            r.up_ev = ev_pool_.back();
+            ev_pool_.pop_back();
+        } else {
+            e = hipEventCreateWithFlags(&r.up_ev, hipEventDisableTiming);
+            if (e != hipSuccess) r.up_ev = nullptr;  // release then waits for the whole copy stream
+        }
+        if (e == hipSuccess) e = hipEventRecord(r.up_ev, copy_);
+        if (e != hipSuccess && r.up_ev) {  // not recorded: release waits for the whole copy stream
+            ev_pool_.push_back(r.up_ev);
+            r.up_ev = nullptr;
+        }
         if (e != hipSuccess && rc == LBP_OK) rc = hip_error(e, "upload event");
         return rc;
     }
@@ -751,6 +783,8 @@ private:
     ReadJob *read_dev_ = nullptr;    // its device copy (after res_dev_)
     std::vector<Request *> fin_;     // the batch being read out
     hipStream_t back_ = nullptr;     // the finisher's stream
+    hipStream_t read_ = nullptr;     // read-outs of finished requests
+    uint64_t read_gen_ = 0;          // uploads the read-out stream was last made to wait for
     std::thread fin_th_;
     std::mutex fmu_;
     std::condition_variable fcv_, fdone_cv_;
@@ -766,7 +800,7 @@ private:
     std::vector<Request *> udone_;   // umu_: uploads queued, for the worker to take back
     int upending_ = 0;               // umu_: handed over and not yet taken back by the uploader
     bool ustop_ = false;             // umu_
-    hipEvent_t up_ev_ = nullptr;     // umu_: recorded on the copy stream after each request's uploads
+    std::vector<hipEvent_t> ev_pool_;  // umu_: upload events not in use
     uint64_t up_gen_ = 0;            // umu_: uploads issued
     uint64_t up_done_ = 0;           // uploads known to have completed
     uint64_t round_gen_ = 0;         // uploads the compute stream was last made to wait for
@@ -979,15 +1013,23 @@ struct lbp_server {
         arena_peak = (int64_t)arena.peak();
     }
 
+    // The worker keeps at most one round in flight.  After waiting for it,
+    // it launches the next round first and then, while that runs, reads out
+    // the requests the finished round completed (on their own stream) and
+    // admits new ones, so the GPU is idle only between a round's end and the
+    // next launch.
     void run() {
         if (gpu) gpu->bind();
+        std::vector<Request *> inflight;  // the round in flight
+        int32_t inflight_s = 0;
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv.wait(lk, [&] {
-                    return stop || !incoming.empty() || (int64_t)resident.size() > n_in_backward + n_uploading ||
-                           !cancels.empty() || back_ready > 0 || (!pending.empty() && pending.front()->prep != 0);
-                });
+                if (inflight.empty())
+                    cv.wait(lk, [&] {
+                        return stop || !incoming.empty() || (int64_t)resident.size() > n_in_backward + n_uploading ||
+                               !cancels.empty() || back_ready > 0 || (!pending.empty() && pending.front()->prep != 0);
+                    });
                 if (stop) break;
                 back_ready = 0;
                 while (!incoming.empty()) {
@@ -1001,6 +1043,33 @@ struct lbp_server {
                         if (r->id == id) r->cancel = true;
                 }
                 cancels.clear();
+            }
+            const double tl = clock();
+            // the round in flight ends
+            if (!inflight.empty()) {
+                const double tw = clock();
+                int rc = exec->wait();
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    round_s += clock() - tw;
+                }
+                if (rc != LBP_OK) {
+                    for (Request *r : inflight) {
+                        drop_resident(r);
+                        resident.erase(std::find(resident.begin(), resident.end(), r));
+                        complete(r, rc);
+                    }
+                } else {
+                    exec->residuals(inflight);
+                    exec->images_done(resident);
+                    for (Request *r : inflight) {
+                        r->done += inflight_s;
+                        if (r->check_now && r->residual < r->tol) r->settled = true;
+                    }
+                    std::lock_guard<std::mutex> lk(mu);
+                    ++n_rounds;
+                }
+                inflight.clear();
             }
             take_uploaded();
             // requests whose reverse sweep has finished leave
@@ -1030,6 +1099,7 @@ struct lbp_server {
             }
             admit();
             update_stats();
+            // the next round
             std::vector<Request *> active;
             int32_t s = steps;
             for (Request *r : resident)
@@ -1041,38 +1111,30 @@ struct lbp_server {
                 }
             for (Request *r : active)
                 r->check_now = r->tol >= 0.0f && ((r->done + s) % r->check == 0 || r->done + s == r->iters);
-            const double tr = clock();
             if (!active.empty()) {
+                const double tr = clock();
                 int rc = exec->round(active, s);
                 {
                     std::lock_guard<std::mutex> lk(mu);
                     launch_s += clock() - tr;
-                }
-                if (rc == LBP_OK) admit();  // uploads on the copy stream overlap the round
-                if (rc == LBP_OK) rc = exec->wait();
-                {
-                    std::lock_guard<std::mutex> lk(mu);
                     round_s += clock() - tr;
                 }
                 if (rc != LBP_OK) {
+                    // whatever of it was queued ends before its memory is reused
+                    exec->quiesce();
                     for (Request *r : active) {
                         drop_resident(r);
                         resident.erase(std::find(resident.begin(), resident.end(), r));
                         complete(r, rc);
                     }
-                    continue;
+                } else {
+                    inflight = active;
+                    inflight_s = s;
                 }
-                exec->residuals(active);
-                exec->images_done(resident);
-                for (Request *r : active) {
-                    r->done += s;
-                    if (r->check_now && r->residual < r->tol) r->settled = true;
-                }
-                std::lock_guard<std::mutex> lk(mu);
-                ++n_rounds;
             }
-            // finished requests: all read-outs queued, one wait, then each
-            // leaves (its memory is reused only after the wait)
+            // finished requests (none is in the round just launched): all
+            // read-outs queued, one wait, then each leaves (its memory is
+            // reused only after the wait)
             std::vector<Request *> fin;
             for (Request *r : resident)
                 if ((r->done >= r->iters || r->settled) && !r->in_backward && !r->uploading) fin.push_back(r);
@@ -1096,12 +1158,15 @@ struct lbp_server {
                 std::lock_guard<std::mutex> lk(mu);
                 finish_s += clock() - tf;
             }
+            admit();  // slots and memory the read-outs freed
             {
                 std::lock_guard<std::mutex> lk(mu);
-                busy_s += clock() - tr;
+                busy_s += clock() - tl;
             }
             update_stats();
         }
+        // a round still in flight ends first
+        if (!inflight.empty()) (void)exec->wait();
         // shutting down: uploads and sweeps under way finish, everything else
         // is cancelled
         exec->drain_uploads();
