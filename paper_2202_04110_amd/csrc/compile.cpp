@@ -58,6 +58,49 @@ bool pair_fast(bool dense, int32_t arity, const int32_t *ns) {
     return dense && arity == 2 && ns[0] <= kPairStatesMax && ns[1] <= kPairStatesMax;
 }
 
+// Internal variable order.  A logical factor with more edges than a lane
+// tile holds is gathered by one wavefront, which reads the beliefs of all
+// its parents (every edge but the last); parents with at most two edges are
+// renumbered consecutively in the order those factors list them, into the
+// positions they held (every other variable keeps its id), so that the
+// gather reads consecutive lanes of few panels.  order[i] = the caller's id
+// of internal id i; false (and order empty) when no variable moves.
+bool internal_order(const lbp_graph_desc *d, std::vector<int32_t> *order) {
+    const int64_t V = d->num_vars, F = d->num_factors, E = V > 0 ? d->factor_edge_off[F] : 0;
+    auto wide = [&](int64_t f) {
+        return d->factor_kind[f] != LBP_FACTOR_ENUM &&
+               d->factor_edge_off[f + 1] - d->factor_edge_off[f] > kLogLaneArityMax;
+    };
+    bool any = false;
+    for (int64_t f = 0; f < F && !any; ++f) any = wide(f);
+    if (!any) return false;
+    std::vector<int32_t> deg(V, 0);
+    for (int64_t e = 0; e < E; ++e) ++deg[d->edge_var[e]];
+    std::vector<char> taken(V, 0);
+    std::vector<int32_t> seq;
+    for (int64_t f = 0; f < F; ++f) {
+        if (!wide(f)) continue;
+        for (int64_t e = d->factor_edge_off[f]; e + 1 < d->factor_edge_off[f + 1]; ++e) {
+            const int32_t v = d->edge_var[e];
+            if (deg[v] <= 2 && !taken[v]) {
+                taken[v] = 1;
+                seq.push_back(v);
+            }
+        }
+    }
+    std::vector<int32_t> pos(seq);
+    std::sort(pos.begin(), pos.end());
+    order->resize(V);
+    for (int64_t v = 0; v < V; ++v) (*order)[v] = (int32_t)v;
+    bool moved = false;
+    for (size_t i = 0; i < seq.size(); ++i) {
+        (*order)[pos[i]] = seq[i];
+        moved = moved || pos[i] != seq[i];
+    }
+    if (!moved) order->clear();
+    return moved;
+}
+
 }  // namespace
 
 int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err, bool scan_potentials) {
@@ -201,20 +244,46 @@ int validate_desc(const lbp_graph_desc *d, int64_t sizes[6], std::string *err, b
     return LBP_OK;
 }
 
-int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool fill) {
+int compile_desc(const lbp_graph_desc *d_in, HostLayout *L, std::string *err, bool fill) {
     int64_t sz[6];
     // the potentials are checked for NaN and infinity while they are copied
     // into their panels (every one of them is), not in a pass of their own
-    int rc = validate_desc(d, sz, err, false);
+    int rc = validate_desc(d_in, sz, err, false);
     if (rc != LBP_OK) return rc;
     L->V = sz[0]; L->VS = sz[1]; L->F = sz[2]; L->E = sz[3]; L->ES = sz[4]; L->Tn = sz[5];
     const int64_t V = L->V, F = L->F, E = L->E;
+
+    // The layout is built over the variables in internal order, from a copy
+    // of the description whose edges name internal ids (factors keep theirs).
+    const lbp_graph_desc *d = d_in;
+    lbp_graph_desc pd;
+    std::vector<int32_t> p_nst, p_evar;
+    L->vext.clear();
+    if (internal_order(d_in, &L->vext)) {
+        std::vector<int32_t> inv(V);
+        for (int64_t i = 0; i < V; ++i) inv[L->vext[i]] = (int32_t)i;
+        p_nst.resize(V);
+        for (int64_t i = 0; i < V; ++i) p_nst[i] = d_in->var_num_states[L->vext[i]];
+        p_evar.resize(E);
+        for (int64_t e = 0; e < E; ++e) p_evar[e] = inv[d_in->edge_var[e]];
+        pd = *d_in;
+        pd.var_num_states = p_nst.data();
+        pd.edge_var = p_evar.data();
+        pd.evidence = nullptr;  // read through vs_off from the caller's description only
+        d = &pd;
+    }
 
     L->vs_off.assign(V + 1, 0);
     L->vn.assign(V, 0);
     for (int64_t v = 0; v < V; ++v) {
         L->vn[v] = d->var_num_states[v];
         L->vs_off[v + 1] = L->vs_off[v] + L->vn[v];
+    }
+    if (!L->vext.empty()) {  // offsets in the caller's flat order
+        std::vector<int64_t> ext(V + 1, 0);
+        for (int64_t v = 0; v < V; ++v) ext[v + 1] = ext[v] + d_in->var_num_states[v];
+        for (int64_t i = 0; i < V; ++i) L->vs_off[i] = ext[L->vext[i]];
+        L->vs_off[V] = ext[V];
     }
     L->es_off.assign(E + 1, 0);
     for (int64_t e = 0; e < E; ++e) L->es_off[e + 1] = L->es_off[e] + L->vn[d->edge_var[e]];
@@ -355,6 +424,15 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
             fl.swap(sorted);
         } else {
             std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
+        }
+        if (std::get<0>(class_key[c]) == TK_LOGL && !L->vext.empty()) {
+            // renumbered variables (wide logical factors' parents): by the
+            // internal id of the child instead, so a tile's children are the
+            // consecutive parents of a few wide factors (measured faster on
+            // the deconvolution graph than keeping the first variable's
+            // blocks together, which in turn beats the caller's order)
+            auto child = [&](int32_t f) { return d->edge_var[d->factor_edge_off[f + 1] - 1]; };
+            std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) { return child(x) < child(y); });
         }
         if (std::get<0>(class_key[c]) != TK_PAIR) continue;
         // pairwise factors that all join two block-path variables (a dense
@@ -786,7 +864,7 @@ int compile_desc(const lbp_graph_desc *d, HostLayout *L, std::string *err, bool 
     L->theta_panel.resize(L->VB);
     L->phi_panel.resize(L->P);
     L->tile_fac.swap(tile_fac);
-    rc = fill_panels(d, *L, L->theta_panel.data(), L->phi_panel.data(), err);
+    rc = fill_panels(d_in, *L, L->theta_panel.data(), L->phi_panel.data(), err);
     std::vector<int32_t>().swap(L->tile_fac);
     return rc;
 }
@@ -1008,6 +1086,11 @@ int check_layout(const HostLayout &L, std::string *err) {
             }
         }
     // read-out and flat-order exchange
+    if (!L.vext.empty()) {
+        if ((int64_t)L.vext.size() != L.V) return oob("variable order size");
+        for (int64_t v = 0; v < L.V; ++v)
+            if (!in(L.vext[v], L.V)) return oob("variable order entry");
+    }
     for (int64_t v = 0; v < L.V; ++v) {
         const VTile &vt = L.vtile[v / kLanes];
         if (L.vn[v] > vt.n) return oob("read-out panel rows");

@@ -81,8 +81,12 @@ struct HostLayout {
     std::vector<GenClass> gcls;
     std::vector<uint8_t> grows;
     std::vector<int32_t> edge_maddr;
+    // Variables are laid out in an internal order (see compile_desc): vn,
+    // vs_off and every tile array are indexed by internal id, vs_off holds
+    // each variable's offset in the caller's flat order, and vext maps an
+    // internal id to the caller's (empty when the two orders agree).
     std::vector<int64_t> es_off, vs_off;
-    std::vector<int32_t> vn, fac_phi;
+    std::vector<int32_t> vn, fac_phi, vext;
     std::vector<int64_t> lp_off;
     PanelBuf theta_panel, phi_panel;  // every element written by compile_desc (or fill_panels)
     std::vector<int32_t> tile_fac;    // factor of each (tile, lane) with a potential panel, -1 otherwise

@@ -73,7 +73,7 @@ struct GGraph {
     gptr<const uint8_t> grows;
     gptr<const int32_t> edge_maddr;
     gptr<const int64_t> es_off, vs_off;
-    gptr<const int32_t> vn, fac_phi;
+    gptr<const int32_t> vn, fac_phi, vext;
     gptr<const int64_t> lp_off;
     gptr<int32_t> flag;
     int32_t V, E, F, zero_addr, raw_msgs;
@@ -105,6 +105,7 @@ __device__ __forceinline__ GGraph glob(const DevGraph &d) {
     g.vs_off = as_global(d.vs_off);
     g.vn = as_global(d.vn);
     g.fac_phi = as_global(d.fac_phi);
+    g.vext = as_global(d.vext);
     g.lp_off = as_global(d.lp_off);
     g.flag = as_global(d.flag);
     g.V = d.V;
@@ -1547,7 +1548,7 @@ __device__ __forceinline__ void readout_tile(const GV &G, int w, const TParams &
         G.flag[0] = 1;
         if (flag_host) flag_host[0] = 1;
     }
-    if (mapout) mapout[v] = best;
+    if (mapout) mapout[G.vext ? G.vext[v] : v] = best;
     if (qout) {
         float z = 0.0f;
         if (normalized) {

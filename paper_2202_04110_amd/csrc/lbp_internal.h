@@ -114,8 +114,9 @@ struct DevGraph {
     // flat-order mapping (read-out, state exchange)
     const int32_t *edge_maddr;   // E
     const int64_t *es_off;       // E+1
-    const int64_t *vs_off;       // V+1
+    const int64_t *vs_off;       // V+1, by internal id: offset in the caller's flat order
     const int32_t *vn;           // V
+    const int32_t *vext;         // V: the caller's id of each internal id, or null (same order)
     const int32_t *fac_phi;      // F: potential address of config 0, -1 logical
     const int64_t *lp_off;       // F+1
     int32_t *flag;               // non-finite read-out flag

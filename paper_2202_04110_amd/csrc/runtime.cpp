@@ -290,7 +290,7 @@ struct GraphPieces {
     bool raw = false;       // the image holds the raw evidence and tables; panels are scattered on the device
     size_t rev = 0, rlp = 0;
     size_t base = 0;        // device offset where the host image starts (after the raw potentials)
-    size_t m, B, th, phi, ft, fvb, fvar, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, fp, lp, fl, dg, q, map, items;
+    size_t m, B, th, phi, ft, fvb, fvar, vt, ve, vns, hv, he, gc, gr, em, es, vs, vn, vx, fp, lp, fl, dg, q, map, items;
     size_t m2 = 0, fdg = 0;
     size_t data_end = 0;
     bool fused;
@@ -331,6 +331,7 @@ struct GraphPieces {
         es = add(L.es_off.data(), sizeof(int64_t) * L.es_off.size());
         vs = add(L.vs_off.data(), sizeof(int64_t) * L.vs_off.size());
         vn = add(L.vn.data(), sizeof(int32_t) * L.vn.size());
+        vx = add(L.vext.data(), sizeof(int32_t) * L.vext.size());
         fp = add(L.fac_phi.data(), sizeof(int32_t) * L.fac_phi.size());
         lp = add(L.lp_off.data(), sizeof(int64_t) * L.lp_off.size());
         GraphShape s{L.fgroups, L.vgroups, L.mids, L.highs, L.cols};
@@ -434,6 +435,7 @@ int graph_create(lbp_ctx *ctx, const HostLayout &L, bool with_fused, char *mem, 
         h.es_off = (const int64_t *)ptr(gp.es);
         h.vs_off = (const int64_t *)ptr(gp.vs);
         h.vn = (const int32_t *)ptr(gp.vn);
+        h.vext = L.vext.empty() ? nullptr : (const int32_t *)ptr(gp.vx);
         h.fac_phi = (const int32_t *)ptr(gp.fp);
         h.lp_off = (const int64_t *)ptr(gp.lp);
         h.flag = (int32_t *)ptr(gp.fl);

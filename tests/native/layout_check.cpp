@@ -193,6 +193,75 @@ int main() {
          {"column group entry", [](HostLayout &L) { L.cols.push_back(L.highs.back()); }},
          {"variable path lists", [](HostLayout &L) { L.cols.pop_back(); }}});
 
+    // a small blind deconvolution: 2 activation maps of 8 units, a 3-unit
+    // template each, products AND(S, W) in activation order, 10 pixels each
+    // an OR over the products that land on it.  The products (two edges
+    // each) are renumbered in pixel order into the ids they held; the
+    // activation and template units keep theirs.
+    Builder dc;
+    const int K = 2, sd = 8, tw = 3, img = 10;
+    std::vector<int> W, S, prod_pix;
+    for (int i = 0; i < K * tw; ++i) W.push_back(dc.var(2));
+    for (int i = 0; i < K * sd; ++i) S.push_back(dc.var(2));
+    std::vector<std::vector<int>> pix_par(img);
+    std::vector<int> prods;
+    for (int k = 0; k < K; ++k)
+        for (int p = 0; p < sd; ++p)
+            for (int a = 0; a < tw; ++a)
+                if (p + a < img) {
+                    const int sw = dc.var(2);
+                    prods.push_back(sw);
+                    pix_par[p + a].push_back(sw);
+                    dc.logical({S[k * sd + p], W[k * tw + a], sw}, LBP_FACTOR_AND);
+                }
+    std::vector<int> X, pad;
+    for (int i = 0; i < img; ++i) X.push_back(dc.var(2));
+    // parents shared by every OR (more than two edges each: never renumbered)
+    // make each OR wide enough for a wavefront tile
+    for (int i = 0; i < kLogLaneArityMax; ++i) pad.push_back(dc.var(2));
+    for (int i = 0; i < img; ++i) {
+        std::vector<int> vs = pix_par[i];
+        vs.insert(vs.end(), pad.begin(), pad.end());
+        vs.push_back(X[i]);
+        dc.logical(vs, LBP_FACTOR_OR);
+    }
+    {
+        HostLayout L;
+        std::string err;
+        expect(compile_desc(dc.desc(), &L, &err) == LBP_OK, "deconvolution: compile: " + err);
+        const int64_t V = L.V;
+        expect((int64_t)L.vext.size() == V, "deconvolution: variables renumbered");
+        std::vector<int> inv(V, -1);
+        bool perm = (int64_t)L.vext.size() == V;
+        for (int64_t i = 0; perm && i < V; ++i) {
+            perm = L.vext[i] >= 0 && L.vext[i] < V && inv[L.vext[i]] < 0;
+            if (perm) inv[L.vext[i]] = (int)i;
+        }
+        expect(perm, "deconvolution: the order is a permutation");
+        if (perm) {
+            for (int v : W) expect(inv[v] == v, "deconvolution: template units keep their ids");
+            for (int v : S) expect(inv[v] == v, "deconvolution: activation units keep their ids");
+            for (int v : X) expect(inv[v] == v, "deconvolution: pixels keep their ids");
+            for (int v : pad) expect(inv[v] == v, "deconvolution: shared parents keep their ids");
+            // every OR factor's product parents, in its edge order, are consecutive internal ids
+            int next = prods.front();
+            for (int i = 0; i < img; ++i)
+                for (int v : pix_par[i]) expect(inv[v] == next++, "deconvolution: OR parents consecutive");
+            // the flat offsets follow the caller's order
+            for (int64_t i = 0; i < V; ++i) expect(L.vs_off[i] == 2LL * L.vext[i], "deconvolution: flat offsets");
+        }
+    }
+    run("deconvolution", dc,
+        {{"variable order entry", [](HostLayout &L) { L.vext[3] = (int32_t)L.V; }},
+         {"variable order size", [](HostLayout &L) { L.vext.pop_back(); }}});
+
+    // a graph without wide logical factors keeps the caller's order
+    {
+        HostLayout L;
+        std::string err;
+        expect(compile_desc(g.desc(), &L, &err) == LBP_OK && L.vext.empty(), "grid: caller's order kept");
+    }
+
     if (failures) {
         std::printf("%d failures\n", failures);
         return 1;
