@@ -325,11 +325,13 @@ void lbp_sampler_free(lbp_sampler *s);
  * worker thread admits queued requests first-in first-out whenever a slot
  * is free and the server's memory arena (one device allocation of
  * hbm_budget_bytes) has room for the graph, its messages and, for backward
- * requests, the checkpoint workspace.  Admitted graphs are uploaded on a copy
- * stream while the compute stream advances every resident graph by up to
- * steps_per_round iterations per round in shared multi-graph launches (the
- * batch form above); graphs join and leave at round boundaries, and their
- * messages stay resident in between.  Results are bitwise equal to lone runs.
+ * requests, the checkpoint workspace.  An uploader thread queues each
+ * admitted graph's copies on a copy stream while the compute stream advances
+ * every resident graph whose upload is queued by up to steps_per_round
+ * iterations per round in shared multi-graph launches (the batch form
+ * above); graphs join and leave at round boundaries, and their messages stay
+ * resident in between.  Finished graphs are read out on a stream of their
+ * own beside the next round.  Results are bitwise equal to lone runs.
  */
 typedef struct lbp_completion {
     uint64_t req_id;
@@ -399,8 +401,9 @@ int lbp_server_drain(lbp_server *s, double timeout_s);
  * cancelled, rounds, resident now, queued now, max resident, arena peak bytes,
  * worker busy microseconds, of which in rounds (launch + wait), preparation
  * microseconds summed over the preparation threads, preparation threads,
- * worker microseconds in admissions, in enqueueing rounds (launch lists and
- * kernels), in read-outs of finished requests}. */
+ * worker microseconds in admissions (handing requests to the uploader), in
+ * enqueueing rounds (launch lists and kernels), in read-outs of finished
+ * requests}. */
 int lbp_server_stats(lbp_server *s, int64_t out[18]);
 /* Stops the worker (queued and resident requests are dropped) and frees
  * everything. */
