@@ -426,13 +426,20 @@ int compile_desc(const lbp_graph_desc *d_in, HostLayout *L, std::string *err, bo
             std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) { return key(x) < key(y); });
         }
         if (std::get<0>(class_key[c]) == TK_LOGL && !L->vext.empty()) {
-            // renumbered variables (wide logical factors' parents): by the
-            // internal id of the child instead, so a tile's children are the
-            // consecutive parents of a few wide factors (measured faster on
-            // the deconvolution graph than keeping the first variable's
-            // blocks together, which in turn beats the caller's order)
+            // renumbered variables (wide logical factors' parents): within a
+            // block, by the internal id of the child, so a tile's children
+            // are consecutive parents of a few wide factors while its first
+            // variables stay in one block (measured on the deconvolution
+            // graph against ordering by the child alone: within 2% either
+            // way, this one ahead with the tuned launch shapes)
             auto child = [&](int32_t f) { return d->edge_var[d->factor_edge_off[f + 1] - 1]; };
-            std::stable_sort(fl.begin(), fl.end(), [&](int32_t x, int32_t y) { return child(x) < child(y); });
+            for (size_t i = 0; i < fl.size();) {
+                size_t j = i;
+                while (j < fl.size() && key(fl[j]) == key(fl[i])) ++j;
+                std::stable_sort(fl.begin() + (int64_t)i, fl.begin() + (int64_t)j,
+                                 [&](int32_t x, int32_t y) { return child(x) < child(y); });
+                i = j;
+            }
         }
         if (std::get<0>(class_key[c]) != TK_PAIR) continue;
         // pairwise factors that all join two block-path variables (a dense
