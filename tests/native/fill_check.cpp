@@ -6,7 +6,9 @@
 // 4, and a three-way class.  Built against liblbp.so and run by
 // tests/test_fill_check.py.
 #include <cmath>
+#include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <limits>
 #include <string>
 #include <vector>
@@ -102,6 +104,36 @@ int main() {
     for (int i = 0; i < 70; ++i) c.enumf({v2[i], v5[(i * 7) % 70]}, tp);
     for (int i = 0; i + 1 < 40; ++i) c.enumf({v2[i], v3[i], v3[i + 1]}, t3);
     check("mixed classes", c);
+
+    // the submission-time copy of the potentials: every value copied bit for
+    // bit (signed zeros, denormals, the largest finite values included) and
+    // the first NaN or infinity reported, wherever it falls in its block
+    {
+        const int64_t n = 3 * 4096 + 77;
+        std::vector<float> src(n), dst(n);
+        for (int64_t i = 0; i < n; ++i) src[i] = (float)((i * 37) % 1001) * 0.25f - 100.0f;
+        src[5] = -0.0f;
+        src[9] = 1e-40f;
+        src[11] = 3.4e38f;
+        src[12] = -3.4e38f;
+        int64_t r = copy_check_finite(dst.data(), src.data(), n);
+        expect(r == -1, "finite copy: no index");
+        expect(std::memcmp(dst.data(), src.data(), sizeof(float) * n) == 0, "finite copy: bitwise");
+        const float bad[3] = {std::numeric_limits<float>::quiet_NaN(), std::numeric_limits<float>::infinity(),
+                              -std::numeric_limits<float>::infinity()};
+        const int64_t at[4] = {0, 4095, 4096, n - 1};
+        for (float b : bad)
+            for (int64_t i : at) {
+                std::vector<float> s2(src);
+                s2[i] = b;
+                if (i + 100 < n) s2[i + 100] = b;  // a later one is not the first
+                std::fill(dst.begin(), dst.end(), 7.0f);
+                r = copy_check_finite(dst.data(), s2.data(), n);
+                expect(r == i, "non-finite copy: first index " + std::to_string(i));
+                expect(std::memcmp(dst.data(), s2.data(), sizeof(float) * n) == 0, "non-finite copy: bitwise");
+            }
+        expect(copy_check_finite(dst.data(), src.data(), 0) == -1, "empty copy");
+    }
     if (failures) {
         std::printf("%d failures\n", failures);
         return 1;
