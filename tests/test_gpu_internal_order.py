@@ -4,8 +4,8 @@ order; everything that crosses the boundary stays in the caller's order.
 
 The check: the same graph with its variables relabelled by a random
 permutation gives bitwise the same results, mapped through the permutation
-(beliefs, MAP, messages, results after new evidence, perturb-and-MAP samples
-and served results).  Relabelling keeps every variable's edges in the same
+(beliefs, MAP, messages, results after new evidence, perturb-and-MAP samples,
+batched and served results).  Relabelling keeps every variable's edges in the same
 order and no variable here has enough edges for column groups, so each
 variable's sum runs in the same order in both layouts.  The graph is also
 checked against the FP64 oracle over its first iterations."""
@@ -138,6 +138,35 @@ def test_relabelled_graph_gives_the_same_results(lbp, ctx, T):
     finally:
         g.free()
         g2.free()
+
+
+def test_batched_with_a_relabelled_copy(lbp, ctx):
+    """A batch holding the graph, its relabelled copy and a Potts grid (in
+    the caller's order) gives each graph its lone results."""
+    spec = scattered_graph(38)
+    perm = np.random.default_rng(39).permutation(spec.num_vars)
+    spec2 = relabel(spec, perm)
+    fidx = flat_perm(spec, perm)
+    grid = W.potts_grid(20, 3, 40)
+    lone = []
+    for sp in (spec, spec2, grid):
+        g = lbp.Graph(ctx, sp)
+        g.run_bp(25, 0.5, 0.0)
+        lone.append((g.get_beliefs(), g.decode_map()))
+        g.free()
+    gs = [lbp.Graph(ctx, sp) for sp in (spec, spec2, grid)]
+    b = lbp.Batch(ctx, gs)
+    try:
+        b.run_bp(25, 0.5, 0.0)
+        for g, (q, mp) in zip(gs, lone):
+            np.testing.assert_array_equal(g.get_beliefs(), q)
+            np.testing.assert_array_equal(g.decode_map(), mp)
+        np.testing.assert_array_equal(gs[0].get_beliefs(), gs[1].get_beliefs()[fidx])
+        np.testing.assert_array_equal(gs[0].decode_map(), gs[1].decode_map()[perm])
+    finally:
+        b.free()
+        for g in gs:
+            g.free()
 
 
 def test_internal_order_against_the_oracle(lbp, ctx):
