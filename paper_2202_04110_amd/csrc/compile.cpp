@@ -309,6 +309,12 @@ int compile_desc(const lbp_graph_desc *d_in, HostLayout *L, std::string *err, bo
     VB += (int64_t)kLanes * kMaxStates;
     L->VB = VB;
     std::vector<int32_t> tile_fac;  // factor of each (tile, lane) with a potential panel, -1 otherwise
+    // the tiles' rows hold every edge once plus idle lanes: room for the
+    // edges and a few partial tiles, so the arrays rarely grow by copying
+    L->fvb.reserve((size_t)E + 64 * kLanes);
+    L->fvar.reserve((size_t)E + 64 * kLanes);
+    L->ftile.reserve((size_t)F / kLanes + 64);
+    tile_fac.reserve((size_t)F + 64 * kLanes);
     auto add_vb_rows = [&](int32_t rows) {
         tile_fac.resize((L->ftile.size() + 1) * kLanes, -1);
         const size_t base = L->fvb.size();
@@ -392,8 +398,13 @@ int compile_desc(const lbp_graph_desc *d_in, HostLayout *L, std::string *err, bo
                 c = it->second;
             }
         }
-        class_facs[c].push_back((int32_t)f);
         fclass[f] = c;
+    }
+    {  // members in factor order, each class sized once
+        std::vector<size_t> cnt(class_key.size(), 0);
+        for (int64_t f = 0; f < F; ++f) ++cnt[fclass[f]];
+        for (size_t c = 0; c < class_key.size(); ++c) class_facs[c].reserve(cnt[c]);
+        for (int64_t f = 0; f < F; ++f) class_facs[fclass[f]].push_back((int32_t)f);
     }
 
     L->edge_maddr.assign(E, 0);
@@ -712,6 +723,8 @@ int compile_desc(const lbp_graph_desc *d_in, HostLayout *L, std::string *err, bo
 
     // ------------------------------------------------ variable edge-address rows
     L->vns.assign(nvt * kLanes, 0);
+    L->vedge.reserve((size_t)E + 16 * kLanes);  // rows of low-degree lanes: about one entry per edge
+    L->hedge.reserve((size_t)E / 4 + kLanes);
     std::map<int32_t, size_t> vgroup_of;
     auto degree = [&](int64_t v) { return adj_off[v + 1] - adj_off[v]; };
     auto edge_addr = [&](int64_t v, int64_t k) { return L->edge_maddr[adj[adj_off[v] + k]]; };
