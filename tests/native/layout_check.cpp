@@ -255,6 +255,34 @@ int main() {
         {{"variable order entry", [](HostLayout &L) { L.vext[3] = (int32_t)L.V; }},
          {"variable order size", [](HostLayout &L) { L.vext.pop_back(); }}});
 
+    // parents shared by two wide factors (taken by the first), a parent
+    // listed twice in one factor, and parents that are children elsewhere:
+    // still a permutation, and the layout checks clean
+    {
+        Builder e;
+        std::vector<int> vs;
+        for (int i = 0; i < 120; ++i) vs.push_back(e.var(2));
+        std::vector<int> o1, o2, o3;
+        for (int i = 0; i < 30; ++i) o1.push_back(vs[(i * 37) % 120]);
+        o1.push_back(vs[119]);
+        for (int i = 0; i < 20; ++i) o2.push_back(vs[(i * 37) % 120]);  // the same parents again
+        o2.push_back(vs[118]);
+        for (int i = 0; i < 12; ++i) o3.push_back(vs[(i * 53 + 7) % 120]);
+        o3.push_back(o3[0]);  // a parent twice
+        o3.push_back(vs[(5 * 37) % 120]);  // a child that is also a parent above
+        e.logical(o1, LBP_FACTOR_OR);
+        e.logical(o2, LBP_FACTOR_AND);
+        e.logical(o3, LBP_FACTOR_OR);
+        HostLayout L;
+        std::string err;
+        expect(compile_desc(e.desc(), &L, &err) == LBP_OK, "shared parents: compile: " + err);
+        std::vector<int> seen(L.V, 0);
+        bool perm = L.vext.empty() || (int64_t)L.vext.size() == L.V;
+        for (int32_t x : L.vext) perm = perm && x >= 0 && x < L.V && !seen[x]++;
+        expect(perm, "shared parents: the order is a permutation");
+        expect(check_layout(L, &err) == LBP_OK, "shared parents: layout check: " + err);
+    }
+
     // a graph without wide logical factors keeps the caller's order
     {
         HostLayout L;
