@@ -223,3 +223,47 @@ def test_early_exit_requests_equal_lone_run_until(lbp, ctx):
         assert r["iters"] == pit and r["residual"] == -1.0
         np.testing.assert_array_equal(r["beliefs"], q)
         np.testing.assert_array_equal(r["map"], mp)
+
+
+def test_many_small_requests_through_the_uploader(lbp, ctx):
+    """Hundreds of small requests (many uploads in flight at once, upload
+    events reused, rounds that start while later requests still upload),
+    some with a tolerance and some with zero iterations: every one completes
+    and a sample equals its lone run bitwise."""
+    rng = np.random.default_rng(60)
+    specs, params = [], []
+    for i in range(300):
+        L, n = int(rng.integers(6, 25)), int(rng.integers(2, 6))
+        specs.append(W.potts_grid(L, n, 600 + i))
+        params.append((int(rng.choice([0, 7, 20, 33])), bool(rng.random() < 0.2)))
+    srv = lbp.Server(ctx, budget_bytes=32 << 20, max_slots=16, steps_per_round=6)
+    for i, (spec, (it, early)) in enumerate(zip(specs, params)):
+        if early and it > 0:
+            srv.submit(spec, it, 0.5, 1.0, req_id=i, tol=1e-3, check_every=4)
+        else:
+            srv.submit(spec, it, 0.5, 1.0, req_id=i)
+    srv.drain(120)
+    res = {}
+    while True:
+        got = srv.poll(256)
+        if not got:
+            break
+        for r in got:
+            res[r["req_id"]] = r
+    st = srv.stats()
+    srv.close()
+    assert len(res) == len(specs) and all(r["status"] == 0 for r in res.values())
+    assert st["max_resident"] > 1
+    for i in range(0, len(specs), 23):
+        it, early = params[i]
+        g = lbp.Graph(ctx, specs[i])
+        if early and it > 0:
+            done, _ = g.run_bp_until(it, 0.5, 1.0, 1e-3, 4)
+        else:
+            g.run_bp(it, 0.5, 1.0)
+            done = it
+        q, mp = g.get_beliefs(), g.decode_map()
+        g.free()
+        assert res[i]["iters"] == done
+        np.testing.assert_array_equal(res[i]["beliefs"], q)
+        np.testing.assert_array_equal(res[i]["map"], mp)
