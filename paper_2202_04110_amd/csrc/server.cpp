@@ -499,8 +499,10 @@ public:
         bdone_.clear();
     }
 
+    // Once set_wake returns, no call of the previous function is under way
+    // or will start: the server clears it before it goes away.
     void set_wake(std::function<void()> w) override {
-        std::lock_guard<std::mutex> lk(fmu_);
+        std::lock_guard<std::mutex> lk(wmu_);
         wake_ = std::move(w);
     }
 
@@ -554,6 +556,12 @@ public:
     }
 
 private:
+    // Wakes the worker (a sweep or an upload has finished).
+    void call_wake() {
+        std::lock_guard<std::mutex> lk(wmu_);
+        if (wake_) wake_();
+    }
+
     // A request's uploads on the copy stream (see admit).
     int upload(Request &r) {
         char *mem = base_ + r.off;
@@ -606,7 +614,6 @@ private:
                 uq_.pop_front();
             }
             const int rc = upload(*r);
-            std::function<void()> wake;
             {
                 std::lock_guard<std::mutex> lk(umu_);
                 r->upload_status = rc;
@@ -614,11 +621,7 @@ private:
                 --upending_;
             }
             udone_cv_.notify_all();
-            {
-                std::lock_guard<std::mutex> lk(fmu_);
-                wake = wake_;
-            }
-            if (wake) wake();
+            call_wake();
         }
     }
 
@@ -645,15 +648,13 @@ private:
                 if (e != hipSuccess) rc = hip_error(e, "gradient read-out");
             }
             r->back_status = rc;
-            std::function<void()> wake;
             {
                 std::lock_guard<std::mutex> lk(fmu_);
                 bdone_.push_back(r);
                 --fpending_;
-                wake = wake_;
             }
             fdone_cv_.notify_all();
-            if (wake) wake();
+            call_wake();
         }
     }
 
@@ -792,6 +793,7 @@ private:
     std::vector<Request *> bdone_;   // fmu_: swept, for the worker to complete
     int fpending_ = 0;               // fmu_: handed over and not yet swept
     bool fstop_ = false;             // fmu_
+    std::mutex wmu_;                 // guards wake_ and every call of it
     std::function<void()> wake_;
     std::thread up_th_;              // the uploader
     std::mutex umu_;
