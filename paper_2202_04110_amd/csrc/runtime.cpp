@@ -368,14 +368,16 @@ size_t graph_image_bytes(const HostLayout &L) {
 
 int graph_fill_image(const HostLayout &L, char *image, const lbp_graph_desc *d) {
     GraphPieces gp(L, false);
-    char *at = image - gp.base;  // pieces are placed by device offset
+    // pieces are placed by device offset; the image starts at gp.base (every
+    // piece written here lies at or above it)
+    auto at = [&](size_t off) { return image + (off - gp.base); };
     for (const Piece &p : gp.p)
-        if (p.src && p.bytes) std::memcpy(at + p.off, p.src, p.bytes);
-    pack_lists(gp.ll, at + gp.p[gp.items].off);
+        if (p.src && p.bytes) std::memcpy(at(p.off), p.src, p.bytes);
+    pack_lists(gp.ll, at(gp.p[gp.items].off));
     if (!gp.raw) return LBP_OK;
     // the evidence as given (graph_create scatters it into its panel)
     if (!d) return set_error(LBP_E_INVALID, "graph image: the layout has no panels and no description was given");
-    float *ev = (float *)(at + gp.p[gp.rev].off);
+    float *ev = (float *)at(gp.p[gp.rev].off);
     if (d->evidence) std::memcpy(ev, d->evidence, sizeof(float) * L.VS);
     else std::memset(ev, 0, sizeof(float) * L.VS);
     return LBP_OK;
