@@ -164,7 +164,11 @@ void lbp_ctx_destroy(lbp_ctx *ctx);
  * implementation": index arrays computed once, messages in flat arrays).
  * Host arrays are read before return and may be freed afterwards.  The
  * graph owns its device memory until lbp_graph_free.  Messages start at 0.
- * The upload is complete (stream synchronised) when the call returns. */
+ * The upload is complete (stream synchronised) when the call returns.  The
+ * library may lay the variables out in an order of its own (it renumbers the
+ * low-degree parents of logical factors with more than 8 edges); every array
+ * that crosses this interface (evidence, beliefs, MAP, messages, gradients,
+ * samples) stays in the description's order. */
 int lbp_graph_upload(lbp_ctx *ctx, const lbp_graph_desc *desc, lbp_graph **out);
 /* Frees a graph after waiting for its queued work. */
 void lbp_graph_free(lbp_graph *g);
